@@ -1,0 +1,173 @@
+"""Pins of the CPU cull re-implementation (Sec. 3.2, Eq. 3-5).
+
+The cull's job is to drop only (tile, Gaussian) pairs whose Gaussian is below
+tau at every query of the tile.  These tests check that safety property by
+brute force with the float64 oracle (Cauchy-Schwarz makes it exact: a pair
+outside a projected kappa-sigma interval has M > kappa^2), plus the
+structural facts of the tiling and special cases.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_20067_amd import inputs
+
+
+def _setup(n=4, k=64, q=2048, layout="cube", sdiag=(5, 50), soff=2.0, seed=1, near=0.5):
+    mix = inputs.gen_mixture(n, k, layout, sdiag, soff, seed=seed)
+    x = inputs.gen_queries(n, q - int(q * near), layout, seed=seed + 1)
+    if near:
+        xn = inputs.gen_near_queries([mix], int(q * near), seed=seed + 2)
+        x = np.concatenate([x, xn])
+    proj = inputs.gen_projections(n, 16, seed=seed + 3)
+    return mix, np.ascontiguousarray(x), proj
+
+
+def _tile_queries(c, t):
+    return c["perm"][t * c["tile"]:(t + 1) * c["tile"]]
+
+
+def _culled_pairs(c, k):
+    T = c["ntiles"]
+    out = []
+    for t in range(T):
+        keep = np.zeros(k, bool)
+        keep[c["cand"][c["tile_off"][t]:c["tile_off"][t + 1]]] = True
+        for s in np.nonzero(~keep)[0]:
+            out.append((t, c["gperm"][s]))
+    return out
+
+
+@pytest.mark.parametrize("cfg", [
+    dict(n=4, k=64, q=2048, layout="cube", sdiag=(5, 50), soff=2.0),
+    dict(n=6, k=96, q=1536, layout="pos3+dir3", sdiag=(10, 200), soff=5.0),
+    dict(n=10, k=96, q=1300, layout="pos3+nrm3+view3+rough1", sdiag=(10, 200), soff=5.0),
+])
+@pytest.mark.parametrize("tau", [1e-4, np.exp(-4.5)])
+def test_culled_pairs_are_below_tau_everywhere_in_tile(cfg, tau):
+    mix, x, proj = _setup(**cfg)
+    c = oracle.cull(mix["mean"], mix["factor"], x, proj, tau=tau)
+    culled = _culled_pairs(c, cfg["k"])
+    assert len(culled) > 0
+    qi, gi = [], []
+    for t, g in culled:
+        for p in _tile_queries(c, t):
+            qi.append(p)
+            gi.append(g)
+    M = oracle.msq_pairs(mix["mean"], mix["factor"], x, qi, gi)
+    kappa2 = -2 * np.log(tau)
+    # every culled pair sits outside the kappa-ellipsoid at every tile query
+    assert M.min() >= kappa2 * (1 - 1e-5), M.min()
+
+
+def test_kept_pairs_include_every_contributor():
+    """Pairs with G > tau at some query are always kept (the same fact seen
+    from the other side, checked over all pairs)."""
+    mix, x, proj = _setup(n=4, k=48, q=1024)
+    c = oracle.cull(mix["mean"], mix["factor"], x, proj, tau=1e-4)
+    qi = np.repeat(np.arange(x.shape[0]), 48)
+    gi = np.tile(np.arange(48), x.shape[0])
+    M = oracle.msq_pairs(mix["mean"], mix["factor"], x, qi, gi).reshape(-1, 48)
+    pos = np.empty(x.shape[0], np.int64)
+    pos[c["perm"]] = np.arange(x.shape[0])
+    tile_of = pos // c["tile"]
+    inv_g = np.empty(48, np.int64)
+    inv_g[c["gperm"]] = np.arange(48)
+    for p, g in zip(*np.nonzero(M < -2 * np.log(1e-4))):
+        t = tile_of[p]
+        assert inv_g[g] in c["cand"][c["tile_off"][t]:c["tile_off"][t + 1]]
+
+
+def test_culling_is_effective_with_locality_tiles():
+    """With locality-sorted tiles most pairs are culled; with kappa huge
+    nothing is."""
+    mix, x, proj = _setup(n=6, k=256, q=8192, layout="pos3+dir3", sdiag=(10, 200), soff=5.0)
+    c = oracle.cull(mix["mean"], mix["factor"], x, proj, tau=1e-4)
+    frac = c["total"] / (c["ntiles"] * 256)
+    assert frac < 0.5, frac
+    c_all = oracle.cull(mix["mean"], mix["factor"], x, proj, tau=1e-300)
+    big = oracle.cull(mix["mean"], mix["factor"] * np.float32(1e3), x, proj, tau=1e-4)
+    assert big["total"] == big["ntiles"] * 256
+    assert c_all["total"] >= c["total"]
+
+
+def test_tiling_structure():
+    mix, x, proj = _setup(n=6, k=100, q=3000, layout="pos3+dir3", sdiag=(10, 200), soff=5.0)
+    c = oracle.cull(mix["mean"], mix["factor"], x, proj)
+    q, k = x.shape[0], 100
+    assert c["ntiles"] == -(-q // 256)
+    np.testing.assert_array_equal(np.sort(c["perm"]), np.arange(q))
+    np.testing.assert_array_equal(np.sort(c["gperm"]), np.arange(k))
+    ks = c["qkey"][c["perm"]]
+    assert np.all(np.diff(ks.astype(np.int64)) >= 0)
+    same = np.diff(ks.astype(np.int64)) == 0
+    assert np.all(np.diff(c["perm"])[same] > 0)          # stable
+    gk = c["gkey"][c["gperm"]]
+    assert np.all(np.diff(gk.astype(np.int64)) >= 0)
+    # tile bounds contain their queries' projections (float64 recompute)
+    qr = x.astype(np.float64) @ proj.astype(np.float64).T
+    for t in range(c["ntiles"]):
+        sel = _tile_queries(c, t)
+        assert np.all(c["tile_lo"][t] <= qr[sel].min(0) + 1e-6)
+        assert np.all(c["tile_hi"][t] >= qr[sel].max(0) - 1e-6)
+        np.testing.assert_allclose(c["tile_lo"][t], qr[sel].min(0), atol=1e-5)
+    # candidate lists ascending, transposed lists consistent
+    for t in range(c["ntiles"]):
+        lst = c["cand"][c["tile_off"][t]:c["tile_off"][t + 1]]
+        assert np.all(np.diff(lst) > 0)
+    pairs_a = {(t, s) for t in range(c["ntiles"])
+               for s in c["cand"][c["tile_off"][t]:c["tile_off"][t + 1]]}
+    pairs_b = {(t, s) for s in range(k) for t in c["g_tiles"][c["g_off"][s]:c["g_off"][s + 1]]}
+    assert pairs_a == pairs_b
+    assert c["g_off"][-1] == c["total"]
+
+
+def test_mean_inside_tile_box_is_never_culled():
+    """A Gaussian centred on a query projects inside that query's tile
+    interval on every r, so dist = 0 and it is kept however narrow it is."""
+    mix, x, proj = _setup(n=10, k=40, q=1024, layout="pos3+nrm3+view3+rough1",
+                          sdiag=(10, 200), soff=5.0, near=0.0)
+    mix["mean"][:20] = x[::51][:20]
+    mix["factor"][:20] *= np.float32(1e-3)
+    c = oracle.cull(mix["mean"], mix["factor"], x, proj)
+    pos = np.empty(x.shape[0], np.int64)
+    pos[c["perm"]] = np.arange(x.shape[0])
+    inv_g = np.empty(40, np.int64)
+    inv_g[c["gperm"]] = np.arange(40)
+    for i in range(20):
+        t = pos[51 * i] // 256
+        assert inv_g[i] in c["cand"][c["tile_off"][t]:c["tile_off"][t + 1]]
+
+
+def test_power_of_two_scaling_of_projections_changes_nothing():
+    """Eq. 5 is invariant to the length of r; scaling r by 2 is exact in
+    floating point, so the lists are identical bit for bit."""
+    mix, x, proj = _setup(n=6, k=64, q=1024, layout="pos3+dir3", sdiag=(10, 200), soff=5.0)
+    a = oracle.cull(mix["mean"], mix["factor"], x, proj)
+    b = oracle.cull(mix["mean"], mix["factor"], x, proj * np.float32(2))
+    for key in ("perm", "gperm", "tile_off", "cand", "g_off", "g_tiles"):
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_single_query_tiles_are_pointwise_safe():
+    mix, x, proj = _setup(n=4, k=32, q=300)
+    c = oracle.cull(mix["mean"], mix["factor"], x, proj, tile=1)
+    assert c["ntiles"] == 300
+    qi, gi = [], []
+    for t, g in _culled_pairs(c, 32):
+        qi.append(c["perm"][t])
+        gi.append(g)
+    M = oracle.msq_pairs(mix["mean"], mix["factor"], x, qi, gi)
+    assert M.min() >= -2 * np.log(1e-4) * (1 - 1e-5)
+
+
+def test_ragged_and_empty():
+    mix, x, proj = _setup(n=4, k=16, q=300)
+    c = oracle.cull(mix["mean"], mix["factor"], x[:257], proj)
+    assert c["ntiles"] == 2
+    assert c["tile_off"].shape == (3,)
+    e = oracle.cull(mix["mean"], mix["factor"], x[:0], proj)
+    assert e["ntiles"] == 0 and e["total"] == 0
+    z = oracle.cull(mix["mean"][:0], mix["factor"][:0], x, proj)
+    assert z["total"] == 0 and z["ntiles"] == 2

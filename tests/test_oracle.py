@@ -1,0 +1,313 @@
+"""Pins of the float64 CPU oracle against what the paper and mathematics fix.
+
+Nothing here compares the oracle with a retyped copy of itself: the pins are
+hand-derived closed forms (tests/golden), exact identities (value at m + L u,
+integral of the unnormalised Gaussian), textbook special cases, brute force
+through an explicit inverse covariance, and central finite differences of
+the oracle's own forward sum for its gradient.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2405_20067_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "closed_forms.txt")
+
+
+def _parse_golden():
+    cases, cur = [], None
+    for raw in open(GOLDEN):
+        line = raw.split("#", 1)[0].strip()
+        if not line:
+            continue
+        head, _, rest = line.partition(" ")
+        if head in ("case", "mixture"):
+            cur = {"kind": head, "name": rest, "gaussians": []}
+        elif head == "end":
+            cases.append(cur)
+            cur = None
+        elif head == "cite":
+            cur["cite"] = rest
+        elif head == "gaussian":
+            parts = [np.array([float(v) for v in p.split()]) for p in rest.split("|")]
+            cur["gaussians"].append(parts)
+        else:
+            vals = np.array([float(v) for v in rest.split()])
+            cur[head] = vals
+    return cases
+
+
+CASES = _parse_golden()
+
+
+def test_golden_file_has_cases():
+    assert sum(c["kind"] == "case" for c in CASES) >= 6
+    assert all("cite" in c for c in CASES)
+
+
+@pytest.mark.parametrize("case", [c for c in CASES if c["kind"] == "case"],
+                         ids=lambda c: c["name"])
+def test_golden_single_gaussian(case):
+    n = int(case["n"][0])
+    val = oracle.gaussian(case["mean"], case["factor"], case["x"])
+    assert val == pytest.approx(math.exp(-case["msq"][0] / 2), rel=1e-14)
+    # the whole mixture entry point agrees (alpha = 1, colour = (1, 1, 1))
+    f = oracle.eval_mixture(case["mean"].reshape(1, n), case["factor"].reshape(1, -1),
+                            [1.0], [[1.0, 1.0, 1.0]], case["x"].reshape(1, n))
+    np.testing.assert_allclose(f[0], [math.exp(-case["msq"][0] / 2)] * 3, rtol=1e-14)
+    if "grad_mean_over_G" in case:
+        g0 = math.exp(-case["msq"][0] / 2)
+        gm, gl, ga, gc = oracle.grad(case["mean"].reshape(1, n),
+                                     case["factor"].reshape(1, -1), [1.0],
+                                     [[1.0, 0.0, 0.0]], case["x"].reshape(1, n),
+                                     [[1.0, 0.0, 0.0]])
+        np.testing.assert_allclose(gm[0], case["grad_mean_over_G"] * g0, rtol=1e-13)
+        np.testing.assert_allclose(gl[0], case["grad_factor_over_G"] * g0, rtol=1e-13)
+        assert ga[0] == pytest.approx(g0, rel=1e-14)
+        np.testing.assert_allclose(gc[0], [g0, 0.0, 0.0], rtol=1e-14)
+
+
+def test_golden_mixture():
+    (case,) = [c for c in CASES if c["kind"] == "mixture"]
+    n = int(case["n"][0])
+    fac = np.array([g[0] for g in case["gaussians"]])
+    mean = np.array([g[1] for g in case["gaussians"]])
+    alpha = np.array([g[2][0] for g in case["gaussians"]])
+    col = np.array([g[3] for g in case["gaussians"]])
+    f = oracle.eval_mixture(mean, fac, alpha, col, case["x"].reshape(1, n))[0]
+    want = case["coef_exp_-2.5"] * math.exp(-2.5) + case["coef_exp_-0.5"] * math.exp(-0.5)
+    np.testing.assert_allclose(f, want, rtol=1e-14)
+
+
+def _random_factor(rng, n, dyadic=True):
+    """Lower-triangular factor with nonzero diagonal of either sign; with
+    dyadic=True all entries are multiples of 1/8 (exact in float32)."""
+    L = np.zeros((n, n))
+    for i in range(n):
+        for j in range(i):
+            L[i, j] = rng.integers(-16, 17) / 8
+        L[i, i] = rng.choice([-1, 1]) * rng.integers(2, 17) / 8
+    if not dyadic:
+        L = L + np.tril(rng.standard_normal((n, n)) * 0.01, -1)
+    return L
+
+
+def _pack(L):
+    r, c = np.tril_indices(L.shape[0])
+    return L[r, c]
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 6, 10])
+def test_value_at_m_plus_Lu(n):
+    """x = m + L u gives G = exp(-|u|^2/2) exactly, because L^-1 (L u) = u
+    (Eq. 1-2).  Entries are dyadic so x is exact in float32."""
+    rng = np.random.default_rng(100 + n)
+    for _ in range(20):
+        L = _random_factor(rng, n)
+        m = rng.integers(-8, 9, size=n) / 4
+        u = rng.integers(-6, 7, size=n) / 4
+        x = m + L @ u
+        assert np.all(x.astype(np.float32) == x)
+        alpha, col = 0.75, np.array([0.25, 0.5, 1.0])
+        f = oracle.eval_mixture(m.reshape(1, n), _pack(L).reshape(1, -1), [alpha],
+                                col.reshape(1, 3), x.reshape(1, n))[0]
+        np.testing.assert_allclose(f, alpha * col * math.exp(-0.5 * u @ u), rtol=1e-13,
+                                   atol=0)
+
+
+@pytest.mark.parametrize("n", [2, 3])
+def test_integral_equals_sqrt_det(n):
+    """The unnormalised Gaussian of Eq. 1 integrates to
+    (2 pi)^{N/2} |det V|^{1/2} = (2 pi)^{N/2} prod |L_ii|.  Trapezoid rule on a
+    dyadic grid (spectrally accurate for this integrand)."""
+    rng = np.random.default_rng(7 + n)
+    L = _random_factor(rng, n) / 4
+    V = L @ L.T
+    sd = np.sqrt(np.diag(V))
+    h = 1.0 / 64 if n == 2 else 1.0 / 32
+    axes = []
+    for a in range(n):
+        half = math.ceil(11 * sd[a] / h) * h
+        axes.append(np.arange(-half, half + h / 2, h))
+    grid = np.stack(np.meshgrid(*axes, indexing="ij"), -1).reshape(-1, n)
+    f = oracle.eval_mixture(np.zeros((1, n)), _pack(L).reshape(1, -1), [1.0],
+                            [[1.0, 0.0, 0.0]], grid)[:, 0]
+    integral = f.sum() * h ** n
+    want = (2 * math.pi) ** (n / 2) * np.prod(np.abs(np.diag(L)))
+    assert integral == pytest.approx(want, rel=1e-9)
+
+
+def test_special_cases_1d_and_isotropic():
+    rng = np.random.default_rng(5)
+    # N = 1: exp(-(x-m)^2 / (2 L^2))
+    for _ in range(10):
+        l, m, x = rng.uniform(0.1, 2), rng.uniform(-1, 1), rng.uniform(-3, 3)
+        assert oracle.gaussian([m], [l], [x]) == pytest.approx(
+            math.exp(-(x - m) ** 2 / (2 * l * l)), rel=1e-13)
+    # isotropic L = s I: exp(-|x-m|^2 / (2 s^2))
+    for n in (3, 5, 10):
+        s = rng.uniform(0.1, 1)
+        m, x = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+        got = oracle.gaussian(m, _pack(s * np.eye(n)), x)
+        assert got == pytest.approx(math.exp(-np.sum((x - m) ** 2) / (2 * s * s)),
+                                    rel=1e-12)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4])
+def test_brute_force_explicit_inverse(n):
+    """Tiny mixtures against exp(-1/2 d^T inv(L L^T) d) summed by numpy."""
+    rng = np.random.default_rng(n)
+    k, q = 8, 40
+    Ls = [_random_factor(rng, n, dyadic=False) for _ in range(k)]
+    mean = rng.uniform(-1, 1, (k, n))
+    alpha = rng.uniform(0.1, 1, k)
+    col = rng.uniform(0, 1, (k, 3))
+    x = rng.uniform(-2, 2, (q, n))
+    f = oracle.eval_mixture(mean, np.array([_pack(L) for L in Ls]), alpha, col, x)
+    want = np.zeros((q, 3))
+    for i in range(k):
+        Vinv = np.linalg.inv(Ls[i] @ Ls[i].T)
+        d = x - mean[i]
+        g = np.exp(-0.5 * np.einsum("qa,ab,qb->q", d, Vinv, d))
+        want += g[:, None] * alpha[i] * col[i]
+    np.testing.assert_allclose(f, want, rtol=1e-11, atol=1e-300)
+
+
+def test_symmetries_permutation_and_linearity():
+    w = inputs.WORKLOADS["4d-dense"]
+    mix = inputs.workload_mixture(w, k=32)
+    x = inputs.gen_queries(4, 64, "cube", seed=9)
+    f = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x)
+    perm = np.random.default_rng(1).permutation(32)
+    fp = oracle.eval_mixture(mix["mean"][perm], mix["factor"][perm], mix["weight"][perm],
+                             mix["colour"][perm], x)
+    np.testing.assert_allclose(fp, f, rtol=1e-13, atol=1e-300)
+    f2 = oracle.eval_mixture(mix["mean"], mix["factor"], 2 * mix["weight"].astype(np.float64),
+                             mix["colour"], x)
+    np.testing.assert_allclose(f2, 2 * f, rtol=1e-14, atol=0)
+
+
+def test_spd_from_any_factor():
+    """Sec. 3.1: V = L L^T is symmetric positive definite for any L with a
+    nonzero diagonal, and its Cholesky factor is L up to the signs of the
+    columns (P:295's uniqueness up to unitary transforms)."""
+    rng = np.random.default_rng(11)
+    mix = inputs.gen_mixture(10, 64, "pos3+nrm3+view3+rough1", (10, 200), 5.0, seed=5)
+    r, c = np.tril_indices(10)
+    for row in mix["factor"][:16]:
+        L = np.zeros((10, 10))
+        L[r, c] = row
+        V = L @ L.T
+        np.testing.assert_allclose(V, V.T, rtol=0, atol=0)
+        assert np.linalg.eigvalsh(V).min() > 0
+        C = np.linalg.cholesky(V)
+        np.testing.assert_allclose(C, L * np.sign(np.diag(L))[None, :], rtol=1e-6,
+                                   atol=1e-9 * np.abs(L).max())
+    for _ in range(8):
+        L = _random_factor(rng, 5, dyadic=False)
+        V = L @ L.T
+        assert np.linalg.eigvalsh(V).min() > 0
+
+
+def _loss(mean, fac, alpha, col, x, g):
+    return float(np.sum(oracle.eval_mixture(mean, fac, alpha, col, x) * g))
+
+
+@pytest.mark.parametrize("n", [2, 3, 5])
+def test_gradient_central_differences(n):
+    """The analytic gradient against central differences of the oracle's
+    forward sum, l = sum_q g(q) . f(q), for every parameter entry."""
+    rng = np.random.default_rng(40 + n)
+    k, q = 3, 25
+    Ls = [_random_factor(rng, n, dyadic=False) * 0.5 for _ in range(k)]
+    fac = np.array([_pack(L) for L in Ls])
+    mean = rng.uniform(-0.5, 0.5, (k, n))
+    alpha = rng.uniform(0.2, 1, k)
+    col = rng.uniform(0, 1, (k, 3))
+    # queries near the components so every parameter matters
+    x = np.concatenate([mean[i] + (Ls[i] @ rng.standard_normal((n, q // k + 1))).T
+                        for i in range(k)])[:q]
+    g = rng.standard_normal((q, 3))
+    gm, gl, ga, gc = oracle.grad(mean, fac, alpha, col, x, g)
+    for name, arr, ana in (("mean", mean, gm), ("factor", fac, gl), ("alpha", alpha, ga),
+                           ("colour", col, gc)):
+        num = np.zeros_like(arr)
+        for idx in np.ndindex(arr.shape):
+            h = 6e-6 * max(abs(arr[idx]), 1e-3)
+            args = {"mean": mean, "factor": fac, "alpha": alpha, "colour": col}
+            up = {kk: v.copy() for kk, v in args.items()}
+            dn = {kk: v.copy() for kk, v in args.items()}
+            up[name][idx] += h
+            dn[name][idx] -= h
+            lp = _loss(up["mean"], up["factor"], up["alpha"], up["colour"], x, g)
+            lm = _loss(dn["mean"], dn["factor"], dn["alpha"], dn["colour"], x, g)
+            num[idx] = (lp - lm) / (2 * h)
+        scale = np.abs(num).max()
+        np.testing.assert_allclose(ana, num, rtol=0, atol=2e-7 * scale + 1e-12,
+                                   err_msg=name)
+
+
+def test_gradient_closed_forms_isotropic():
+    """L = s I: dG/dm = G d / s^2 and sum_i dG/dL_ii = G |d|^2 / s^3."""
+    rng = np.random.default_rng(3)
+    n, s = 4, 0.7
+    m, x = rng.uniform(-1, 1, n), rng.uniform(-1, 1, n)
+    d = x - m
+    G = math.exp(-d @ d / (2 * s * s))
+    gm, gl, ga, gc = oracle.grad(m.reshape(1, n), _pack(s * np.eye(n)).reshape(1, -1),
+                                 [1.0], [[1.0, 0.0, 0.0]], x.reshape(1, n), [[1.0, 0.0, 0.0]])
+    np.testing.assert_allclose(gm[0], G * d / s ** 2, rtol=1e-13)
+    diag = [i * (i + 1) // 2 + i for i in range(n)]
+    assert gl[0][diag].sum() == pytest.approx(G * (d @ d) / s ** 3, rel=1e-13)
+    # at the mean the mean-gradient vanishes
+    gm0, *_ = oracle.grad(m.reshape(1, n), _pack(s * np.eye(n)).reshape(1, -1), [1.0],
+                          [[1.0, 0.0, 0.0]], m.reshape(1, n), [[1.0, 0.0, 0.0]])
+    np.testing.assert_allclose(gm0[0], 0.0, atol=0)
+
+
+def test_restricted_sums_match_full_when_lists_are_complete():
+    """eval_lists / grad_lists with every pair listed equal the full sums."""
+    mix = inputs.gen_mixture(3, 10, "cube", (2, 5), 1.0, seed=4)
+    x = inputs.gen_queries(3, 30, "cube", seed=5)
+    full = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x)
+    qoff = np.arange(31) * 10
+    gidx = np.tile(np.arange(10), 30)
+    lists = oracle.eval_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x,
+                              qoff, gidx)
+    np.testing.assert_array_equal(lists, full)
+    g = inputs.gen_grad_out(30, seed=2)
+    a = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g)
+    sel = np.arange(10)
+    b = oracle.grad_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g,
+                          sel, np.arange(11) * 30, np.tile(np.arange(30), 10))
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+    # sampled Gaussians: same values as the full call
+    part = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g,
+                       sel=[7, 2])
+    for u, v in zip(a, part):
+        np.testing.assert_array_equal(u[[7, 2]], v)
+
+
+def test_msq_pairs_cauchy_schwarz():
+    """(r . d)^2 <= sigma_r^2 M with sigma_r^2 = |L^T r|^2 (Eq. 3-4): the fact
+    that makes the projection cull safe."""
+    rng = np.random.default_rng(8)
+    mix = inputs.gen_mixture(6, 50, "pos3+dir3", (10, 200), 5.0, seed=8)
+    x = inputs.gen_queries(6, 50, "pos3+dir3", seed=9)
+    qi, gi = np.arange(50), rng.integers(0, 50, 50)
+    M = oracle.msq_pairs(mix["mean"], mix["factor"], x, qi, gi)
+    r, c = np.tril_indices(6)
+    for _ in range(5):
+        rv = rng.standard_normal(6)
+        for e in range(50):
+            L = np.zeros((6, 6))
+            L[r, c] = mix["factor"][gi[e]]
+            d = x[qi[e]].astype(np.float64) - mix["mean"][gi[e]]
+            s2 = np.sum((L.T @ rv) ** 2)
+            assert (rv @ d) ** 2 <= s2 * M[e] * (1 + 1e-12)
