@@ -1,0 +1,204 @@
+/*
+ * libngd -- evaluation and differentiation of N-dimensional Gaussian
+ * mixtures with random-projection tile culling, on AMD Instinct MI355X
+ * (gfx950).
+ *
+ * The method is that of Diolatzis et al., "N-Dimensional Gaussians for
+ * Fitting of High Dimensional Functions" (SIGGRAPH 2024):
+ *   Sec. 3.1, Eq. 1   G(x - m) = exp(-1/2 (x-m)^T V^-1 (x-m))   (unnormalised)
+ *   Sec. 3.1, Eq. 2   V = L L^T, L lower triangular, optimised directly
+ *   Sec. 4.1, Eq. 8   f(x) = sum_i G_i(x - m_i) alpha_i c_i     (RGB)
+ *   Sec. 3.2, Eq. 3-5 cull Gaussian i for a tile of queries when, on some
+ *                     random unit vector r, the tile's projected extent lies
+ *                     outside [m_r - kappa sigma_r, m_r + kappa sigma_r],
+ *                     sigma_r^2 = r^T V r
+ *   Sec. 4.1          gradients of all parameters computed analytically
+ *
+ * Conventions for every call:
+ *   - Returns NGD_OK (0) or a negative NGD_E_* code; ngd_last_error() gives a
+ *     message for the calling thread.  No C++ exception crosses this ABI.
+ *   - Array arguments named "device" are device pointers (hipMalloc'ed or
+ *     from a framework allocator); "host" arguments are host pointers.  All
+ *     device arrays are float32 (or the integer type shown), C-contiguous,
+ *     4-byte aligned, and owned by the caller.
+ *   - `stream` is a hipStream_t passed as void* (NULL: the null stream).  All
+ *     device work is enqueued on it; the caller keeps its buffers alive until
+ *     that work has finished.  Calls documented as "synchronises" wait for
+ *     the stream before returning.
+ *   - Outputs are overwritten, never accumulated into.
+ *   - Handles are not thread-safe; one handle, one thread at a time.
+ *   - Arguments are validated on the host before any device work; an invalid
+ *     call changes nothing.
+ */
+#ifndef NGD_H
+#define NGD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NGD_OK 0
+#define NGD_E_INVAL (-1)    /* NULL pointer, size out of range, bad parameter */
+#define NGD_E_SINGULAR (-2) /* a factor has a zero or non-finite diagonal entry,
+                               or a parameter is not finite (ngd_mixture_validate) */
+#define NGD_E_HIP (-3)      /* HIP runtime error; message holds HIP's string */
+#define NGD_E_NOMEM (-4)    /* device or host allocation failed */
+#define NGD_E_STALE (-5)    /* cull built for another mixture version, another
+                               query buffer or another query count */
+
+#define NGD_MAX_N 12        /* dimensions supported: 1 .. NGD_MAX_N */
+#define NGD_MAX_PROJ 32     /* projection vectors: 1 .. NGD_MAX_PROJ */
+
+/* Arithmetic of ngd_eval / ngd_eval_backward. */
+#define NGD_FP32 0          /* float32 direct evaluation */
+
+typedef struct ngd_mixture ngd_mixture;
+typedef struct ngd_cull ngd_cull;
+
+/* Parameters of the tile cull (Sec. 3.2). */
+typedef struct {
+    int n_proj;     /* number of random projection vectors, 1..NGD_MAX_PROJ (16) */
+    float tau;      /* value threshold in (0, 1): a culled (tile, Gaussian) pair
+                       has G <= tau at every query of the tile.  The interval
+                       half-width is kappa sigma_r with kappa^2 = 2 ln(1/tau)
+                       (tau = exp(-4.5) gives the paper's 3 sigma). (1e-4) */
+    int tile;       /* queries per tile: 256 (the paper's 16 x 16 pixel tile) */
+    int key_proj;   /* projections in the query locality key, 0..n_proj (16) */
+    int key_bits;   /* bits per key projection; key_proj*key_bits <= 32 (2) */
+} ngd_cull_params;
+
+/* Message for the last failing call on this thread ("" if none). */
+const char *ngd_last_error(void);
+
+/* Library version: major*10000 + minor*100 + patch. */
+int ngd_version(void);
+
+/* Default cull parameters (values in parentheses above).  `p` host. */
+int ngd_cull_params_default(ngd_cull_params *p);
+
+/* Replaces the device allocator used for library-owned workspaces (default
+ * hipMalloc / hipFree).  alloc(bytes, ctx) returns a device pointer or NULL;
+ * free(ptr, ctx) releases it.  Both NULL restores the default.  Affects
+ * allocations made after the call; memory is always released with the
+ * allocator that made it. */
+int ngd_set_allocator(void *(*alloc_fn)(size_t bytes, void *ctx),
+                      void (*free_fn)(void *ptr, void *ctx), void *ctx);
+
+/* ---- mixture --------------------------------------------------------- */
+
+/* Creates a mixture of k Gaussians in n dimensions (1 <= n <= NGD_MAX_N,
+ * 0 <= k < 2^31) and allocates its derived-data workspace on the current
+ * device.  *out receives the handle. */
+int ngd_mixture_create(int n, int64_t k, ngd_mixture **out);
+
+/* Loads parameters (Sec. 3.1, Eq. 2; Sec. 4.1) and derives, in float64 on
+ * the device, S = L^-1 for every Gaussian (the precision factor,
+ * V^-1 = S^T S) plus the per-Gaussian records the kernels read.  Inputs are
+ * activated values:
+ *   mean   device, k x n
+ *   factor device, k x n(n+1)/2: L packed lower triangle by rows,
+ *          element (i, j), j <= i, at i(i+1)/2 + j; any nonzero diagonal
+ *   weight device, k       (alpha: brightness, or opacity)
+ *   colour device, k x 3   (c: RGB)
+ * Copies what it needs; the inputs may be freed once the stream reaches
+ * this point.  Bumps the mixture version (culls built before go stale).
+ * A zero or non-finite diagonal entry sets a device flag that
+ * ngd_mixture_validate reports; this call itself does not synchronise. */
+int ngd_mixture_update(ngd_mixture *mix, const float *mean, const float *factor,
+                       const float *weight, const float *colour, void *stream);
+
+/* Synchronises; NGD_E_SINGULAR if the last update saw a zero or non-finite
+ * factor diagonal or a non-finite parameter. */
+int ngd_mixture_validate(const ngd_mixture *mix, void *stream);
+
+/* Number of dimensions / Gaussians / current version. */
+int ngd_mixture_info(const ngd_mixture *mix, int *n, int64_t *k, int64_t *version);
+
+/* Frees the handle (NULL is a no-op).  Synchronises the device. */
+int ngd_mixture_destroy(ngd_mixture *mix);
+
+/* ---- cull ------------------------------------------------------------ */
+
+/* Builds (or, when *inout is non-NULL, rebuilds in place, reusing its
+ * memory) the cull structure for `queries` against the mixture's current
+ * version (Sec. 3.2, Eq. 3-5):
+ *   queries device, q x n (the buffer later passed to ngd_eval)
+ *   proj    host, p->n_proj x n: the random projection vectors r_j (any
+ *           length; Eq. 5 does not depend on it).  Copied.
+ * Steps on the device: query and mean projections (Eq. 3), projected
+ * variances in float64 (Eq. 4), locality keys and stable radix sorts of
+ * queries and Gaussians, tiles of p->tile consecutive sorted queries with
+ * their projected bounds, the (tile, Gaussian) interval test (Eq. 5), the
+ * per-tile candidate lists (CSR, ascending) and their transpose.
+ * Synchronises once, to read the number of candidates.  q = 0 or k = 0
+ * gives an empty structure. */
+int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
+                   const ngd_cull_params *p, const float *proj, void *stream,
+                   ngd_cull **inout);
+
+/* Sizes of a built cull (host outputs, any may be NULL): total candidates,
+ * the longest tile list, and the number of tiles. */
+int ngd_cull_stats(const ngd_cull *cull, int64_t *total, int64_t *max_per_tile,
+                   int64_t *ntiles);
+
+/* Copies the cull to host arrays (any may be NULL; synchronises):
+ *   perm     q        sorted query position -> caller's query index
+ *   gperm    k        sorted Gaussian position -> caller's Gaussian index
+ *   tile_off ntiles+1 offsets into cand (int64)
+ *   cand     total    candidates per tile, as sorted Gaussian positions,
+ *                     ascending within a tile
+ *   g_off    k+1      offsets into g_tiles, by sorted Gaussian position
+ *   g_tiles  total    tiles of each sorted Gaussian, ascending
+ *   tile_lo, tile_hi  ntiles x n_proj projected bounds of each tile */
+int ngd_cull_export(const ngd_cull *cull, int32_t *perm, int32_t *gperm,
+                    int64_t *tile_off, int32_t *cand, int64_t *g_off, int32_t *g_tiles,
+                    float *tile_lo, float *tile_hi);
+
+/* Frees the handle (NULL is a no-op).  Synchronises the device. */
+int ngd_cull_destroy(ngd_cull *cull);
+
+/* ---- evaluation -------------------------------------------------------- */
+
+/* Mixture colour f(x) = sum_i G_i(x - m_i) alpha_i c_i (Sec. 4.1, Eq. 8).
+ *   cull     NULL: dense direct sum over all Gaussians, no culling.
+ *            Otherwise a cull built for this mixture version, this
+ *            `queries` pointer and this q (NGD_E_STALE if not): the sum over
+ *            each tile's candidates, where pairs whose Gaussian value is
+ *            certified below tau * 2^-20 are skipped without evaluation.
+ *   queries  device, q x n
+ *   out      device, q x 3, in the caller's query order
+ * Does not synchronise. */
+int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
+             int64_t q, int precision, float *out, void *stream);
+
+/* Gradients of a loss l given grad_out = dl/df (device, q x 3), with respect
+ * to every Gaussian's mean, factor, weight and colour (the analytic
+ * gradients of Sec. 4.1; no query gradient):
+ *   dl/dalpha_i = sum_x G_i s,  dl/dc_i = alpha_i sum_x G_i g,
+ *   dl/dm_i = sum_x w z,        dl/dL_i = tril(sum_x w z y^T),
+ * with g = grad_out(x), s = g . c_i, w = alpha_i G_i s, y = L_i^-1 (x - m_i),
+ * z = L_i^-T y.  With a cull the sums run over the same pairs as ngd_eval's.
+ * Outputs (device, overwritten, caller's Gaussian order): g_mean k x n,
+ * g_factor k x n(n+1)/2 (packed like the factor), g_weight k, g_colour k x 3.
+ * Each Gaussian's sums are formed by one wave in a fixed order: no atomics,
+ * bitwise reproducible.  `cull` may be NULL (dense).  Does not synchronise. */
+int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull,
+                      const float *queries, int64_t q, const float *grad_out,
+                      int precision, float *g_mean, float *g_factor, float *g_weight,
+                      float *g_colour, void *stream);
+
+/* Mean squared error and its gradient, the loss of the 10-D fitting
+ * workload (Sec. 4.1 fits colours with an L2-type loss):
+ *   loss = 1/(3q) sum (f - target)^2,  grad = 2 (f - target) / (3q)
+ * f, target, grad device q x 3; loss device, one float.  Deterministic
+ * two-level reduction.  Does not synchronise. */
+int ngd_l2_loss(const float *f, const float *target, int64_t q, float *loss,
+                float *grad, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NGD_H */

@@ -1,0 +1,460 @@
+// C-ABI of libngd: argument validation, handles, workspaces and error
+// reporting around the kernels.  Every check runs on the host before any
+// device work, so an invalid call has no effect.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <string>
+
+#include "ngd_internal.hpp"
+
+namespace ngd {
+namespace {
+
+thread_local std::string g_err;
+
+struct Allocator {
+    void *(*alloc_fn)(size_t, void *) = nullptr;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+std::mutex g_alloc_mu;
+Allocator g_alloc;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *where)
+{
+    return fail(NGD_E_HIP, "%s: %s", where, hipGetErrorString(e));
+}
+
+inline hipStream_t S(void *stream) { return static_cast<hipStream_t>(stream); }
+
+bool aligned4(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+}  // namespace
+
+void *dev_alloc(size_t bytes, void (**free_fn)(void *, void *), void **ctx)
+{
+    Allocator a;
+    {
+        std::lock_guard<std::mutex> lk(g_alloc_mu);
+        a = g_alloc;
+    }
+    *free_fn = a.free_fn;
+    *ctx = a.ctx;
+    if (a.alloc_fn) return a.alloc_fn(bytes, a.ctx);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+
+bool DevBuf::ensure(size_t bytes)
+{
+    if (bytes == 0) bytes = 4;
+    if (bytes <= cap) return true;
+    release();
+    // grow with headroom so repeated rebuilds settle quickly
+    const size_t want = bytes + bytes / 8;
+    p = dev_alloc(want, &free_fn, &ctx);
+    if (!p) return false;
+    cap = want;
+    return true;
+}
+
+void DevBuf::release()
+{
+    if (p) {
+        if (free_fn)
+            free_fn(p, ctx);
+        else
+            (void)hipFree(p);
+    }
+    p = nullptr;
+    cap = 0;
+    free_fn = nullptr;
+    ctx = nullptr;
+}
+
+}  // namespace ngd
+
+using namespace ngd;
+
+extern "C" {
+
+const char *ngd_last_error(void) { return g_err.c_str(); }
+
+int ngd_version(void) { return 1 * 10000 + 0 * 100 + 0; }
+
+int ngd_cull_params_default(ngd_cull_params *p)
+{
+    if (!p) return fail(NGD_E_INVAL, "ngd_cull_params_default: p is NULL");
+    p->n_proj = 16;
+    p->tau = 1e-4f;
+    p->tile = 256;
+    p->key_proj = 16;
+    p->key_bits = 2;
+    return NGD_OK;
+}
+
+int ngd_set_allocator(void *(*alloc_fn)(size_t, void *), void (*free_fn)(void *, void *),
+                      void *ctx)
+{
+    if ((alloc_fn == nullptr) != (free_fn == nullptr))
+        return fail(NGD_E_INVAL, "ngd_set_allocator: give both functions or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc_fn = alloc_fn;
+    g_alloc.free_fn = free_fn;
+    g_alloc.ctx = alloc_fn ? ctx : nullptr;
+    return NGD_OK;
+}
+
+int ngd_mixture_create(int n, int64_t k, ngd_mixture **out)
+{
+    if (!out) return fail(NGD_E_INVAL, "ngd_mixture_create: out is NULL");
+    *out = nullptr;
+    if (n < 1 || n > NGD_MAX_N)
+        return fail(NGD_E_INVAL, "ngd_mixture_create: n=%d outside [1, %d]", n, NGD_MAX_N);
+    if (k < 0 || k >= (int64_t(1) << 31))
+        return fail(NGD_E_INVAL, "ngd_mixture_create: k=%lld outside [0, 2^31)", (long long)k);
+    ngd_mixture *m = new (std::nothrow) ngd_mixture();
+    if (!m) return fail(NGD_E_NOMEM, "ngd_mixture_create: host allocation failed");
+    m->n = n;
+    m->k = k;
+    const size_t kk = size_t(k > 0 ? k : 1);
+    if (!m->rec.ensure(sizeof(float) * kk * rec_stride(n)) ||
+        !m->lfac.ensure(sizeof(float) * kk * tri(n)) || !m->flag.ensure(sizeof(int))) {
+        m->rec.release();
+        m->lfac.release();
+        m->flag.release();
+        delete m;
+        return fail(NGD_E_NOMEM, "ngd_mixture_create: device allocation of %zu bytes failed",
+                    sizeof(float) * kk * (rec_stride(n) + tri(n)));
+    }
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) m->device = dev;
+    (void)hipGetLastError();
+    *out = m;
+    return NGD_OK;
+}
+
+int ngd_mixture_update(ngd_mixture *mix, const float *mean, const float *factor,
+                       const float *weight, const float *colour, void *stream)
+{
+    if (!mix) return fail(NGD_E_INVAL, "ngd_mixture_update: mixture is NULL");
+    if (mix->k > 0 && (!mean || !factor || !weight || !colour))
+        return fail(NGD_E_INVAL, "ngd_mixture_update: NULL parameter array");
+    if (!aligned4(mean) || !aligned4(factor) || !aligned4(weight) || !aligned4(colour))
+        return fail(NGD_E_INVAL, "ngd_mixture_update: arrays must be 4-byte aligned");
+    hipError_t e = launch_prepare(mix->n, mix->k, mean, factor, weight, colour,
+                                  mix->rec.as<float>(), mix->lfac.as<float>(),
+                                  mix->flag.as<int>(), S(stream));
+    if (e != hipSuccess) return hip_fail(e, "ngd_mixture_update");
+    ++mix->version;
+    return NGD_OK;
+}
+
+int ngd_mixture_validate(const ngd_mixture *mix, void *stream)
+{
+    if (!mix) return fail(NGD_E_INVAL, "ngd_mixture_validate: mixture is NULL");
+    int flag = 0;
+    hipError_t e = hipMemcpyAsync(&flag, mix->flag.p, sizeof(int), hipMemcpyDeviceToHost,
+                                  S(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+    if (e != hipSuccess) return hip_fail(e, "ngd_mixture_validate");
+    if (flag)
+        return fail(NGD_E_SINGULAR,
+                    "ngd_mixture_validate: a factor has a zero or non-finite diagonal entry, "
+                    "or a parameter is not finite");
+    return NGD_OK;
+}
+
+int ngd_mixture_info(const ngd_mixture *mix, int *n, int64_t *k, int64_t *version)
+{
+    if (!mix) return fail(NGD_E_INVAL, "ngd_mixture_info: mixture is NULL");
+    if (n) *n = mix->n;
+    if (k) *k = mix->k;
+    if (version) *version = mix->version;
+    return NGD_OK;
+}
+
+int ngd_mixture_destroy(ngd_mixture *mix)
+{
+    if (!mix) return NGD_OK;
+    (void)hipDeviceSynchronize();
+    mix->rec.release();
+    mix->lfac.release();
+    mix->flag.release();
+    delete mix;
+    return NGD_OK;
+}
+
+static void cull_release(ngd_cull *c)
+{
+    DevBuf *bufs[] = {&c->proj,    &c->qr,       &c->range_part, &c->qrange,  &c->g_mr,
+                      &c->g_thr,   &c->keys0,    &c->keys1,      &c->vals0,   &c->vals1,
+                      &c->radix_hist, &c->radix_off, &c->perm,   &c->gperm,   &c->qs,
+                      &c->gs,      &c->tile_lo,  &c->tile_hi,    &c->grec,    &c->g_mr_s,
+                      &c->g_thr_s, &c->masks,    &c->seg_cnt,    &c->tile_cnt, &c->tile_off,
+                      &c->cand,    &c->g_cnt,    &c->g_off,      &c->g_tiles, &c->scan_tmp,
+                      &c->stats};
+    for (DevBuf *b : bufs) b->release();
+    if (c->stats_host) (void)hipHostFree(c->stats_host);
+    c->stats_host = nullptr;
+}
+
+int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
+                   const ngd_cull_params *p, const float *proj, void *stream,
+                   ngd_cull **inout)
+{
+    if (!mix || !p || !proj || !inout)
+        return fail(NGD_E_INVAL, "ngd_cull_build: NULL argument");
+    if (q < 0 || q >= (int64_t(1) << 31))
+        return fail(NGD_E_INVAL, "ngd_cull_build: q=%lld outside [0, 2^31)", (long long)q);
+    if (q > 0 && !queries) return fail(NGD_E_INVAL, "ngd_cull_build: queries is NULL");
+    if (!aligned4(queries)) return fail(NGD_E_INVAL, "ngd_cull_build: queries not aligned");
+    if (p->n_proj < 1 || p->n_proj > NGD_MAX_PROJ)
+        return fail(NGD_E_INVAL, "ngd_cull_build: n_proj=%d outside [1, %d]", p->n_proj,
+                    NGD_MAX_PROJ);
+    if (!(p->tau > 0.0f && p->tau < 1.0f))
+        return fail(NGD_E_INVAL, "ngd_cull_build: tau must lie in (0, 1)");
+    if (p->tile < 1 || p->tile > 1024)
+        return fail(NGD_E_INVAL, "ngd_cull_build: tile=%d outside [1, 1024]", p->tile);
+    if (p->key_proj < 0 || p->key_proj > p->n_proj || p->key_bits < 0 ||
+        p->key_proj * p->key_bits > 32 || (p->key_proj > 0 && p->key_bits > 16))
+        return fail(NGD_E_INVAL, "ngd_cull_build: key_proj=%d key_bits=%d invalid", p->key_proj,
+                    p->key_bits);
+    for (int i = 0; i < p->n_proj * mix->n; ++i)
+        if (!std::isfinite(proj[i]))
+            return fail(NGD_E_INVAL, "ngd_cull_build: projection vectors must be finite");
+
+    ngd_cull *c = *inout;
+    const bool fresh = (c == nullptr);
+    if (fresh) {
+        c = new (std::nothrow) ngd_cull();
+        if (!c) return fail(NGD_E_NOMEM, "ngd_cull_build: host allocation failed");
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->stats_host), 2 * sizeof(int64_t),
+                          hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            delete c;
+            return fail(NGD_E_NOMEM, "ngd_cull_build: pinned host allocation failed");
+        }
+    }
+    auto bail = [&](int code) {
+        if (fresh) {
+            cull_release(c);
+            delete c;
+        } else {
+            c->mix = nullptr;   // leave the handle unusable rather than half-built
+            c->mix_version = -1;
+        }
+        return code;
+    };
+    c->mix = mix;
+    c->mix_version = mix->version;
+    c->queries = queries;
+    c->q = q;
+    c->n = mix->n;
+    c->k = mix->k;
+    c->params = *p;
+    c->kappa2 = float(-2.0 * std::log(double(p->tau)));
+    c->ntiles = (q + p->tile - 1) / p->tile;
+    c->tpad = (c->ntiles + 63) / 64 * 64;
+    c->nchunks = (mix->k + 63) / 64;
+    c->nseg = int(std::min<int64_t>(64, std::max<int64_t>(1, c->nchunks / 16)));
+    c->total = 0;
+    c->max_per_tile = 0;
+    if (!cull_reserve_front(c))
+        return bail(fail(NGD_E_NOMEM, "ngd_cull_build: device workspace allocation failed"));
+    hipStream_t s = S(stream);
+    hipError_t e = hipMemcpyAsync(c->proj.p, proj, sizeof(float) * p->n_proj * mix->n,
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_cull_build_front(c, mix, queries, s);
+    if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (projections, sort, test)"));
+    // the only device -> host read: list sizes
+    e = hipMemcpyAsync(&c->stats_host[0], c->tile_off.as<int64_t>() + c->ntiles, sizeof(int64_t),
+                       hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&c->stats_host[1], c->stats.as<int64_t>() + 1, sizeof(int64_t),
+                           hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (list sizes)"));
+    c->total = c->stats_host[0];
+    c->max_per_tile = (c->ntiles > 0 && c->k > 0) ? c->stats_host[1] : 0;
+    if (c->total >= (int64_t(1) << 31))
+        return bail(fail(NGD_E_NOMEM, "ngd_cull_build: %lld candidates exceed 2^31",
+                         (long long)c->total));
+    if (!c->cand.ensure(sizeof(int32_t) * size_t(c->total)) ||
+        !c->g_tiles.ensure(sizeof(int32_t) * size_t(c->total)))
+        return bail(fail(NGD_E_NOMEM, "ngd_cull_build: candidate list allocation failed"));
+    e = launch_cull_build_lists(c, s);
+    if (e == hipSuccess) e = launch_cull_build_transpose(c, s);
+    if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (lists)"));
+    *inout = c;
+    return NGD_OK;
+}
+
+int ngd_cull_stats(const ngd_cull *c, int64_t *total, int64_t *max_per_tile, int64_t *ntiles)
+{
+    if (!c) return fail(NGD_E_INVAL, "ngd_cull_stats: cull is NULL");
+    if (total) *total = c->total;
+    if (max_per_tile) *max_per_tile = c->max_per_tile;
+    if (ntiles) *ntiles = c->ntiles;
+    return NGD_OK;
+}
+
+int ngd_cull_export(const ngd_cull *c, int32_t *perm, int32_t *gperm, int64_t *tile_off,
+                    int32_t *cand, int64_t *g_off, int32_t *g_tiles, float *tile_lo,
+                    float *tile_hi)
+{
+    if (!c) return fail(NGD_E_INVAL, "ngd_cull_export: cull is NULL");
+    if (!c->mix) return fail(NGD_E_STALE, "ngd_cull_export: cull was not built");
+    struct Item {
+        void *dst;
+        const void *src;
+        size_t bytes;
+    } items[] = {
+        {perm, c->perm.p, sizeof(int32_t) * size_t(c->q)},
+        {gperm, c->gperm.p, sizeof(int32_t) * size_t(c->k)},
+        {tile_off, c->tile_off.p, sizeof(int64_t) * size_t(c->ntiles + 1)},
+        {cand, c->cand.p, sizeof(int32_t) * size_t(c->total)},
+        {g_off, c->g_off.p, sizeof(int64_t) * size_t(c->k + 1)},
+        {g_tiles, c->g_tiles.p, sizeof(int32_t) * size_t(c->total)},
+        {tile_lo, c->tile_lo.p, sizeof(float) * size_t(c->ntiles * c->params.n_proj)},
+        {tile_hi, c->tile_hi.p, sizeof(float) * size_t(c->ntiles * c->params.n_proj)},
+    };
+    hipError_t e = hipDeviceSynchronize();
+    for (const Item &it : items) {
+        if (e != hipSuccess) break;
+        if (it.dst && it.bytes) e = hipMemcpy(it.dst, it.src, it.bytes, hipMemcpyDeviceToHost);
+    }
+    if (e != hipSuccess) return hip_fail(e, "ngd_cull_export");
+    return NGD_OK;
+}
+
+int ngd_cull_destroy(ngd_cull *c)
+{
+    if (!c) return NGD_OK;
+    (void)hipDeviceSynchronize();
+    cull_release(c);
+    delete c;
+    return NGD_OK;
+}
+
+static int check_cull(const char *fn, const ngd_mixture *mix, const ngd_cull *c,
+                      const float *queries, int64_t q)
+{
+    if (c->mix != mix || c->mix_version != mix->version)
+        return fail(NGD_E_STALE, "%s: cull was built for another mixture or version", fn);
+    if (c->queries != queries || c->q != q)
+        return fail(NGD_E_STALE, "%s: cull was built for another query buffer or count", fn);
+    return NGD_OK;
+}
+
+int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries, int64_t q,
+             int precision, float *out, void *stream)
+{
+    if (!mix) return fail(NGD_E_INVAL, "ngd_eval: mixture is NULL");
+    if (q < 0 || q >= (int64_t(1) << 31))
+        return fail(NGD_E_INVAL, "ngd_eval: q=%lld outside [0, 2^31)", (long long)q);
+    if (q > 0 && (!queries || !out)) return fail(NGD_E_INVAL, "ngd_eval: NULL array");
+    if (!aligned4(queries) || !aligned4(out))
+        return fail(NGD_E_INVAL, "ngd_eval: arrays must be 4-byte aligned");
+    if (precision != NGD_FP32)
+        return fail(NGD_E_INVAL, "ngd_eval: unknown precision %d", precision);
+    if (mix->version == 0) return fail(NGD_E_STALE, "ngd_eval: mixture has no parameters yet");
+    if (cull) {
+        const int rc = check_cull("ngd_eval", mix, cull, queries, q);
+        if (rc) return rc;
+    }
+    if (q == 0) return NGD_OK;
+    hipError_t e;
+    if (mix->k == 0 || (cull && cull->total == 0)) {
+        e = launch_zero_f32(out, 3 * q, S(stream));
+    } else if (cull) {
+        e = launch_eval_culled(mix, cull, out, S(stream));
+    } else {
+        e = launch_eval_dense(mix, queries, q, out, S(stream));
+    }
+    if (e != hipSuccess) return hip_fail(e, "ngd_eval");
+    return NGD_OK;
+}
+
+int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
+                      int64_t q, const float *grad_out, int precision, float *g_mean,
+                      float *g_factor, float *g_weight, float *g_colour, void *stream)
+{
+    if (!mix) return fail(NGD_E_INVAL, "ngd_eval_backward: mixture is NULL");
+    if (q < 0 || q >= (int64_t(1) << 31))
+        return fail(NGD_E_INVAL, "ngd_eval_backward: q=%lld outside [0, 2^31)", (long long)q);
+    if (q > 0 && (!queries || !grad_out))
+        return fail(NGD_E_INVAL, "ngd_eval_backward: NULL input array");
+    if (mix->k > 0 && (!g_mean || !g_factor || !g_weight || !g_colour))
+        return fail(NGD_E_INVAL, "ngd_eval_backward: NULL output array");
+    if (!aligned4(queries) || !aligned4(grad_out) || !aligned4(g_mean) || !aligned4(g_factor) ||
+        !aligned4(g_weight) || !aligned4(g_colour))
+        return fail(NGD_E_INVAL, "ngd_eval_backward: arrays must be 4-byte aligned");
+    if (precision != NGD_FP32)
+        return fail(NGD_E_INVAL, "ngd_eval_backward: unknown precision %d", precision);
+    if (mix->version == 0)
+        return fail(NGD_E_STALE, "ngd_eval_backward: mixture has no parameters yet");
+    if (cull) {
+        const int rc = check_cull("ngd_eval_backward", mix, cull, queries, q);
+        if (rc) return rc;
+    }
+    if (mix->k == 0) return NGD_OK;
+    hipError_t e;
+    if (cull)
+        e = launch_backward_culled(mix, const_cast<ngd_cull *>(cull), grad_out, g_mean, g_factor,
+                                   g_weight, g_colour, S(stream));
+    else
+        e = launch_backward_dense(mix, queries, q, grad_out, g_mean, g_factor, g_weight, g_colour,
+                                  S(stream));
+    if (e != hipSuccess) return hip_fail(e, "ngd_eval_backward");
+    return NGD_OK;
+}
+
+int ngd_l2_loss(const float *f, const float *target, int64_t q, float *loss, float *grad,
+                void *stream)
+{
+    if (q < 0 || q >= (int64_t(1) << 31))
+        return fail(NGD_E_INVAL, "ngd_l2_loss: q=%lld outside [0, 2^31)", (long long)q);
+    if (!loss || (q > 0 && (!f || !target || !grad)))
+        return fail(NGD_E_INVAL, "ngd_l2_loss: NULL array");
+    if (!aligned4(f) || !aligned4(target) || !aligned4(grad) || !aligned4(loss))
+        return fail(NGD_E_INVAL, "ngd_l2_loss: arrays must be 4-byte aligned");
+    // per-device partial-sum workspace, kept for the life of the process
+    constexpr int kParts = 1024;
+    static std::mutex mu;
+    static DevBuf parts[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "ngd_l2_loss");
+    if (dev < 0 || dev >= 64) return fail(NGD_E_INVAL, "ngd_l2_loss: device %d", dev);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!parts[dev].ensure(sizeof(double) * kParts))
+            return fail(NGD_E_NOMEM, "ngd_l2_loss: workspace allocation failed");
+    }
+    e = launch_l2_loss(f, target, q, loss, grad, parts[dev].as<float>(), kParts, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "ngd_l2_loss");
+    return NGD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,701 @@
+// Tile cull (Sec. 3.2, Eq. 3-5) on the device.
+//
+// Steps, all on the caller's stream:
+//   1. Gaussian projections m_r = m . r (float32 fma chain) and thresholds
+//      kappa^2 sigma_r^2 with sigma_r^2 = |L^T r|^2 in float64 (Eq. 3, 4).
+//   2. Query projections q_r (Eq. 3) and their range per projection.
+//   3. Locality keys: key_proj projections quantised to key_bits each over
+//      the queries' range, bits interleaved (a Morton code); the same key for
+//      the projected means.
+//   4. Stable LSD radix sorts (8-bit digits, wavefront ballot ranking) of the
+//      queries and of the Gaussians by key.
+//   5. Tiles of `tile` consecutive sorted queries; per tile and projection
+//      the extent [lo, hi] of its projected queries; sorted SoA query copy.
+//   6. The (tile, Gaussian) interval test: one wave per 64 sorted Gaussians
+//      walks a range of tiles, tile bounds wave-uniform, leaving each tile as
+//      soon as no lane survives; one 64-bit ballot mask per (chunk, tile).
+//   7. Per-tile counts, an exclusive scan into CSR offsets, and the
+//      candidate lists (ascending sorted positions); then the transposed
+//      Gaussian -> tile lists for the backward pass.
+//
+// Every operation that decides membership is an IEEE basic operation in a
+// fixed order (no contraction in this file), so the lists are reproducible
+// bit for bit by a CPU implementation of the same recipe.
+#pragma clang fp contract(off)
+
+#include <algorithm>
+#include <utility>
+
+#include "ngd_internal.hpp"
+#include "wave.hpp"
+
+namespace ngd {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <int N>
+__global__ __launch_bounds__(kThreads) void k_gauss_proj(int64_t k, int P,
+                                                         const float *__restrict__ rec, int R,
+                                                         const float *__restrict__ lfac,
+                                                         const float *__restrict__ proj,
+                                                         float kappa2, float *__restrict__ g_mr,
+                                                         float *__restrict__ g_thr)
+{
+    constexpr int T = N * (N + 1) / 2;
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= k) return;
+    float m[N];
+    double L[T];
+#pragma unroll
+    for (int a = 0; a < N; ++a) m[a] = rec[i * R + a];
+#pragma unroll
+    for (int e = 0; e < T; ++e) L[e] = lfac[i * T + e];
+    for (int j = 0; j < P; ++j) {
+        const float *r = proj + j * N;
+        float acc = 0.0f;
+#pragma unroll
+        for (int a = 0; a < N; ++a) acc = fmaf(m[a], r[a], acc);
+        g_mr[j * k + i] = acc;
+        double s2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+            double u = 0.0;   // (L^T r)_b = sum_{a >= b} L_ab r_a
+#pragma unroll
+            for (int a = b; a < N; ++a) u = fma(L[a * (a + 1) / 2 + b], double(r[a]), u);
+            s2 = fma(u, u, s2);
+        }
+        const float s2f = float(s2);
+        g_thr[j * k + i] = kappa2 * s2f;
+    }
+}
+
+template <int N, int PMAX>
+__global__ __launch_bounds__(kThreads) void k_query_proj(int64_t q, int P,
+                                                         const float *__restrict__ queries,
+                                                         const float *__restrict__ proj,
+                                                         float *__restrict__ qr,
+                                                         float *__restrict__ part)
+{
+    __shared__ float smin[kThreads / kWave][PMAX], smax[kThreads / kWave][PMAX];
+    const int64_t p = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const bool valid = p < q;
+    const int w = threadIdx.x / kWave;
+    float x[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) x[a] = valid ? queries[p * N + a] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        if (j < P) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int a = 0; a < N; ++a) acc = fmaf(x[a], proj[j * N + a], acc);
+            if (valid) qr[j * q + p] = acc;
+            const float lo = wave_min(valid ? acc : INFINITY);
+            const float hi = wave_max(valid ? acc : -INFINITY);
+            if (lane_id() == 0) {
+                smin[w][j] = lo;
+                smax[w][j] = hi;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < P) {
+        const int j = threadIdx.x;
+        float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+        for (int i = 0; i < kThreads / kWave; ++i) {
+            lo = fminf(lo, smin[i][j]);
+            hi = fmaxf(hi, smax[i][j]);
+        }
+        part[(int64_t(blockIdx.x) * P + j) * 2 + 0] = lo;
+        part[(int64_t(blockIdx.x) * P + j) * 2 + 1] = hi;
+    }
+}
+
+// qrange = [lo (P) | hi (P) | scale (P)]
+__global__ __launch_bounds__(kThreads) void k_range_final(int64_t nparts, int P, int key_bits,
+                                                          const float *__restrict__ part,
+                                                          float *__restrict__ qrange)
+{
+    const int j = threadIdx.x;
+    if (j >= P) return;
+    float lo = INFINITY, hi = -INFINITY;
+    for (int64_t b = 0; b < nparts; ++b) {
+        lo = fminf(lo, part[(b * P + j) * 2 + 0]);
+        hi = fmaxf(hi, part[(b * P + j) * 2 + 1]);
+    }
+    qrange[j] = lo;
+    qrange[P + j] = hi;
+    qrange[2 * P + j] =
+        (hi > lo) ? float(double(1u << key_bits) / (double(hi) - double(lo))) : 0.0f;
+}
+
+// Locality key of row i of a P x n SoA array of projections.
+__global__ __launch_bounds__(kThreads) void k_keys(int64_t n, int P,
+                                                   const float *__restrict__ vals,
+                                                   const float *__restrict__ qrange,
+                                                   int key_proj, int key_bits,
+                                                   uint32_t *__restrict__ keys,
+                                                   int32_t *__restrict__ idx)
+{
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const float top = float((1u << key_bits) - 1u);
+    uint32_t key = 0;
+    int digit[NGD_MAX_PROJ];
+#pragma unroll
+    for (int j = 0; j < NGD_MAX_PROJ; ++j) {
+        if (j < key_proj) {
+            const float t = vals[j * n + i] - qrange[j];
+            float u = t * qrange[2 * P + j];
+            u = fminf(fmaxf(u, 0.0f), top);
+            digit[j] = int(u);
+        }
+    }
+    for (int b = key_bits - 1; b >= 0; --b) {
+#pragma unroll
+        for (int j = 0; j < NGD_MAX_PROJ; ++j)
+            if (j < key_proj) key = (key << 1) | uint32_t((digit[j] >> b) & 1);
+    }
+    keys[i] = key;
+    idx[i] = int32_t(i);
+}
+
+// ---- stable LSD radix sort (8-bit digits) ------------------------------
+constexpr int kRadixItems = 16;                        // per lane
+constexpr int kRadixPerWave = kRadixItems * kWave;     // 1024
+constexpr int kRadixPerBlock = kRadixPerWave * (kThreads / kWave);   // 4096
+
+__global__ __launch_bounds__(kThreads) void k_radix_count(int64_t n, int shift,
+                                                          const uint32_t *__restrict__ keys,
+                                                          int32_t *__restrict__ hist,
+                                                          int64_t nblocks)
+{
+    __shared__ int cnt[256];
+    cnt[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = int64_t(blockIdx.x) * kRadixPerBlock;
+    for (int it = threadIdx.x; it < kRadixPerBlock; it += kThreads) {
+        const int64_t i = base + it;
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1);
+    }
+    __syncthreads();
+    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
+}
+
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(
+    int64_t n, int shift, const uint32_t *__restrict__ keys_in,
+    const int32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
+    int32_t *__restrict__ vals_out, const int64_t *__restrict__ off, int64_t nblocks)
+{
+    constexpr int W = kThreads / kWave;
+    __shared__ int wcnt[W][256];
+    __shared__ int wbase[W][256];
+    const int w = threadIdx.x / kWave, lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < W; ++i) wcnt[i][threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t wstart = int64_t(blockIdx.x) * kRadixPerBlock + int64_t(w) * kRadixPerWave;
+    for (int it = 0; it < kRadixItems; ++it) {
+        const int64_t i = wstart + int64_t(it) * kWave + lane;
+        if (i < n) atomicAdd(&wcnt[w][(keys_in[i] >> shift) & 0xffu], 1);
+    }
+    __syncthreads();
+    {
+        const int d = threadIdx.x;
+        int run = int(off[int64_t(d) * nblocks + blockIdx.x]);
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            wbase[i][d] = run;
+            run += wcnt[i][d];
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < kRadixItems; ++it) {
+        const int64_t i = wstart + int64_t(it) * kWave + lane;
+        const bool valid = i < n;
+        const uint32_t key = valid ? keys_in[i] : 0u;
+        const int d = int((key >> shift) & 0xffu);
+        uint64_t match = ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const bool bit = (d >> b) & 1;
+            const uint64_t m = ballot(valid && bit);
+            match &= bit ? m : ~m;
+        }
+        if (valid) {
+            const int rank = __popcll(match & lanemask_lt());
+            const int64_t dest = int64_t(wbase[w][d]) + rank;
+            if (dest < n) {
+                keys_out[dest] = key;
+                vals_out[dest] = vals_in[i];
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (valid && ((match >> lane) >> 1) == 0) wbase[w][d] += __popcll(match);
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// ---- tiles ---------------------------------------------------------------
+template <int N, int PMAX>
+__global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P,
+                                                      const int32_t *__restrict__ perm,
+                                                      const float *__restrict__ qr,
+                                                      const float *__restrict__ queries,
+                                                      float *__restrict__ qs,
+                                                      float *__restrict__ tlo,
+                                                      float *__restrict__ thi)
+{
+    __shared__ float smin[1024 / kWave][PMAX], smax[1024 / kWave][PMAX];
+    const int64_t t = blockIdx.x;
+    float lo[PMAX], hi[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        lo[j] = INFINITY;
+        hi[j] = -INFINITY;
+    }
+    for (int s = threadIdx.x; s < tile; s += blockDim.x) {
+        const int64_t p = t * tile + s;
+        if (p >= q) break;
+        const int64_t idx = perm[p];
+#pragma unroll
+        for (int a = 0; a < N; ++a) qs[a * q + p] = queries[idx * N + a];
+#pragma unroll
+        for (int j = 0; j < PMAX; ++j) {
+            if (j < P) {
+                const float v = qr[j * q + idx];
+                lo[j] = fminf(lo[j], v);
+                hi[j] = fmaxf(hi[j], v);
+            }
+        }
+    }
+    const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        if (j < P) {
+            const float a = wave_min(lo[j]), b = wave_max(hi[j]);
+            if (lane_id() == 0) {
+                smin[w][j] = a;
+                smax[w][j] = b;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < P) {
+        const int j = threadIdx.x;
+        float a = INFINITY, b = -INFINITY;
+        for (int i = 0; i < nw; ++i) {
+            a = fminf(a, smin[i][j]);
+            b = fmaxf(b, smax[i][j]);
+        }
+        tlo[t * P + j] = a;
+        thi[t * P + j] = b;
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_gauss_gather(
+    int64_t k, int R, int P, const int32_t *__restrict__ gperm, const float *__restrict__ rec,
+    const float *__restrict__ g_mr, const float *__restrict__ g_thr, float *__restrict__ grec,
+    float *__restrict__ g_mr_s, float *__restrict__ g_thr_s)
+{
+    const int64_t s = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (s >= k) return;
+    const int64_t i = gperm[s];
+    for (int e = 0; e < R; e += 4)
+        *reinterpret_cast<float4 *>(grec + s * R + e) =
+            *reinterpret_cast<const float4 *>(rec + i * R + e);
+    for (int j = 0; j < P; ++j) {
+        g_mr_s[j * k + s] = g_mr[j * k + i];
+        g_thr_s[j * k + s] = g_thr[j * k + i];
+    }
+}
+
+// ---- the interval test (Eq. 5 per tile) -----------------------------------
+template <int PMAX>
+__global__ __launch_bounds__(kThreads) void k_cull_test(
+    int64_t k, int64_t ntiles, int64_t tpad, int P, int tiles_per_wave,
+    const float *__restrict__ g_mr_s, const float *__restrict__ g_thr_s,
+    const float *__restrict__ tlo, const float *__restrict__ thi, uint64_t *__restrict__ masks)
+{
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t nchunks = (k + kWave - 1) / kWave;
+    const int64_t c = int64_t(blockIdx.x) * (kThreads / kWave) + w;
+    if (c >= nchunks) return;
+    const int64_t s = c * kWave + lane;
+    const bool valid = s < k;
+    float mr[PMAX], thr[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        mr[j] = (valid && j < P) ? g_mr_s[j * k + s] : 0.0f;
+        thr[j] = (valid && j < P) ? g_thr_s[j * k + s] : -1.0f;
+    }
+    const int64_t t0 = int64_t(blockIdx.y) * tiles_per_wave;
+    const int64_t t1 = (t0 + tiles_per_wave < ntiles) ? t0 + tiles_per_wave : ntiles;
+    uint64_t mine = 0;
+    for (int64_t t = t0; t < t1; ++t) {
+        const float *lo = tlo + t * P;
+        const float *hi = thi + t * P;
+        bool alive = valid;
+#pragma unroll
+        for (int j = 0; j < PMAX; ++j) {
+            if (j < P) {
+                const float a = lo[j] - mr[j];
+                const float b = mr[j] - hi[j];
+                const float dist = fmaxf(fmaxf(a, b), 0.0f);
+                const float d2 = dist * dist;
+                alive = alive && (d2 <= thr[j]);
+                if (ballot(alive) == 0) break;
+            }
+        }
+        const uint64_t m = ballot(alive);
+        const int slot = int((t - t0) & (kWave - 1));
+        if (lane == slot) mine = m;
+        if (slot == kWave - 1 || t == t1 - 1) {
+            const int64_t tb = t - slot;
+            if (tb + lane <= t) masks[c * tpad + tb + lane] = mine;
+        }
+    }
+}
+
+// ---- lists ----------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_seg_count(int64_t ntiles, int64_t tpad,
+                                                        int64_t nchunks, int64_t per_seg,
+                                                        const uint64_t *__restrict__ masks,
+                                                        int32_t *__restrict__ seg_cnt)
+{
+    const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (t >= ntiles) return;
+    const int64_t seg = blockIdx.y;
+    const int64_t c0 = seg * per_seg;
+    const int64_t c1 = (c0 + per_seg < nchunks) ? c0 + per_seg : nchunks;
+    int cnt = 0;
+    for (int64_t c = c0; c < c1; ++c) cnt += __popcll(masks[c * tpad + t]);
+    seg_cnt[seg * ntiles + t] = cnt;
+}
+
+__global__ __launch_bounds__(kThreads) void k_seg_prefix(int64_t ntiles, int nseg,
+                                                         int32_t *__restrict__ seg_cnt,
+                                                         int32_t *__restrict__ tile_cnt,
+                                                         unsigned long long *__restrict__ maxc)
+{
+    const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (t >= ntiles) return;
+    int run = 0;
+    for (int seg = 0; seg < nseg; ++seg) {
+        const int v = seg_cnt[int64_t(seg) * ntiles + t];
+        seg_cnt[int64_t(seg) * ntiles + t] = run;
+        run += v;
+    }
+    tile_cnt[t] = run;
+    atomicMax(maxc, static_cast<unsigned long long>(run));
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t tpad,
+                                                        int64_t nchunks, int64_t per_seg,
+                                                        const uint64_t *__restrict__ masks,
+                                                        const int32_t *__restrict__ seg_cnt,
+                                                        const int64_t *__restrict__ tile_off,
+                                                        int32_t *__restrict__ cand)
+{
+    const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (t >= ntiles) return;
+    const int64_t seg = blockIdx.y;
+    const int64_t c0 = seg * per_seg;
+    const int64_t c1 = (c0 + per_seg < nchunks) ? c0 + per_seg : nchunks;
+    int64_t pos = tile_off[t] + seg_cnt[seg * ntiles + t];
+    const int64_t end = tile_off[t + 1];
+    for (int64_t c = c0; c < c1; ++c) {
+        uint64_t m = masks[c * tpad + t];
+        while (m) {
+            const int b = __ffsll(static_cast<unsigned long long>(m)) - 1;
+            if (pos < end) cand[pos] = int32_t(c * kWave + b);
+            ++pos;
+            m &= m - 1;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_g_count(int64_t k, int64_t ntiles, int64_t tpad,
+                                                      const uint64_t *__restrict__ masks,
+                                                      int32_t *__restrict__ g_cnt)
+{
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t nchunks = (k + kWave - 1) / kWave;
+    const int64_t c = int64_t(blockIdx.x) * (kThreads / kWave) + w;
+    if (c >= nchunks) return;
+    const uint64_t *row = masks + c * tpad;
+    int cnt = 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const uint64_t m = row[t];
+        cnt += int((m >> lane) & 1u);
+    }
+    const int64_t s = c * kWave + lane;
+    if (s < k) g_cnt[s] = cnt;
+}
+
+__global__ __launch_bounds__(kThreads) void k_g_fill(int64_t k, int64_t ntiles, int64_t tpad,
+                                                     const uint64_t *__restrict__ masks,
+                                                     const int64_t *__restrict__ g_off,
+                                                     int32_t *__restrict__ g_tiles)
+{
+    const int w = threadIdx.x / kWave, lane = lane_id();
+    const int64_t nchunks = (k + kWave - 1) / kWave;
+    const int64_t c = int64_t(blockIdx.x) * (kThreads / kWave) + w;
+    if (c >= nchunks) return;
+    const int64_t s = c * kWave + lane;
+    const bool valid = s < k;
+    const uint64_t *row = masks + c * tpad;
+    int64_t pos = valid ? g_off[s] : 0;
+    const int64_t end = valid ? g_off[s + 1] : 0;
+    for (int64_t t = 0; t < ntiles; ++t) {
+        const uint64_t m = row[t];
+        if (m == 0) continue;
+        if (valid && ((m >> lane) & 1u)) {
+            if (pos < end) g_tiles[pos] = int32_t(t);
+            ++pos;
+        }
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p, int n)
+{
+    if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
+}
+
+__global__ void k_zero_i32(int32_t *p, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+template <typename T> inline unsigned nblk(T n, int per)
+{
+    return unsigned((int64_t(n) + per - 1) / per);
+}
+
+// Sorts (keys, vals) by the low `nbits` bits of the keys; returns which
+// ping-pong buffer holds the result (0 or 1).
+hipError_t radix_sort(int64_t n, int nbits, uint32_t *k0, uint32_t *k1, int32_t *v0,
+                      int32_t *v1, int32_t *hist, int64_t *off, void *scan_tmp, hipStream_t s,
+                      int *which)
+{
+    *which = 0;
+    if (n == 0) return hipSuccess;
+    const int64_t nb = (n + kRadixPerBlock - 1) / kRadixPerBlock;
+    uint32_t *kin = k0, *kout = k1;
+    int32_t *vin = v0, *vout = v1;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        k_radix_count<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, shift, kin, hist, nb);
+        hipError_t e = scan_counts(hist, off, 256 * nb, scan_tmp, s);
+        if (e != hipSuccess) return e;
+        k_radix_scatter<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, shift, kin, vin, kout, vout,
+                                                               off, nb);
+        std::swap(kin, kout);
+        std::swap(vin, vout);
+        *which ^= 1;
+    }
+    return hipGetLastError();
+}
+
+template <int N>
+hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hipStream_t s)
+{
+    const int P = c->params.n_proj;
+    const int64_t q = c->q, k = c->k;
+    const int R = rec_stride(N);
+    const int nbits = c->params.key_proj * c->params.key_bits;
+    hipError_t e;
+    if (k > 0) {
+        k_gauss_proj<N><<<nblk(k, kThreads), kThreads, 0, s>>>(
+            k, P, mix->rec.as<float>(), R, mix->lfac.as<float>(), c->proj.as<float>(), c->kappa2,
+            c->g_mr.as<float>(), c->g_thr.as<float>());
+    }
+    const int64_t nparts = (q + kThreads - 1) / kThreads;
+    if (q > 0) {
+        if (P <= 16)
+            k_query_proj<N, 16><<<nblk(q, kThreads), kThreads, 0, s>>>(
+                q, P, queries, c->proj.as<float>(), c->qr.as<float>(), c->range_part.as<float>());
+        else
+            k_query_proj<N, 32><<<nblk(q, kThreads), kThreads, 0, s>>>(
+                q, P, queries, c->proj.as<float>(), c->qr.as<float>(), c->range_part.as<float>());
+    }
+    k_range_final<<<1, kThreads, 0, s>>>(nparts, P, c->params.key_bits,
+                                         c->range_part.as<float>(), c->qrange.as<float>());
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    // queries: keys, sort -> perm
+    int which = 0;
+    if (q > 0) {
+        k_keys<<<nblk(q, kThreads), kThreads, 0, s>>>(q, P, c->qr.as<float>(),
+                                                      c->qrange.as<float>(), c->params.key_proj,
+                                                      c->params.key_bits, c->keys0.as<uint32_t>(),
+                                                      c->vals0.as<int32_t>());
+        e = radix_sort(q, nbits, c->keys0.as<uint32_t>(), c->keys1.as<uint32_t>(),
+                       c->vals0.as<int32_t>(), c->vals1.as<int32_t>(), c->radix_hist.as<int32_t>(),
+                       c->radix_off.as<int64_t>(), c->scan_tmp.p, s, &which);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(c->perm.p, which ? c->vals1.p : c->vals0.p, sizeof(int32_t) * q,
+                           hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    // Gaussians: keys of the projected means, sort -> gperm
+    if (k > 0) {
+        k_keys<<<nblk(k, kThreads), kThreads, 0, s>>>(k, P, c->g_mr.as<float>(),
+                                                      c->qrange.as<float>(), c->params.key_proj,
+                                                      c->params.key_bits, c->keys0.as<uint32_t>(),
+                                                      c->vals0.as<int32_t>());
+        e = radix_sort(k, nbits, c->keys0.as<uint32_t>(), c->keys1.as<uint32_t>(),
+                       c->vals0.as<int32_t>(), c->vals1.as<int32_t>(), c->radix_hist.as<int32_t>(),
+                       c->radix_off.as<int64_t>(), c->scan_tmp.p, s, &which);
+        if (e != hipSuccess) return e;
+        e = hipMemcpyAsync(c->gperm.p, which ? c->vals1.p : c->vals0.p, sizeof(int32_t) * k,
+                           hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return e;
+    }
+    // tiles
+    if (c->ntiles > 0) {
+        const int bt = int(std::min<int64_t>(1024, (int64_t(c->params.tile) + 63) / 64 * 64));
+        if (P <= 16)
+            k_tile_bounds<N, 16><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
+                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), queries,
+                c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>());
+        else
+            k_tile_bounds<N, 32><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
+                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), queries,
+                c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>());
+    }
+    if (k > 0) {
+        k_gauss_gather<<<nblk(k, kThreads), kThreads, 0, s>>>(
+            k, R, P, c->gperm.as<int32_t>(), mix->rec.as<float>(), c->g_mr.as<float>(),
+            c->g_thr.as<float>(), c->grec.as<float>(), c->g_mr_s.as<float>(),
+            c->g_thr_s.as<float>());
+    }
+    k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long *>(c->stats.p), 2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (k == 0 || c->ntiles == 0) {
+        // no pairs: every tile list is empty
+        if (c->ntiles > 0)
+            k_zero_i32<<<nblk(c->ntiles, kThreads), kThreads, 0, s>>>(c->tile_cnt.as<int32_t>(),
+                                                                     c->ntiles);
+        return scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
+                           c->scan_tmp.p, s);
+    }
+    // interval test
+    const int tiles_per_wave = 512;
+    dim3 grid(nblk(c->nchunks, kThreads / kWave), nblk(c->ntiles, tiles_per_wave));
+    if (P <= 16)
+        k_cull_test<16><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,
+                                                   c->g_mr_s.as<float>(), c->g_thr_s.as<float>(),
+                                                   c->tile_lo.as<float>(), c->tile_hi.as<float>(),
+                                                   c->masks.as<uint64_t>());
+    else
+        k_cull_test<32><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,
+                                                   c->g_mr_s.as<float>(), c->g_thr_s.as<float>(),
+                                                   c->tile_lo.as<float>(), c->tile_hi.as<float>(),
+                                                   c->masks.as<uint64_t>());
+    // per-tile counts -> offsets
+    const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
+    dim3 sgrid(nblk(c->ntiles, kThreads), unsigned(c->nseg));
+    k_seg_count<<<sgrid, kThreads, 0, s>>>(c->ntiles, c->tpad, c->nchunks, per_seg,
+                                           c->masks.as<uint64_t>(), c->seg_cnt.as<int32_t>());
+    k_seg_prefix<<<nblk(c->ntiles, kThreads), kThreads, 0, s>>>(
+        c->ntiles, c->nseg, c->seg_cnt.as<int32_t>(), c->tile_cnt.as<int32_t>(),
+        reinterpret_cast<unsigned long long *>(c->stats.as<int64_t>() + 1));
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
+                       c->scan_tmp.p, s);
+}
+
+}  // namespace
+
+hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix, const float *queries,
+                                   hipStream_t s)
+{
+    switch (c->n) {
+#define NGD_CASE(NN) \
+    case NN: return front_n<NN>(c, mix, queries, s);
+        NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
+        NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
+#undef NGD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s)
+{
+    if (c->total == 0 || c->ntiles == 0 || c->k == 0) return hipSuccess;
+    const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
+    dim3 sgrid(nblk(c->ntiles, kThreads), unsigned(c->nseg));
+    k_fill_cand<<<sgrid, kThreads, 0, s>>>(c->ntiles, c->tpad, c->nchunks, per_seg,
+                                           c->masks.as<uint64_t>(), c->seg_cnt.as<int32_t>(),
+                                           c->tile_off.as<int64_t>(), c->cand.as<int32_t>());
+    return hipGetLastError();
+}
+
+hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s)
+{
+    const int64_t k = c->k;
+    if (k == 0) return scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), 0,
+                                   c->scan_tmp.p, s);
+    if (c->ntiles == 0 || c->total == 0) {
+        // no candidates: every Gaussian has an empty tile list
+        k_zero_i32<<<nblk(k, kThreads), kThreads, 0, s>>>(c->g_cnt.as<int32_t>(), k);
+        return scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k, c->scan_tmp.p, s);
+    }
+    const unsigned gb = nblk(c->nchunks, kThreads / kWave);
+    k_g_count<<<gb, kThreads, 0, s>>>(k, c->ntiles, c->tpad, c->masks.as<uint64_t>(),
+                                      c->g_cnt.as<int32_t>());
+    hipError_t e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k, c->scan_tmp.p, s);
+    if (e != hipSuccess) return e;
+    k_g_fill<<<gb, kThreads, 0, s>>>(k, c->ntiles, c->tpad, c->masks.as<uint64_t>(),
+                                     c->g_off.as<int64_t>(), c->g_tiles.as<int32_t>());
+    return hipGetLastError();
+}
+
+bool cull_reserve_front(ngd_cull *c)
+{
+    const int P = c->params.n_proj;
+    const int64_t q = c->q, k = c->k, n = c->n;
+    const int64_t qq = q > 0 ? q : 1, kk = k > 0 ? k : 1;
+    const int64_t T = c->ntiles > 0 ? c->ntiles : 1;
+    const int64_t qk = std::max(qq, kk);
+    const int64_t nb_sort = (qk + kRadixPerBlock - 1) / kRadixPerBlock;
+    const int64_t nparts = (qq + kThreads - 1) / kThreads;
+    const int64_t scan_n = std::max<int64_t>({256 * nb_sort, T, kk});
+    bool ok = true;
+    ok &= c->proj.ensure(sizeof(float) * P * n);
+    ok &= c->qr.ensure(sizeof(float) * P * qq);
+    ok &= c->range_part.ensure(sizeof(float) * 2 * P * nparts);
+    ok &= c->qrange.ensure(sizeof(float) * 3 * P);
+    ok &= c->g_mr.ensure(sizeof(float) * P * kk);
+    ok &= c->g_thr.ensure(sizeof(float) * P * kk);
+    ok &= c->keys0.ensure(sizeof(uint32_t) * qk);
+    ok &= c->keys1.ensure(sizeof(uint32_t) * qk);
+    ok &= c->vals0.ensure(sizeof(int32_t) * qk);
+    ok &= c->vals1.ensure(sizeof(int32_t) * qk);
+    ok &= c->radix_hist.ensure(sizeof(int32_t) * 256 * nb_sort);
+    ok &= c->radix_off.ensure(sizeof(int64_t) * (256 * nb_sort + 1));
+    ok &= c->perm.ensure(sizeof(int32_t) * qq);
+    ok &= c->gperm.ensure(sizeof(int32_t) * kk);
+    ok &= c->qs.ensure(sizeof(float) * n * qq);
+    ok &= c->gs.ensure(sizeof(float) * 3 * qq);
+    ok &= c->tile_lo.ensure(sizeof(float) * T * P);
+    ok &= c->tile_hi.ensure(sizeof(float) * T * P);
+    ok &= c->grec.ensure(sizeof(float) * kk * rec_stride(int(n)));
+    ok &= c->g_mr_s.ensure(sizeof(float) * P * kk);
+    ok &= c->g_thr_s.ensure(sizeof(float) * P * kk);
+    ok &= c->masks.ensure(sizeof(uint64_t) * std::max<int64_t>(c->nchunks, 1) *
+                          std::max<int64_t>(c->tpad, 64));
+    ok &= c->seg_cnt.ensure(sizeof(int32_t) * c->nseg * T);
+    ok &= c->tile_cnt.ensure(sizeof(int32_t) * T);
+    ok &= c->tile_off.ensure(sizeof(int64_t) * (T + 1));
+    ok &= c->g_cnt.ensure(sizeof(int32_t) * kk);
+    ok &= c->g_off.ensure(sizeof(int64_t) * (kk + 1));
+    ok &= c->scan_tmp.ensure(scan_tmp_bytes(scan_n));
+    ok &= c->stats.ensure(sizeof(int64_t) * 2);
+    return ok;
+}
+
+}  // namespace ngd

@@ -1,0 +1,137 @@
+// Internal declarations shared by the host side of libngd and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/ngd.h"
+
+namespace ngd {
+
+// 0.5 * log2(e): exp(-M/2) == exp2(-M * kHalfLog2e).  The precision factor
+// is stored pre-scaled by sqrt(kHalfLog2e) so the kernels call exp2 directly.
+constexpr double kHalfLog2e = 0.72134752044448170368;
+constexpr double kSqrtHalfLog2e = 0.84932180028801904272;
+
+// Pairs whose Gaussian value is certified below tau * 2^-kSkipLog2Margin
+// are skipped inside the evaluation kernels (see ngd_eval).
+constexpr double kSkipLog2Margin = 20.0;
+
+inline int tri(int n) { return n * (n + 1) / 2; }
+
+// Per-Gaussian record read by the evaluation kernels, one row of `stride`
+// floats: m (n) | S' = sqrt(kHalfLog2e) L^-1 packed lower by rows (tri) |
+// alpha*c (3) | alpha (1) | c (3) | padding to a multiple of 4.
+inline int rec_stride(int n) { return (n + tri(n) + 7 + 3) / 4 * 4; }
+
+// Device allocation through the configurable allocator; reports the
+// matching release function (NULL: hipFree) and its context.
+void *dev_alloc(size_t bytes, void (**free_fn)(void *, void *), void **ctx);
+
+// A grow-only device buffer, released with the allocator that made it.
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    void (*free_fn)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+    // Returns false on allocation failure (old contents are not kept).
+    bool ensure(size_t bytes);
+    void release();
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace ngd
+
+struct ngd_mixture {
+    int n = 0;
+    int64_t k = 0;
+    int64_t version = 0;
+    int device = 0;
+    ngd::DevBuf rec;     // k x rec_stride(n) float
+    ngd::DevBuf lfac;    // k x tri(n) float: copy of L for the cull
+    ngd::DevBuf flag;    // int: nonzero if the last update saw a bad factor
+};
+
+struct ngd_cull {
+    // identity of what it was built for
+    const ngd_mixture *mix = nullptr;
+    int64_t mix_version = -1;
+    const float *queries = nullptr;
+    int64_t q = 0;
+    int n = 0;
+    int64_t k = 0;
+    ngd_cull_params params{};
+    float kappa2 = 0.f;
+    int64_t ntiles = 0;
+    int64_t total = 0;
+    int64_t max_per_tile = 0;
+    int64_t nchunks = 0;       // ceil(k / 64)
+    int64_t tpad = 0;          // ntiles rounded up to 64
+    int nseg = 0;              // chunk segments used by the list build
+    // device buffers
+    ngd::DevBuf proj;          // n_proj x n float
+    ngd::DevBuf qr;            // n_proj x q float (caller order)
+    ngd::DevBuf range_part;    // per-block min/max partials
+    ngd::DevBuf qrange;        // n_proj lo | n_proj hi | n_proj scale (float)
+    ngd::DevBuf g_mr, g_thr;   // n_proj x k float (caller order)
+    ngd::DevBuf keys0, keys1, vals0, vals1;   // radix sort ping-pong
+    ngd::DevBuf radix_hist;    // 256 x nblocks int32
+    ngd::DevBuf radix_off;     // 256 x nblocks + 1 int64
+    ngd::DevBuf perm;          // q int32
+    ngd::DevBuf gperm;         // k int32
+    ngd::DevBuf qs;            // n x q float: sorted queries, by dimension
+    ngd::DevBuf gs;            // 3 x q float: sorted upstream gradient
+    ngd::DevBuf tile_lo, tile_hi;   // ntiles x n_proj float
+    ngd::DevBuf grec;          // k x rec_stride float, sorted Gaussians
+    ngd::DevBuf g_mr_s, g_thr_s;    // n_proj x k float, sorted Gaussians
+    ngd::DevBuf masks;         // nchunks x tpad uint64
+    ngd::DevBuf seg_cnt;       // nseg x ntiles int32 (counts, then prefixes)
+    ngd::DevBuf tile_cnt;      // ntiles int32
+    ngd::DevBuf tile_off;      // ntiles + 1 int64
+    ngd::DevBuf cand;          // total int32
+    ngd::DevBuf g_cnt;         // k int32
+    ngd::DevBuf g_off;         // k + 1 int64
+    ngd::DevBuf g_tiles;       // total int32
+    ngd::DevBuf scan_tmp;      // scan block sums
+    ngd::DevBuf stats;         // 2 int64: total, max per tile
+    int64_t *stats_host = nullptr;  // pinned
+};
+
+namespace ngd {
+
+// ---- launchers (each returns the hipError_t of its launches) ----------
+hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *factor,
+                          const float *weight, const float *colour, float *rec,
+                          float *lfac, int *flag, hipStream_t s);
+
+hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix,
+                                   const float *queries, hipStream_t s);
+hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s);
+hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s);
+
+hipError_t launch_eval_dense(const ngd_mixture *mix, const float *queries, int64_t q,
+                             float *out, hipStream_t s);
+hipError_t launch_eval_culled(const ngd_mixture *mix, const ngd_cull *c, float *out,
+                              hipStream_t s);
+hipError_t launch_backward_dense(const ngd_mixture *mix, const float *queries, int64_t q,
+                                 const float *grad_out, float *g_mean, float *g_factor,
+                                 float *g_weight, float *g_colour, hipStream_t s);
+hipError_t launch_backward_culled(const ngd_mixture *mix, ngd_cull *c,
+                                  const float *grad_out, float *g_mean, float *g_factor,
+                                  float *g_weight, float *g_colour, hipStream_t s);
+hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+hipError_t launch_l2_loss(const float *f, const float *target, int64_t q, float *loss,
+                          float *grad, float *partials, int nparts, hipStream_t s);
+
+// Exclusive scan of `n` int32 counts into n + 1 int64 offsets (out[n] is
+// the total).  `tmp` must hold scan_tmp_bytes(n) bytes.
+size_t scan_tmp_bytes(int64_t n);
+hipError_t scan_counts(const int32_t *in, int64_t *out, int64_t n, void *tmp,
+                       hipStream_t s);
+
+// Sizes the cull's buffers need before the lists are built.
+bool cull_reserve_front(ngd_cull *c);
+
+}  // namespace ngd

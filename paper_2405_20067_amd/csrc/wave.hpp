@@ -1,0 +1,92 @@
+// Wavefront (64-lane) primitives for gfx950: DPP prefix scans, ballots and
+// butterfly reductions.  Device code only.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ngd {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+__device__ __forceinline__ uint64_t ballot(bool pred)
+{
+    return __builtin_amdgcn_ballot_w64(pred);
+}
+
+// Mask of the lanes below the calling lane.
+__device__ __forceinline__ uint64_t lanemask_lt()
+{
+    return (uint64_t(1) << lane_id()) - 1;
+}
+
+// DPP controls (GFX9 encoding).
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+// Inclusive prefix sum over the 64 lanes of the wave (all lanes active).
+// Within each row of 16 lanes a Hillis-Steele scan over row_shr 1, 2, 4, 8
+// (lanes shifted in from outside the row read 0), then row_bcast 15 carries
+// row 0 into row 1 and row 2 into row 3, and row_bcast 31 carries lanes
+// 0..31 into rows 2 and 3.
+__device__ __forceinline__ int wave_inclusive_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowBcast15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowBcast31, 0xc, 0xf, false);
+    return x;
+}
+
+// Value of lane 63 (the wave total after an inclusive scan).
+__device__ __forceinline__ int wave_last(int x)
+{
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
+// Sum over the wave, identical in every lane (xor butterfly: each step adds
+// the same two operands in every lane pair, so the result is one value).
+__device__ __forceinline__ float wave_sum(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, kWave);
+    return v;
+}
+
+__device__ __forceinline__ float wave_min(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fminf(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = fmaxf(v, __shfl_xor(v, m, kWave));
+    return v;
+}
+
+template <typename T> __device__ __forceinline__ T uniform(T v)
+{
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int64_t uniform64(int64_t v)
+{
+    const uint64_t u = static_cast<uint64_t>(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(u >> 32));
+    return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+
+}  // namespace ngd

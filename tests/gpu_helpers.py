@@ -1,0 +1,60 @@
+"""Shared helpers of the GPU parity tests (inputs, device upload, error
+measures).  Holds none of the method's arithmetic."""
+
+import numpy as np
+
+from paper_2405_20067_amd import inputs
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def normwise(got, want):
+    """max |got - want| / max |want| (the per-output error of the bench)."""
+    got = np.asarray(got, np.float64)
+    want = np.asarray(want, np.float64)
+    scale = np.abs(want).max()
+    if scale == 0:
+        return float(np.abs(got).max())
+    return float(np.abs(got - want).max() / scale)
+
+
+def case(n, k, q, layout=None, seed=1, near=0.5, sdiag=None, soff=None):
+    """A seeded mixture + queries of the given size; half the queries near
+    the components unless near=0."""
+    layout = layout or {4: "cube", 6: "pos3+dir3", 10: "pos3+nrm3+view3+rough1"}.get(n, "cube")
+    if sdiag is None:
+        sdiag = (5.0, 50.0) if n <= 4 else (10.0, 200.0)
+    if soff is None:
+        soff = 2.0 if n <= 4 else 5.0
+    mix = inputs.gen_mixture(n, k, layout, sdiag, soff, seed=seed)
+    n_near = int(round(q * near)) if k > 0 else 0
+    x = inputs.gen_queries(n, q - n_near, layout, seed=seed + 1)
+    if n_near:
+        xn = inputs.gen_near_queries([mix], n_near, seed=seed + 2)
+        x = np.concatenate([x, xn])
+        x = x[np.random.default_rng(seed + 3).permutation(q)]
+    proj = inputs.gen_projections(n, 16, seed=seed + 4)
+    return mix, np.ascontiguousarray(x, dtype=np.float32), proj
+
+
+def per_query_csr(c, q, tile):
+    """CSR (qoff, gidx) of each query's candidate Gaussians (caller order)."""
+    pos = np.empty(q, np.int64)
+    pos[c["perm"]] = np.arange(q)
+    tiles = pos // tile
+    counts = np.diff(c["tile_off"])[tiles]
+    qoff = np.zeros(q + 1, np.int64)
+    qoff[1:] = np.cumsum(counts)
+    gidx = np.empty(qoff[-1], np.int32)
+    for p in range(q):
+        t = tiles[p]
+        lst = c["cand"][c["tile_off"][t]:c["tile_off"][t + 1]]
+        gidx[qoff[p]:qoff[p + 1]] = c["gperm"][lst]
+    return qoff, gidx

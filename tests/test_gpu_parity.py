@@ -1,0 +1,253 @@
+"""Parity of the HIP path (through the C-ABI) against the float64 CPU oracle.
+
+Bars: integer outputs of the cull (permutations, offsets, candidate and
+transposed lists) bit-exact against the CPU cull; float32 values within the
+1e-4 normwise relative error of the target (max |x - x_ref| / max |x_ref|
+per output tensor), against the full oracle sum (culled pairs included) and
+against the oracle restricted to the same candidate pairs.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import case, dev, host, normwise, per_query_csr
+from paper_2405_20067_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _mixture(torch_cuda, mix):
+    from paper_2405_20067_amd import ngd
+    m = ngd.Mixture(mix["mean"].shape[1], mix["mean"].shape[0])
+    m.update(dev(mix["mean"]), dev(mix["factor"]), dev(mix["weight"]), dev(mix["colour"]))
+    return m
+
+
+def _params(tile=256, tau=1e-4, n_proj=16, key_proj=16, key_bits=2):
+    from paper_2405_20067_amd import ngd
+    p = ngd.default_params()
+    p.tile, p.tau, p.n_proj, p.key_proj, p.key_bits = tile, tau, n_proj, key_proj, key_bits
+    return p
+
+
+CULL_CASES = [
+    dict(n=4, k=300, q=3000, tile=256),
+    dict(n=6, k=777, q=5000, tile=100),
+    dict(n=10, k=1500, q=4100, tile=256),
+    dict(n=3, k=64, q=70, tile=1),
+    dict(n=10, k=65, q=257, tile=64),
+    dict(n=2, k=130, q=1000, tile=1024, key_bits=3, key_proj=10),
+]
+
+
+def _ids(c):
+    return "-".join(f"{k}{v}" for k, v in c.items())
+
+
+@pytest.mark.parametrize("cfg", CULL_CASES, ids=_ids)
+def test_cull_bit_exact(torch_cuda, cfg):
+    from paper_2405_20067_amd import ngd
+    n, k, q = cfg["n"], cfg["k"], cfg["q"]
+    key_bits = cfg.get("key_bits", 2)
+    key_proj = cfg.get("key_proj", 16)
+    mix, x, proj = case(n, k, q, seed=n * 7 + k)
+    m = _mixture(torch_cuda, mix)
+    xd = dev(x)
+    c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"], key_bits=key_bits,
+                                               key_proj=key_proj))
+    got = c.export()
+    want = oracle.cull(mix["mean"], mix["factor"], x, proj, tau=1e-4, tile=cfg["tile"],
+                       key_proj=key_proj, key_bits=key_bits)
+    assert got["ntiles"] == want["ntiles"]
+    assert got["total"] == want["total"]
+    for key in ("perm", "gperm", "tile_off", "cand", "g_off", "g_tiles", "tile_lo", "tile_hi"):
+        np.testing.assert_array_equal(got[key], want[key], err_msg=key)
+    lens = np.diff(want["tile_off"])
+    assert got["max_per_tile"] == (lens.max() if lens.size else 0)
+
+
+@pytest.mark.parametrize("cfg", CULL_CASES[:3] + CULL_CASES[4:], ids=_ids)
+def test_culled_forward_matches_oracle(torch_cuda, cfg):
+    from paper_2405_20067_amd import ngd
+    n, k, q = cfg["n"], cfg["k"], cfg["q"]
+    mix, x, proj = case(n, k, q, seed=n * 7 + k)
+    m = _mixture(torch_cuda, mix)
+    xd = dev(x)
+    c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"]))
+    f = host(ngd.eval_mixture(m, c, xd))
+    full = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x)
+    assert normwise(f, full) <= TOL_FP32
+    # arithmetic error alone: the oracle over exactly the candidate pairs
+    exp = c.export()
+    qoff, gidx = per_query_csr(exp, q, cfg["tile"])
+    restricted = oracle.eval_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x,
+                                   qoff, gidx)
+    assert normwise(f, restricted) <= TOL_FP32
+    # cull error alone is bounded by tau * sum over culled pairs of alpha c
+    ac = mix["weight"].astype(np.float64)[:, None] * mix["colour"]
+    bound = 1e-4 * (ac.sum(0)[None, :] - np.add.reduceat(ac[gidx], qoff[:-1], axis=0)
+                    * (np.diff(qoff) > 0)[:, None])
+    assert np.all(np.abs(full - restricted) <= bound + 1e-300)
+
+
+def test_dense_forward_4d_full_size(torch_cuda):
+    """The 4-D workload at its full size: K=256, 65,536 uniform queries."""
+    from paper_2405_20067_amd import ngd
+    w = inputs.WORKLOADS["4d-dense"]
+    mix = inputs.workload_mixture(w)
+    x = inputs.gen_workload_queries(w)
+    m = _mixture(torch_cuda, mix)
+    f = host(ngd.eval_mixture(m, None, dev(x)))
+    want = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x)
+    assert normwise(f, want) <= TOL_FP32
+    big = np.abs(want) > 1e-3 * np.abs(want).max()
+    assert np.max(np.abs(f - want)[big] / np.abs(want)[big]) < 1e-3
+
+
+@pytest.mark.parametrize("cfg", [dict(n=4, k=200, q=2000), dict(n=6, k=400, q=3000),
+                                 dict(n=10, k=600, q=2600)], ids=_ids)
+def test_dense_backward_matches_oracle(torch_cuda, cfg):
+    from paper_2405_20067_amd import ngd
+    n, k, q = cfg["n"], cfg["k"], cfg["q"]
+    mix, x, _ = case(n, k, q, seed=3 * n + 1)
+    g = inputs.gen_grad_out(q, seed=n)
+    m = _mixture(torch_cuda, mix)
+    got = [host(t) for t in ngd.eval_backward(m, None, dev(x), dev(g))]
+    want = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g)
+    for name, a, b in zip(("mean", "factor", "weight", "colour"), got, want):
+        assert normwise(a, b) <= TOL_FP32, name
+
+
+@pytest.mark.parametrize("cfg", [CULL_CASES[0], CULL_CASES[1], CULL_CASES[2], CULL_CASES[4]],
+                         ids=_ids)
+def test_culled_backward_matches_oracle(torch_cuda, cfg):
+    from paper_2405_20067_amd import ngd
+    n, k, q = cfg["n"], cfg["k"], cfg["q"]
+    mix, x, proj = case(n, k, q, seed=n * 7 + k)
+    g = inputs.gen_grad_out(q, seed=k)
+    m = _mixture(torch_cuda, mix)
+    xd = dev(x)
+    c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"]))
+    got = [host(t) for t in ngd.eval_backward(m, c, xd, dev(g))]
+    want = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g)
+    for name, a, b in zip(("mean", "factor", "weight", "colour"), got, want):
+        assert normwise(a, b) <= TOL_FP32, name
+
+
+def test_repeat_runs_are_bitwise_identical(torch_cuda):
+    from paper_2405_20067_amd import ngd
+    mix, x, proj = case(10, 2000, 6000, seed=5)
+    g = inputs.gen_grad_out(6000, seed=5)
+    m = _mixture(torch_cuda, mix)
+    xd, gd = dev(x), dev(g)
+    runs = []
+    for _ in range(2):
+        c = ngd.Cull().build(m, xd, proj, _params())
+        f = host(ngd.eval_mixture(m, c, xd))
+        grads = [host(t) for t in ngd.eval_backward(m, c, xd, gd)]
+        runs.append([f] + grads)
+    for a, b in zip(*runs):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_rebuild_in_place_and_stale_detection(torch_cuda):
+    from paper_2405_20067_amd import ngd
+    mix, x, proj = case(6, 300, 1500, seed=9)
+    m = _mixture(torch_cuda, mix)
+    xd = dev(x)
+    c = ngd.Cull().build(m, xd, proj, _params())
+    h0 = c.handle.value
+    f0 = host(ngd.eval_mixture(m, c, xd))
+    # a new parameter upload makes the cull stale
+    m.update(dev(mix["mean"]), dev(mix["factor"]), dev(mix["weight"]), dev(mix["colour"]))
+    with pytest.raises(ngd.NgdError) as ei:
+        ngd.eval_mixture(m, c, xd)
+    assert ei.value.code == ngd.E_STALE
+    # another query buffer is stale too
+    c.build(m, xd, proj, _params())
+    assert c.handle.value == h0
+    with pytest.raises(ngd.NgdError) as ei:
+        ngd.eval_mixture(m, c, dev(x))
+    assert ei.value.code == ngd.E_STALE
+    np.testing.assert_array_equal(host(ngd.eval_mixture(m, c, xd)), f0)
+    # a smaller rebuild in the same handle
+    c.build(m, xd[:700], proj, _params())
+    f1 = host(ngd.eval_mixture(m, c, xd[:700]))
+    want = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x[:700])
+    assert normwise(f1, want) <= TOL_FP32
+
+
+def test_validate_flags_singular_factor(torch_cuda):
+    from paper_2405_20067_amd import ngd
+    mix, _, _ = case(4, 50, 10, seed=2)
+    m = _mixture(torch_cuda, mix)
+    m.validate()
+    bad = mix["factor"].copy()
+    bad[7, 2] = 0.0          # L_11 of Gaussian 7
+    m.update(dev(mix["mean"]), dev(bad), dev(mix["weight"]), dev(mix["colour"]))
+    with pytest.raises(ngd.NgdError) as ei:
+        m.validate()
+    assert ei.value.code == ngd.E_SINGULAR
+    nanw = mix["weight"].copy()
+    nanw[3] = np.nan
+    m.update(dev(mix["mean"]), dev(mix["factor"]), dev(nanw), dev(mix["colour"]))
+    with pytest.raises(ngd.NgdError):
+        m.validate()
+
+
+def test_edge_cases(torch_cuda):
+    from paper_2405_20067_amd import ngd
+    import torch
+    mix, x, proj = case(4, 40, 300, seed=4)
+    m = _mixture(torch_cuda, mix)
+    # no queries
+    empty = torch.empty((0, 4), dtype=torch.float32, device="cuda")
+    c = ngd.Cull().build(m, empty, proj, _params())
+    assert c.stats() == dict(total=0, max_per_tile=0, ntiles=0)
+    assert ngd.eval_mixture(m, c, empty).shape == (0, 3)
+    gm, gf, gw, gc = ngd.eval_backward(m, c, empty, torch.empty((0, 3), device="cuda"))
+    assert float(gm.abs().max()) == 0.0 and float(gw.abs().max()) == 0.0
+    # one query
+    xd1 = dev(x[:1])
+    c1 = ngd.Cull().build(m, xd1, proj, _params())
+    f1 = host(ngd.eval_mixture(m, c1, xd1))
+    want = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x[:1])
+    assert normwise(f1, want) <= TOL_FP32
+    # queries far from every Gaussian: everything culled, f = 0, grads = 0
+    far = dev(x + np.float32(50.0))
+    cf = ngd.Cull().build(m, far, proj, _params())
+    assert cf.stats()["total"] == 0
+    assert float(ngd.eval_mixture(m, cf, far).abs().max()) == 0.0
+    grads = ngd.eval_backward(m, cf, far, dev(inputs.gen_grad_out(300)))
+    assert all(float(t.abs().max()) == 0.0 for t in grads)
+    # no Gaussians
+    m0 = ngd.Mixture(4, 0)
+    z = torch.empty((0,), dtype=torch.float32, device="cuda")
+    m0.update(z, z, z, z)
+    xd = dev(x)
+    c0 = ngd.Cull().build(m0, xd, proj, _params())
+    assert float(ngd.eval_mixture(m0, c0, xd).abs().max()) == 0.0
+    assert float(ngd.eval_mixture(m0, None, xd).abs().max()) == 0.0
+
+
+def test_l2_loss(torch_cuda):
+    from paper_2405_20067_amd import ngd
+    rng = np.random.default_rng(0)
+    for q in (1, 1000, 300001):
+        f = rng.standard_normal((q, 3)).astype(np.float32)
+        t = rng.standard_normal((q, 3)).astype(np.float32)
+        loss, grad = ngd.l2_loss(dev(f), dev(t))
+        d = f.astype(np.float64) - t
+        assert float(host(loss)[0]) == pytest.approx(np.mean(d * d), rel=1e-6)
+        np.testing.assert_allclose(host(grad), 2 * d / d.size, rtol=1e-6, atol=0)
