@@ -1,0 +1,225 @@
+"""Benchmark of the culled N-D Gaussian mixture fwd+bwd step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 3] [--workload 10d-fwdbwd]
+
+One step is the whole hot path on one batch, every stage a libngd call:
+  update (float64 inversion of every factor) -> cull build (projections,
+  sort, tiles, interval test, candidate lists) -> forward -> L2 loss and its
+  gradient -> backward (gradients of mean, factor, weight, colour).
+Inputs are resident in HBM before timing starts.  `value` is dense-equivalent
+Gaussian-query evaluations per second of the step: Q*K / (time per step).
+
+Prints one JSON line (rank 0).  Also times the plain float32 dense direct-sum
+kernel (forward and backward, no culling) once for the speedup, and the
+float64 CPU oracle on a bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+FP32_VALU_PEAK_TFLOPS = 157.3   # published dense FP32 vector peak (packed)
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def setup(workload: str):
+    import torch
+    from paper_2405_20067_amd import inputs
+    w = inputs.WORKLOADS[workload]
+    t0 = time.time()
+    mix = inputs.workload_mixture(w)
+    tgt = inputs.workload_mixture(w, k=w.k_target, seed=inputs.SEED_TARGET) if w.k_target else None
+    x = inputs.gen_workload_queries(w, mixtures=[m for m in (mix, tgt) if m is not None])
+    proj = inputs.gen_projections(w.n, 16, inputs.SEED_PROJ)
+    log(f"generated {workload}: n={w.n} k={w.k} q={w.q} in {time.time() - t0:.1f}s")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    dev = dict(mean=d(mix["mean"]), factor=d(mix["factor"]), weight=d(mix["weight"]),
+               colour=d(mix["colour"]), x=d(x))
+    return w, mix, tgt, x, proj, dev
+
+
+def targets(w, tgt, dev, proj):
+    """Values of the hidden target mixture at the queries (workload input,
+    computed once before timing with the library's culled forward)."""
+    import torch
+    from paper_2405_20067_amd import ngd
+    if tgt is None:
+        return torch.zeros((w.q, 3), dtype=torch.float32, device="cuda")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    mt = ngd.Mixture(w.n, tgt["mean"].shape[0])
+    mt.update(d(tgt["mean"]), d(tgt["factor"]), d(tgt["weight"]), d(tgt["colour"]))
+    ct = ngd.Cull().build(mt, dev["x"], proj)
+    t = ngd.eval_mixture(mt, ct, dev["x"])
+    torch.cuda.synchronize()
+    return t
+
+
+def cpu_baseline(w, mix, x, budget_s: float):
+    """The float64 oracle, fwd (direct sum over all K) + bwd (gradient of all
+    K Gaussians) on a sample of queries, timed on this host."""
+    import oracle
+    from paper_2405_20067_amd import inputs
+    rng = np.random.default_rng(12345)
+    g_all = inputs.gen_grad_out(w.q, seed=77)
+    def run(nq):
+        idx = rng.choice(w.q, nq, replace=False)
+        xs, gs = x[idx], g_all[idx]
+        t0 = time.perf_counter()
+        oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], xs)
+        t1 = time.perf_counter()
+        oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], xs, gs)
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1
+    probe = 16
+    a, b = run(probe)
+    nq = int(max(probe, min(w.q, probe * budget_s / max(a + b, 1e-6))))
+    tf, tb = run(nq)
+    pairs = nq * w.k
+    return dict(value=pairs / (tf + tb), unit="Gaussian-query evals/s",
+                cores=int(oracle.threads()), kind="oracle",
+                sample=f"{nq} of the {w.q} queries (seeded), every one of the {w.k} "
+                       f"Gaussians: float64 forward sum ({tf:.1f}s) + gradient of all "
+                       f"Gaussians over those queries ({tb:.1f}s)",
+                fwd_s=tf, bwd_s=tb, pairs=pairs)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="10d-fwdbwd")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2405_20067_amd import ngd
+    torch.cuda.set_device(0)
+    ngd.lib()
+    w, mix, tgt, x, proj, dev = setup(args.workload)
+    target = targets(w, tgt, dev, proj) if w.backward else None
+
+    m = ngd.Mixture(w.n, w.k)
+    cull = ngd.Cull()
+    params = ngd.default_params()
+    grads = (torch.empty((w.k, w.n), device="cuda"),
+             torch.empty((w.k, w.n * (w.n + 1) // 2), device="cuda"),
+             torch.empty((w.k,), device="cuda"), torch.empty((w.k, 3), device="cuda"))
+    f = torch.empty((w.q, 3), device="cuda")
+    loss = torch.empty((1,), device="cuda")
+    gout = torch.empty((w.q, 3), device="cuda")
+    stages = ["update", "cull_build", "forward", "loss", "backward"]
+
+    def step(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        m.update(dev["mean"], dev["factor"], dev["weight"], dev["colour"])
+        mark(1)
+        if w.culled:
+            cull.build(m, dev["x"], proj, params)
+        mark(2)
+        c = cull if w.culled else None
+        ngd.eval_mixture(m, c, dev["x"], out=f)
+        mark(3)
+        if w.backward:
+            ngd.l2_loss(f, target, loss=loss, grad=gout)
+        mark(4)
+        if w.backward:
+            ngd.eval_backward(m, c, dev["x"], gout, grads=grads)
+        mark(5)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(evs[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_stage = {s: [] for s in stages}
+    for e in evs:
+        for j, s in enumerate(stages):
+            per_stage[s].append(e[j].elapsed_time(e[j + 1]))
+    stage_ms = {s: float(np.median(v)) for s, v in per_stage.items()}
+    ms_step = wall * 1e3 / args.steps
+    value = w.q * w.k / (ms_step * 1e-3)
+
+    st = cull.stats() if w.culled else dict(total=w.k, ntiles=1, max_per_tile=w.k)
+    tile = params.tile
+    cand_pairs = st["total"] * tile if w.culled else w.q * w.k
+    log(f"step {ms_step:.3f} ms; stages " +
+        ", ".join(f"{s} {v:.3f}" for s, v in stage_ms.items()) +
+        f"; candidates {st['total']} ({st['total'] / max(st['ntiles'] * w.k, 1):.4%} of "
+        f"tile x Gaussian pairs), max/tile {st['max_per_tile']}")
+
+    dense = None
+    if not args.no_dense:
+        # the plain float32 direct-sum kernels, no culling, same inputs
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        e[0].record()
+        ngd.eval_mixture(m, None, dev["x"], out=f)
+        e[1].record()
+        if w.backward:
+            ngd.eval_backward(m, None, dev["x"], gout, grads=grads)
+        e[2].record()
+        torch.cuda.synchronize()
+        dense = dict(forward_ms=e[0].elapsed_time(e[1]), backward_ms=e[1].elapsed_time(e[2]))
+        dense["speedup_vs_dense"] = ((dense["forward_ms"] + dense["backward_ms"]) /
+                                     (stage_ms["forward"] + stage_ms["backward"]))
+        log(f"dense fp32 direct sum: fwd {dense['forward_ms']:.1f} ms, "
+            f"bwd {dense['backward_ms']:.1f} ms")
+
+    fwd_pairs_s = cand_pairs / (stage_ms["forward"] * 1e-3)
+    roofline = dict(
+        bound="alu", kernel="k_eval_culled (forward)",
+        achieved=None, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=None, traffic=None)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle ...")
+        cpu = cpu_baseline(w, mix, x, args.cpu_seconds)
+
+    out = dict(
+        metric="Gaussian-query evals/sec, culled fwd+bwd 10-D",
+        value=value, unit="Gaussian-query evals/s (dense-equivalent Q*K per step time)",
+        n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
+        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        data="synthetic",
+        config=dict(workload=w.name, description=w.description, n=w.n, k=w.k, q=w.q,
+                    k_target=w.k_target, near_frac=w.near_frac, n_proj=params.n_proj,
+                    tau=params.tau, tile=params.tile, key_proj=params.key_proj,
+                    key_bits=params.key_bits),
+        stages_ms=stage_ms,
+        cull=dict(candidates=st["total"], ntiles=st["ntiles"], max_per_tile=st["max_per_tile"],
+                  candidate_pairs=cand_pairs,
+                  survivor_fraction=st["total"] / max(st["ntiles"] * w.k, 1)),
+        candidate_pairs_per_s_forward=fwd_pairs_s,
+        dense_fp32=dense, roofline=roofline, cpu_baseline=cpu)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

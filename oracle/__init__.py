@@ -28,6 +28,7 @@ __all__ = [
     "gaussian",
     "cull",
     "kappa2_from_tau",
+    "threads",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -51,6 +52,8 @@ def lib():
         _build.build()
     L = ctypes.CDLL(_LIB_PATH)
     i, i64, p = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
+    L.ngd_oracle_threads.argtypes = []
+    L.ngd_oracle_threads.restype = ctypes.c_int
     L.ngd_oracle_gaussian.argtypes = [i, _f64p, _f64p, _f64p]
     L.ngd_oracle_gaussian.restype = ctypes.c_double
     L.ngd_oracle_eval.argtypes = [i, i64, _f64p, _f64p, _f64p, _f64p, i64, _f64p, _f64p]
@@ -98,6 +101,11 @@ def _check_mix(mean, factor, weight, colour):
     weight = _d(weight).reshape(k)
     colour = _d(colour).reshape(k, 3)
     return n, k, mean, factor, weight, colour
+
+
+def threads() -> int:
+    """OpenMP threads the oracle uses."""
+    return lib().ngd_oracle_threads()
 
 
 def gaussian(mean, factor, x) -> float:

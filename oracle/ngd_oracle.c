@@ -39,6 +39,20 @@
 
 #define ORACLE_MAX_N 32
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the oracle's parallel loops use. */
+int ngd_oracle_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 static inline int64_t tri_idx(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
 /* Solve L y = d (forward substitution), return y^T y. */

@@ -8,13 +8,16 @@
 //   dl/dL     = tril(S^T B2),                   B2 = sum_x w y y^T
 // (dl/dm = sum w z and dl/dL = tril(sum w z y^T) with z = S^T y.)
 //
-// Atomics-free, Gaussian-major: one wave owns one Gaussian and walks the
-// tiles whose candidate list holds it, 64 queries per step; the wave keeps
-// its per-lane partial moments in registers (B1: n, B2: n(n+1)/2, H: 3) and
-// reduces them across lanes once at the end, in a fixed order.  Exp terms
-// are recomputed, not stored.  Skipping uses the same two-stage certified
-// bound and threshold as the forward kernel, so forward and backward sum
-// over the same pairs.
+// Atomics-free and Gaussian-major.  Culled: a work item is one Gaussian and
+// at most kItemTiles of the tiles whose candidate list holds it; one wave
+// walks those tiles 64 queries at a time, keeping per-lane partial moments
+// in registers (B1: n, B2: n(n+1)/2, H: 3), reduces them across lanes once
+// and writes them to the item's slot.  k_backward_finalize then adds each
+// Gaussian's items in item order and applies S^T.  Exp terms are recomputed,
+// not stored.  Pairs are dropped with the same staged, certified test and
+// threshold as the forward kernel (same operations in the same order), so
+// forward and backward sum over the same pairs.  Dense: one wave per
+// Gaussian over all queries, no dropping.
 #include "ngd_internal.hpp"
 #include "wave.hpp"
 
@@ -23,6 +26,7 @@ namespace {
 
 constexpr int kBwdThreads = 256;
 constexpr int kWavesPerBlock = kBwdThreads / kWave;
+static_assert(kItemTiles <= kWave, "an item's tile list must fit one wave");
 
 template <int N> constexpr int first_stage_dims() { return N >= 4 ? 4 : N; }
 
@@ -179,6 +183,193 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(
     g_colour[gi * 3 + 2] = alpha * h2;
 }
 
+// ---- culled: work items (Gaussian, up to kItemTiles of its tiles) ---------
+template <int N> struct BwdLayout {
+    static constexpr int T = N * (N + 1) / 2;
+    static constexpr int R = (N + T + 7 + 3) / 4 * 4;
+    static constexpr int NM = N + T + 3;             // B1 | B2 | H
+    static constexpr int K1 = N < 3 ? N : 3;        // stage boundaries
+    static constexpr int K2 = N < 6 ? N : 6;
+};
+
+// y rows [R0, R1) and msq for one lane; d[a] = x[a] - m[a].
+template <int N, int R0, int R1>
+__device__ __forceinline__ void brows(const float *__restrict__ r, const float (&x)[N],
+                                      float (&d)[N], float (&y)[N], float &msq)
+{
+#pragma unroll
+    for (int row = R0; row < R1; ++row) {
+        d[row] = x[row] - r[row];
+        const float *srow = r + N + row * (row + 1) / 2;
+        float acc = srow[0] * d[0];
+#pragma unroll
+        for (int j = 1; j <= row; ++j) acc = fmaf(srow[j], d[j], acc);
+        y[row] = acc;
+        msq = fmaf(acc, acc, msq);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kBwdThreads) void k_backward_items(
+    int64_t k, int64_t q, int tile, const float *__restrict__ grec,
+    const float *__restrict__ qs, const float *__restrict__ gs,
+    const int64_t *__restrict__ g_off, const int32_t *__restrict__ g_tiles,
+    const int64_t *__restrict__ gitem_off, const int32_t *__restrict__ gitem_g, float skip,
+    float *__restrict__ gpart, int32_t *__restrict__ gflag)
+{
+    using Lay = BwdLayout<N>;
+    constexpr int T = Lay::T;
+    const int lane = lane_id();
+    const int64_t it = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
+    if (it >= uniform64(gitem_off[k])) return;
+    const int64_t g = uniform(gitem_g[it]);
+    const int64_t j0 = uniform64(gitem_off[g]);
+    const int64_t t0 = uniform64(g_off[g]), t1 = uniform64(g_off[g + 1]);
+    const int64_t e0 = t0 + (it - j0) * kItemTiles;
+    const int64_t e1 = (e0 + kItemTiles < t1) ? e0 + kItemTiles : t1;
+    const float *__restrict__ r = grec + g * Lay::R;
+    constexpr int AL = N + T + 3, CO = N + T + 4;
+    const float alpha = r[AL], c0 = r[CO], c1 = r[CO + 1], c2 = r[CO + 2];
+
+    float b1[N], b2[T], h0 = 0.0f, h1 = 0.0f, h2 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < N; ++a) b1[a] = 0.0f;
+#pragma unroll
+    for (int e = 0; e < T; ++e) b2[e] = 0.0f;
+    bool any = false;
+
+    // iterations: (tile e, group of 64 queries gq); coordinates of the next
+    // iteration's first K2 dimensions are loaded one iteration ahead
+    const int ngrp = (tile + kWave - 1) / kWave;
+    const int64_t iters = (e1 - e0) * ngrp;
+    float xn[Lay::K2];
+    int64_t pn = 0;
+    bool vn = false;
+    // the item's tile list (at most kItemTiles <= 64 entries), one per lane
+    const int tiles_v = (e0 + lane < e1) ? g_tiles[e0 + lane] : 0;
+    auto fetch = [&](int64_t i) {
+        const int64_t tt = __builtin_amdgcn_readlane(tiles_v, int(i / ngrp));
+        const int sidx = int(i % ngrp) * kWave + lane;
+        pn = tt * tile + sidx;
+        vn = (sidx < tile) && (pn < q);
+#pragma unroll
+        for (int a = 0; a < Lay::K2; ++a) xn[a] = vn ? qs[a * q + pn] : 0.0f;
+    };
+    if (iters > 0) fetch(0);
+    for (int64_t i = 0; i < iters; ++i) {
+        float x[N], d[N], y[N];
+#pragma unroll
+        for (int a = 0; a < Lay::K2; ++a) x[a] = xn[a];
+        const int64_t p = pn;
+        const bool valid = vn;
+        if (i + 1 < iters) fetch(i + 1);
+        float msq = 0.0f;
+        brows<N, 0, Lay::K1>(r, x, d, y, msq);
+        if constexpr (Lay::K1 < N) {
+            if (ballot(valid && msq <= skip) == 0) continue;
+        }
+        brows<N, Lay::K1, Lay::K2>(r, x, d, y, msq);
+        if constexpr (Lay::K2 < N && Lay::K1 < Lay::K2) {
+            if (ballot(valid && msq <= skip) == 0) continue;
+        }
+#pragma unroll
+        for (int a = Lay::K2; a < N; ++a) x[a] = valid ? qs[a * q + p] : 0.0f;
+        brows<N, Lay::K2, N>(r, x, d, y, msq);
+        if (ballot(valid && msq <= skip) == 0) continue;
+        any = true;
+        const float G = valid ? __builtin_amdgcn_exp2f(-msq) : 0.0f;
+        const float g0v = valid ? gs[p] : 0.0f;
+        const float g1v = valid ? gs[q + p] : 0.0f;
+        const float g2v = valid ? gs[2 * q + p] : 0.0f;
+        const float sdot = fmaf(g2v, c2, fmaf(g1v, c1, g0v * c0));
+        const float w = alpha * G * sdot;
+        h0 = fmaf(G, g0v, h0);
+        h1 = fmaf(G, g1v, h1);
+        h2 = fmaf(G, g2v, h2);
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const float wy = w * y[a];
+            b1[a] += wy;
+#pragma unroll
+            for (int b = 0; b <= a; ++b)
+                b2[a * (a + 1) / 2 + b] = fmaf(wy, y[b], b2[a * (a + 1) / 2 + b]);
+        }
+    }
+    if (!any) {
+        if (lane == 0) gflag[it] = 0;
+        return;
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) b1[a] = wave_sum(b1[a]);
+#pragma unroll
+    for (int e = 0; e < T; ++e) b2[e] = wave_sum(b2[e]);
+    h0 = wave_sum(h0);
+    h1 = wave_sum(h1);
+    h2 = wave_sum(h2);
+    if (lane != 0) return;
+    float *out = gpart + it * Lay::NM;
+#pragma unroll
+    for (int a = 0; a < N; ++a) out[a] = b1[a];
+#pragma unroll
+    for (int e = 0; e < T; ++e) out[N + e] = b2[e];
+    out[N + T + 0] = h0;
+    out[N + T + 1] = h1;
+    out[N + T + 2] = h2;
+    gflag[it] = 1;
+}
+
+// Per sorted Gaussian: sum its items' moments in item order, then
+//   dm = S'^T B1 / c, dL = tril(S'^T B2) / c^1.5, dalpha = c . H, dc = alpha H.
+template <int N>
+__global__ __launch_bounds__(kBwdThreads) void k_backward_finalize(
+    int64_t k, const float *__restrict__ grec, const int64_t *__restrict__ gitem_off,
+    const float *__restrict__ gpart, const int32_t *__restrict__ gflag,
+    const int32_t *__restrict__ gperm, float *__restrict__ g_mean,
+    float *__restrict__ g_factor, float *__restrict__ g_weight, float *__restrict__ g_colour)
+{
+    using Lay = BwdLayout<N>;
+    constexpr int T = Lay::T, NM = Lay::NM;
+    const int64_t g = int64_t(blockIdx.x) * kBwdThreads + threadIdx.x;
+    if (g >= k) return;
+    float acc[NM];
+#pragma unroll
+    for (int e = 0; e < NM; ++e) acc[e] = 0.0f;
+    for (int64_t i = gitem_off[g]; i < gitem_off[g + 1]; ++i) {
+        if (!gflag[i]) continue;
+        const float *pp = gpart + i * NM;
+#pragma unroll
+        for (int e = 0; e < NM; ++e) acc[e] += pp[e];
+    }
+    const float *r = grec + g * Lay::R;
+    const int64_t gi = gperm[g];
+    const float inv_c = float(1.0 / kHalfLog2e);
+    const float inv_c15 = float(1.0 / (kHalfLog2e * kSqrtHalfLog2e));
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        float s = 0.0f;
+#pragma unroll
+        for (int kk = a; kk < N; ++kk) s = fmaf(r[N + kk * (kk + 1) / 2 + a], acc[kk], s);
+        g_mean[gi * N + a] = s * inv_c;
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+            float s = 0.0f;
+#pragma unroll
+            for (int kk = a; kk < N; ++kk)
+                s = fmaf(r[N + kk * (kk + 1) / 2 + a], acc[N + kk * (kk + 1) / 2 + b], s);
+            g_factor[gi * T + a * (a + 1) / 2 + b] = s * inv_c15;
+        }
+    }
+    const float alpha = r[N + T + 3];
+    const float h0 = acc[N + T], h1 = acc[N + T + 1], h2 = acc[N + T + 2];
+    g_weight[gi] = fmaf(r[N + T + 6], h2, fmaf(r[N + T + 5], h1, r[N + T + 4] * h0));
+    g_colour[gi * 3 + 0] = alpha * h0;
+    g_colour[gi * 3 + 1] = alpha * h1;
+    g_colour[gi * 3 + 2] = alpha * h2;
+}
+
 __global__ __launch_bounds__(256) void k_gather_grad(int64_t q, const int32_t *__restrict__ perm,
                                                      const float *__restrict__ grad_out,
                                                      float *__restrict__ gs)
@@ -212,11 +403,18 @@ hipError_t culled_n(const ngd_mixture *mix, ngd_cull *c, const float *grad_out, 
             c->q, c->perm.as<int32_t>(), grad_out, c->gs.as<float>());
     }
     const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
-    const unsigned blocks = unsigned((mix->k + kWavesPerBlock - 1) / kWavesPerBlock);
-    k_backward<N, true><<<blocks, kBwdThreads, 0, s>>>(
-        mix->k, c->q, c->params.tile, c->grec.as<float>(), c->qs.as<float>(), c->gs.as<float>(),
-        c->g_off.as<int64_t>(), c->g_tiles.as<int32_t>(), c->gperm.as<int32_t>(), skip, gm, gf,
-        gw, gc);
+    if (c->gitems_cap > 0) {
+        const unsigned blocks = unsigned((c->gitems_cap + kWavesPerBlock - 1) / kWavesPerBlock);
+        k_backward_items<N><<<blocks, kBwdThreads, 0, s>>>(
+            mix->k, c->q, c->params.tile, c->grec.as<float>(), c->qs.as<float>(),
+            c->gs.as<float>(), c->g_off.as<int64_t>(), c->g_tiles.as<int32_t>(),
+            c->gitem_off.as<int64_t>(), c->gitem_g.as<int32_t>(), skip, c->gpart.as<float>(),
+            c->gflag.as<int32_t>());
+    }
+    const unsigned fb = unsigned((mix->k + kBwdThreads - 1) / kBwdThreads);
+    k_backward_finalize<N><<<fb, kBwdThreads, 0, s>>>(
+        mix->k, c->grec.as<float>(), c->gitem_off.as<int64_t>(), c->gpart.as<float>(),
+        c->gflag.as<int32_t>(), c->gperm.as<int32_t>(), gm, gf, gw, gc);
     return hipGetLastError();
 }
 

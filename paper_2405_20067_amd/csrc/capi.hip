@@ -213,7 +213,8 @@ static void cull_release(ngd_cull *c)
                       &c->gs,      &c->tile_lo,  &c->tile_hi,    &c->grec,    &c->g_mr_s,
                       &c->g_thr_s, &c->masks,    &c->seg_cnt,    &c->tile_cnt, &c->tile_off,
                       &c->cand,    &c->g_cnt,    &c->g_off,      &c->g_tiles, &c->scan_tmp,
-                      &c->stats};
+                      &c->stats,   &c->item_cnt, &c->item_off,   &c->item_tile, &c->fpart,
+                      &c->gitem_cnt, &c->gitem_off, &c->gitem_g, &c->gpart,   &c->gflag};
     for (DevBuf *b : bufs) b->release();
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     c->stats_host = nullptr;
@@ -249,7 +250,7 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (fresh) {
         c = new (std::nothrow) ngd_cull();
         if (!c) return fail(NGD_E_NOMEM, "ngd_cull_build: host allocation failed");
-        if (hipHostMalloc(reinterpret_cast<void **>(&c->stats_host), 2 * sizeof(int64_t),
+        if (hipHostMalloc(reinterpret_cast<void **>(&c->stats_host), 3 * sizeof(int64_t),
                           hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             delete c;
@@ -293,15 +294,26 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (e == hipSuccess)
         e = hipMemcpyAsync(&c->stats_host[1], c->stats.as<int64_t>() + 1, sizeof(int64_t),
                            hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&c->stats_host[2], c->item_off.as<int64_t>() + c->ntiles,
+                           sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (list sizes)"));
     c->total = c->stats_host[0];
     c->max_per_tile = (c->ntiles > 0 && c->k > 0) ? c->stats_host[1] : 0;
+    c->nitems = c->stats_host[2];
+    c->gitems_cap = c->k + (c->total + kItemTiles - 1) / kItemTiles;
     if (c->total >= (int64_t(1) << 31))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: %lld candidates exceed 2^31",
                          (long long)c->total));
+    const size_t nm = size_t(c->n + tri(c->n) + 3);
     if (!c->cand.ensure(sizeof(int32_t) * size_t(c->total)) ||
-        !c->g_tiles.ensure(sizeof(int32_t) * size_t(c->total)))
+        !c->g_tiles.ensure(sizeof(int32_t) * size_t(c->total)) ||
+        !c->item_tile.ensure(sizeof(int32_t) * size_t(c->nitems)) ||
+        !c->fpart.ensure(sizeof(float) * 3 * size_t(c->nitems) * size_t(p->tile)) ||
+        !c->gitem_g.ensure(sizeof(int32_t) * size_t(c->gitems_cap)) ||
+        !c->gpart.ensure(sizeof(float) * nm * size_t(c->gitems_cap)) ||
+        !c->gflag.ensure(sizeof(int32_t) * size_t(c->gitems_cap)))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: candidate list allocation failed"));
     e = launch_cull_build_lists(c, s);
     if (e == hipSuccess) e = launch_cull_build_transpose(c, s);
@@ -385,7 +397,7 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
     }
     if (q == 0) return NGD_OK;
     hipError_t e;
-    if (mix->k == 0 || (cull && cull->total == 0)) {
+    if (mix->k == 0 || (cull && cull->nitems == 0)) {
         e = launch_zero_f32(out, 3 * q, S(stream));
     } else if (cull) {
         e = launch_eval_culled(mix, cull, out, S(stream));

@@ -113,17 +113,30 @@ __global__ __launch_bounds__(kThreads) void k_query_proj(int64_t q, int P,
     }
 }
 
-// qrange = [lo (P) | hi (P) | scale (P)]
+// qrange = [lo (P) | hi (P) | scale (P)]; one block per projection.
 __global__ __launch_bounds__(kThreads) void k_range_final(int64_t nparts, int P, int key_bits,
                                                           const float *__restrict__ part,
                                                           float *__restrict__ qrange)
 {
-    const int j = threadIdx.x;
-    if (j >= P) return;
+    __shared__ float slo[kThreads / kWave], shi[kThreads / kWave];
+    const int j = blockIdx.x;
     float lo = INFINITY, hi = -INFINITY;
-    for (int64_t b = 0; b < nparts; ++b) {
+    for (int64_t b = threadIdx.x; b < nparts; b += kThreads) {
         lo = fminf(lo, part[(b * P + j) * 2 + 0]);
         hi = fmaxf(hi, part[(b * P + j) * 2 + 1]);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane_id() == 0) {
+        slo[threadIdx.x / kWave] = lo;
+        shi[threadIdx.x / kWave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int i = 0; i < kThreads / kWave; ++i) {
+        lo = fminf(lo, slo[i]);
+        hi = fmaxf(hi, shi[i]);
     }
     qrange[j] = lo;
     qrange[P + j] = hi;
@@ -417,6 +430,9 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
     }
 }
 
+// Transposed lists.  One wave per chunk of 64 sorted Gaussians (lane =
+// Gaussian); the chunk's masks are read 64 tiles at a time (lane = tile) and
+// only the nonzero ones are visited, in ascending tile order.
 __global__ __launch_bounds__(kThreads) void k_g_count(int64_t k, int64_t ntiles, int64_t tpad,
                                                       const uint64_t *__restrict__ masks,
                                                       int32_t *__restrict__ g_cnt)
@@ -427,9 +443,15 @@ __global__ __launch_bounds__(kThreads) void k_g_count(int64_t k, int64_t ntiles,
     if (c >= nchunks) return;
     const uint64_t *row = masks + c * tpad;
     int cnt = 0;
-    for (int64_t t = 0; t < ntiles; ++t) {
-        const uint64_t m = row[t];
-        cnt += int((m >> lane) & 1u);
+    for (int64_t t0 = 0; t0 < ntiles; t0 += kWave) {
+        const uint64_t mine = (t0 + lane < ntiles) ? row[t0 + lane] : 0ull;
+        uint64_t nz = ballot(mine != 0ull);
+        while (nz) {
+            const int l = __ffsll(static_cast<unsigned long long>(nz)) - 1;
+            nz &= nz - 1;
+            const uint64_t m = __shfl(mine, l, kWave);
+            cnt += int((m >> lane) & 1ull);
+        }
     }
     const int64_t s = c * kWave + lane;
     if (s < k) g_cnt[s] = cnt;
@@ -449,14 +471,37 @@ __global__ __launch_bounds__(kThreads) void k_g_fill(int64_t k, int64_t ntiles, 
     const uint64_t *row = masks + c * tpad;
     int64_t pos = valid ? g_off[s] : 0;
     const int64_t end = valid ? g_off[s + 1] : 0;
-    for (int64_t t = 0; t < ntiles; ++t) {
-        const uint64_t m = row[t];
-        if (m == 0) continue;
-        if (valid && ((m >> lane) & 1u)) {
-            if (pos < end) g_tiles[pos] = int32_t(t);
-            ++pos;
+    for (int64_t t0 = 0; t0 < ntiles; t0 += kWave) {
+        const uint64_t mine = (t0 + lane < ntiles) ? row[t0 + lane] : 0ull;
+        uint64_t nz = ballot(mine != 0ull);
+        while (nz) {
+            const int l = __ffsll(static_cast<unsigned long long>(nz)) - 1;
+            nz &= nz - 1;
+            const uint64_t m = __shfl(mine, l, kWave);
+            if (valid && ((m >> lane) & 1ull)) {
+                if (pos < end) g_tiles[pos] = int32_t(t0 + l);
+                ++pos;
+            }
         }
     }
+}
+
+// Work items: ceil(count / per) items for each row of a CSR.
+__global__ __launch_bounds__(kThreads) void k_item_count(int64_t n, const int64_t *__restrict__ off,
+                                                         int per, int32_t *__restrict__ cnt)
+{
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t len = off[i + 1] - off[i];
+    cnt[i] = int32_t((len + per - 1) / per);
+}
+
+__global__ __launch_bounds__(kThreads) void k_item_fill(int64_t n, const int64_t *__restrict__ ioff,
+                                                        int64_t cap, int32_t *__restrict__ owner)
+{
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t j = ioff[i]; j < ioff[i + 1] && j < cap; ++j) owner[j] = int32_t(i);
 }
 
 __global__ void k_zero_u64(unsigned long long *p, int n)
@@ -499,6 +544,16 @@ hipError_t radix_sort(int64_t n, int nbits, uint32_t *k0, uint32_t *k1, int32_t 
     return hipGetLastError();
 }
 
+// items per CSR row -> exclusive offsets (n + 1)
+hipError_t launch_items(int64_t n, const int64_t *off, int per, int32_t *cnt, int64_t *ioff,
+                        void *scan_tmp, hipStream_t s)
+{
+    if (n > 0) k_item_count<<<nblk(n, kThreads), kThreads, 0, s>>>(n, off, per, cnt);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan_counts(cnt, ioff, n, scan_tmp, s);
+}
+
 template <int N>
 hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hipStream_t s)
 {
@@ -521,7 +576,7 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
             k_query_proj<N, 32><<<nblk(q, kThreads), kThreads, 0, s>>>(
                 q, P, queries, c->proj.as<float>(), c->qr.as<float>(), c->range_part.as<float>());
     }
-    k_range_final<<<1, kThreads, 0, s>>>(nparts, P, c->params.key_bits,
+    k_range_final<<<dim3(unsigned(P)), kThreads, 0, s>>>(nparts, P, c->params.key_bits,
                                          c->range_part.as<float>(), c->qrange.as<float>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
@@ -579,8 +634,12 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         if (c->ntiles > 0)
             k_zero_i32<<<nblk(c->ntiles, kThreads), kThreads, 0, s>>>(c->tile_cnt.as<int32_t>(),
                                                                      c->ntiles);
-        return scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
-                           c->scan_tmp.p, s);
+        e = scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
+                        c->scan_tmp.p, s);
+        if (e != hipSuccess) return e;
+        return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands,
+                            c->item_cnt.as<int32_t>(), c->item_off.as<int64_t>(), c->scan_tmp.p,
+                            s);
     }
     // interval test
     const int tiles_per_wave = 512;
@@ -604,8 +663,11 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         c->ntiles, c->nseg, c->seg_cnt.as<int32_t>(), c->tile_cnt.as<int32_t>(),
         reinterpret_cast<unsigned long long *>(c->stats.as<int64_t>() + 1));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    return scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
-                       c->scan_tmp.p, s);
+    e = scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
+                    c->scan_tmp.p, s);
+    if (e != hipSuccess) return e;
+    return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands,
+                        c->item_cnt.as<int32_t>(), c->item_off.as<int64_t>(), c->scan_tmp.p, s);
 }
 
 }  // namespace
@@ -625,7 +687,10 @@ hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix, const fl
 
 hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s)
 {
-    if (c->total == 0 || c->ntiles == 0 || c->k == 0) return hipSuccess;
+    if (c->nitems > 0)
+        k_item_fill<<<nblk(c->ntiles, kThreads), kThreads, 0, s>>>(
+            c->ntiles, c->item_off.as<int64_t>(), c->nitems, c->item_tile.as<int32_t>());
+    if (c->total == 0 || c->ntiles == 0 || c->k == 0) return hipGetLastError();
     const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
     dim3 sgrid(nblk(c->ntiles, kThreads), unsigned(c->nseg));
     k_fill_cand<<<sgrid, kThreads, 0, s>>>(c->ntiles, c->tpad, c->nchunks, per_seg,
@@ -637,12 +702,21 @@ hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s)
 hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s)
 {
     const int64_t k = c->k;
-    if (k == 0) return scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), 0,
+    if (k == 0) {
+        hipError_t e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), 0,
                                    c->scan_tmp.p, s);
+        if (e != hipSuccess) return e;
+        return scan_counts(c->gitem_cnt.as<int32_t>(), c->gitem_off.as<int64_t>(), 0,
+                           c->scan_tmp.p, s);
+    }
     if (c->ntiles == 0 || c->total == 0) {
-        // no candidates: every Gaussian has an empty tile list
+        // no candidates: every Gaussian has an empty tile list and no items
         k_zero_i32<<<nblk(k, kThreads), kThreads, 0, s>>>(c->g_cnt.as<int32_t>(), k);
-        return scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k, c->scan_tmp.p, s);
+        hipError_t e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k,
+                                   c->scan_tmp.p, s);
+        if (e != hipSuccess) return e;
+        return launch_items(k, c->g_off.as<int64_t>(), kItemTiles, c->gitem_cnt.as<int32_t>(),
+                            c->gitem_off.as<int64_t>(), c->scan_tmp.p, s);
     }
     const unsigned gb = nblk(c->nchunks, kThreads / kWave);
     k_g_count<<<gb, kThreads, 0, s>>>(k, c->ntiles, c->tpad, c->masks.as<uint64_t>(),
@@ -651,6 +725,11 @@ hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s)
     if (e != hipSuccess) return e;
     k_g_fill<<<gb, kThreads, 0, s>>>(k, c->ntiles, c->tpad, c->masks.as<uint64_t>(),
                                      c->g_off.as<int64_t>(), c->g_tiles.as<int32_t>());
+    e = launch_items(k, c->g_off.as<int64_t>(), kItemTiles, c->gitem_cnt.as<int32_t>(),
+                     c->gitem_off.as<int64_t>(), c->scan_tmp.p, s);
+    if (e != hipSuccess) return e;
+    k_item_fill<<<nblk(k, kThreads), kThreads, 0, s>>>(k, c->gitem_off.as<int64_t>(),
+                                                       c->gitems_cap, c->gitem_g.as<int32_t>());
     return hipGetLastError();
 }
 
@@ -693,6 +772,10 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->tile_off.ensure(sizeof(int64_t) * (T + 1));
     ok &= c->g_cnt.ensure(sizeof(int32_t) * kk);
     ok &= c->g_off.ensure(sizeof(int64_t) * (kk + 1));
+    ok &= c->item_cnt.ensure(sizeof(int32_t) * T);
+    ok &= c->item_off.ensure(sizeof(int64_t) * (T + 1));
+    ok &= c->gitem_cnt.ensure(sizeof(int32_t) * kk);
+    ok &= c->gitem_off.ensure(sizeof(int64_t) * (kk + 1));
     ok &= c->scan_tmp.ensure(scan_tmp_bytes(scan_n));
     ok &= c->stats.ensure(sizeof(int64_t) * 2);
     return ok;

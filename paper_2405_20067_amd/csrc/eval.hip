@@ -3,19 +3,26 @@
 //
 // Layout: one lane per query, queries held in registers; the Gaussian being
 // evaluated is the same for the whole wave, so its record (mean, S', alpha c)
-// is read with wave-uniform loads and feeds the VALU as scalar operands.
+// is read with wave-uniform loads and feeds the VALU as scalar operands.  The
+// first 32 floats of the next candidate's record are loaded one iteration
+// ahead, so the loop does not wait on the load of the record it evaluates.
 //
-// Culled kernel: one workgroup per tile (up to 256 lanes per group; larger
-// tiles use several groups), looping over the tile's candidate list.  Each
-// pair is evaluated in two stages: the first n1 coordinates give the
-// Mahalanobis distance of the marginal over those coordinates, a lower
-// bound of the full one (the leading block of L^-1 is the inverse of the
-// leading block of L).  When no lane of the wave is below the skip
-// threshold the rest of the pair is skipped; likewise before the exp.
-// The threshold certifies G < tau * 2^-20, so a skipped pair changes f by
-// less than that times alpha |c|.
+// Culled kernel: one workgroup per work item -- a tile's queries and at most
+// kItemCands of its candidates -- so a tile with a long list is spread over
+// many workgroups.  A tile with a single item writes its colours directly;
+// otherwise items write partial sums that k_eval_reduce adds in item order.
+//
+// Each pair is evaluated in stages.  After the first 3 and 6 coordinates
+// the partial sum |y_{0..k}|^2 is the Mahalanobis distance of the marginal
+// over those coordinates (the leading block of L^-1 is the inverse of the
+// leading block of L), a lower bound of the full distance.  When no lane of
+// the wave is below the skip threshold the pair is dropped; the threshold
+// certifies G < tau * 2^-20, so a dropped pair changes f by less than that
+// times alpha |c|.  The same test is applied once more before the exp.
 //
 // Dense kernel: the plain direct sum over all Gaussians, no skipping.
+#include <utility>
+
 #include "ngd_internal.hpp"
 #include "wave.hpp"
 
@@ -23,50 +30,84 @@ namespace ngd {
 namespace {
 
 constexpr int kEvalThreads = 256;
+// s_waitcnt immediate that waits for all scalar-memory (and LDS) loads only:
+// vmcnt and expcnt at their maxima, lgkmcnt 0.
+constexpr int kWaitScalar = 0xC07F;
 
-template <int N> constexpr int first_stage_dims() { return N >= 4 ? 4 : N; }
+template <int N> struct RecLayout {
+    static constexpr int T = N * (N + 1) / 2;
+    static constexpr int R = (N + T + 7 + 3) / 4 * 4;
+    static constexpr int AC = N + T;
+    static constexpr int PF = R < 32 ? R : 32;   // floats loaded ahead
+    static constexpr int K1 = N < 3 ? N : 3;      // stage boundaries
+    static constexpr int K2 = N < 6 ? N : 6;
+};
 
-// Accumulates one Gaussian (record r, wave-uniform) into f for this lane's
-// query x.  With SKIP, returns early when the wave can skip the pair.
+// Record field e: from the prefetched block when e < PF, else from memory.
+template <int N, int E>
+__device__ __forceinline__ float field(const float (&blk)[RecLayout<N>::PF],
+                                       const float *__restrict__ r)
+{
+    if constexpr (E < RecLayout<N>::PF)
+        return blk[E];
+    else
+        return r[E];
+}
+
+// Rows [R0, R1) of y = S'(x - m), accumulated into msq; d holds x - m.
+template <int N, int R0, int R1>
+__device__ __forceinline__ void rows(const float (&blk)[RecLayout<N>::PF],
+                                     const float *__restrict__ r, const float (&x)[N],
+                                     float (&d)[N], float (&y)[N], float &msq)
+{
+    if constexpr (R0 < R1) {
+        d[R0] = x[R0] - field<N, R0>(blk, r);
+        constexpr int base = N + R0 * (R0 + 1) / 2;
+        float acc = field<N, base>(blk, r) * d[0];
+        [&]<int... J>(std::integer_sequence<int, J...>) {
+            ((acc = fmaf(field<N, base + 1 + J>(blk, r), d[1 + J], acc)), ...);
+        }(std::make_integer_sequence<int, R0>{});
+        y[R0] = acc;
+        msq = fmaf(acc, acc, msq);
+        rows<N, R0 + 1, R1>(blk, r, x, d, y, msq);
+    }
+}
+
+// Accumulates one Gaussian into f for this lane's query x.  With SKIP,
+// returns early when the whole wave can drop the pair.
 template <int N, bool SKIP>
-__device__ __forceinline__ void eval_pair(const float *__restrict__ r, const float (&x)[N],
+__device__ __forceinline__ void eval_pair(const float (&blk)[RecLayout<N>::PF],
+                                          const float *__restrict__ r, const float (&x)[N],
                                           bool valid, float skip, float &f0, float &f1,
                                           float &f2)
 {
-    constexpr int N1 = first_stage_dims<N>();
-    float d[N];
+    using Lay = RecLayout<N>;
+    float d[N], y[N];
     float msq = 0.0f;
-#pragma unroll
-    for (int a = 0; a < N1; ++a) d[a] = x[a] - r[a];
-#pragma unroll
-    for (int row = 0; row < N1; ++row) {
-        const float *srow = r + N + row * (row + 1) / 2;
-        float y = srow[0] * d[0];
-#pragma unroll
-        for (int j = 1; j <= row; ++j) y = fmaf(srow[j], d[j], y);
-        msq = fmaf(y, y, msq);
-    }
-    if constexpr (SKIP && N1 < N) {
+    rows<N, 0, Lay::K1>(blk, r, x, d, y, msq);
+    if constexpr (SKIP && Lay::K1 < N) {
         if (ballot(valid && msq <= skip) == 0) return;
     }
-#pragma unroll
-    for (int a = N1; a < N; ++a) d[a] = x[a] - r[a];
-#pragma unroll
-    for (int row = N1; row < N; ++row) {
-        const float *srow = r + N + row * (row + 1) / 2;
-        float y = srow[0] * d[0];
-#pragma unroll
-        for (int j = 1; j <= row; ++j) y = fmaf(srow[j], d[j], y);
-        msq = fmaf(y, y, msq);
+    rows<N, Lay::K1, Lay::K2>(blk, r, x, d, y, msq);
+    if constexpr (SKIP && Lay::K2 < N && Lay::K1 < Lay::K2) {
+        if (ballot(valid && msq <= skip) == 0) return;
     }
+    rows<N, Lay::K2, N>(blk, r, x, d, y, msq);
     if constexpr (SKIP) {
         if (ballot(valid && msq <= skip) == 0) return;
     }
-    constexpr int AC = N + N * (N + 1) / 2;
     const float g = __builtin_amdgcn_exp2f(-msq);
-    f0 = fmaf(g, r[AC + 0], f0);
-    f1 = fmaf(g, r[AC + 1], f1);
-    f2 = fmaf(g, r[AC + 2], f2);
+    f0 = fmaf(g, field<N, Lay::AC + 0>(blk, r), f0);
+    f1 = fmaf(g, field<N, Lay::AC + 1>(blk, r), f1);
+    f2 = fmaf(g, field<N, Lay::AC + 2>(blk, r), f2);
+}
+
+template <int N>
+__device__ __forceinline__ void load_block(float (&blk)[RecLayout<N>::PF],
+                                           const float *__restrict__ r)
+{
+#pragma unroll
+    for (int e = 0; e < RecLayout<N>::PF; ++e) blk[e] = r[e];
 }
 
 template <int N>
@@ -75,14 +116,21 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t 
                                                              const float *__restrict__ queries,
                                                              float *__restrict__ out)
 {
-    constexpr int R = (N + N * (N + 1) / 2 + 7 + 3) / 4 * 4;
+    using Lay = RecLayout<N>;
     const int64_t p = int64_t(blockIdx.x) * kEvalThreads + threadIdx.x;
     const bool valid = p < q;
     float x[N];
 #pragma unroll
     for (int a = 0; a < N; ++a) x[a] = valid ? queries[p * N + a] : 0.0f;
     float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
-    for (int64_t i = 0; i < k; ++i) eval_pair<N, false>(rec + i * R, x, valid, 0.0f, f0, f1, f2);
+    float blk[Lay::PF], nxt[Lay::PF];
+    if (k > 0) load_block<N>(nxt, rec);
+    for (int64_t i = 0; i < k; ++i) {
+#pragma unroll
+        for (int e = 0; e < Lay::PF; ++e) blk[e] = nxt[e];
+        if (i + 1 < k) load_block<N>(nxt, rec + (i + 1) * Lay::R);
+        eval_pair<N, false>(blk, rec + i * Lay::R, x, valid, 0.0f, f0, f1, f2);
+    }
     if (valid) {
         out[p * 3 + 0] = f0;
         out[p * 3 + 1] = f1;
@@ -91,13 +139,22 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t 
 }
 
 template <int N>
-__global__ __launch_bounds__(kEvalThreads) void k_eval_culled(
+__global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     int64_t q, int tile, const float *__restrict__ grec, const float *__restrict__ qs,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ cand,
-    const int32_t *__restrict__ perm, float skip, float *__restrict__ out)
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ item_tile,
+    const int64_t *__restrict__ item_off, float skip, float *__restrict__ out,
+    float *__restrict__ part)
 {
-    constexpr int R = (N + N * (N + 1) / 2 + 7 + 3) / 4 * 4;
-    const int64_t t = blockIdx.x;
+    using Lay = RecLayout<N>;
+    const int64_t it = blockIdx.x;
+    const int64_t t = uniform(item_tile[it]);
+    const int64_t i0 = uniform64(item_off[t]);
+    const int64_t nit = uniform64(item_off[t + 1]) - i0;
+    const int64_t c0 = uniform64(tile_off[t]), c1 = uniform64(tile_off[t + 1]);
+    const int64_t e0 = c0 + (it - i0) * kItemCands;
+    const int64_t e1 = (e0 + kItemCands < c1) ? e0 + kItemCands : c1;
+
     const int s = int(blockIdx.y) * kEvalThreads + int(threadIdx.x);
     const int64_t p = t * tile + s;
     const bool valid = (s < tile) && (p < q);
@@ -105,17 +162,72 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_culled(
 #pragma unroll
     for (int a = 0; a < N; ++a) x[a] = valid ? qs[a * q + p] : 0.0f;
     float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
-    const int64_t e0 = uniform64(tile_off[t]), e1 = uniform64(tile_off[t + 1]);
-    for (int64_t e = e0; e < e1; ++e) {
-        const int64_t c = uniform(cand[e]);
-        eval_pair<N, true>(grec + c * R, x, valid, skip, f0, f1, f2);
+
+    // Candidate indices are read 64 at a time with one vector load; each
+    // record is fetched with wave-uniform loads one candidate ahead into one
+    // of two register blocks.  Uniform loads may complete out of order, so
+    // the wait for the current block is placed before the next block's load
+    // is issued: the wait then never covers the load still in flight.
+    float bufA[Lay::PF], bufB[Lay::PF];
+    for (int64_t ch = e0; ch < e1; ch += kWave) {
+        const int n = int((e1 - ch < kWave) ? e1 - ch : kWave);
+        const int vidx = (lane_id() < n) ? cand[ch + lane_id()] : 0;
+        int64_t ia = __builtin_amdgcn_readlane(vidx, 0);
+        load_block<N>(bufA, grec + ia * Lay::R);
+        for (int j = 0; j < n; j += 2) {
+            __builtin_amdgcn_s_waitcnt(kWaitScalar);
+            int64_t ib = 0;
+            if (j + 1 < n) {
+                ib = __builtin_amdgcn_readlane(vidx, j + 1);
+                load_block<N>(bufB, grec + ib * Lay::R);
+            }
+            eval_pair<N, true>(bufA, grec + ia * Lay::R, x, valid, skip, f0, f1, f2);
+            if (j + 1 >= n) break;
+            __builtin_amdgcn_s_waitcnt(kWaitScalar);
+            if (j + 2 < n) {
+                ia = __builtin_amdgcn_readlane(vidx, j + 2);
+                load_block<N>(bufA, grec + ia * Lay::R);
+            }
+            eval_pair<N, true>(bufB, grec + ib * Lay::R, x, valid, skip, f0, f1, f2);
+        }
     }
-    if (valid) {
+    if (!valid) return;
+    if (nit == 1) {
         const int64_t o = perm[p];
         out[o * 3 + 0] = f0;
         out[o * 3 + 1] = f1;
         out[o * 3 + 2] = f2;
+    } else {
+        float *pp = part + it * 3 * int64_t(tile);
+        pp[s] = f0;
+        pp[tile + s] = f1;
+        pp[2 * tile + s] = f2;
     }
+}
+
+// Tiles with no item (no candidates) get zeros; tiles with two or more items
+// get the sum of their items' partials in item order.
+__global__ __launch_bounds__(kEvalThreads) void k_eval_reduce(
+    int64_t q, int tile, const int32_t *__restrict__ perm, const int64_t *__restrict__ item_off,
+    const float *__restrict__ part, float *__restrict__ out)
+{
+    const int64_t t = blockIdx.x;
+    const int64_t i0 = item_off[t], i1 = item_off[t + 1];
+    if (i1 - i0 == 1) return;
+    const int s = int(blockIdx.y) * kEvalThreads + int(threadIdx.x);
+    const int64_t p = t * tile + s;
+    if (s >= tile || p >= q) return;
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+    for (int64_t i = i0; i < i1; ++i) {
+        const float *pp = part + i * 3 * int64_t(tile);
+        f0 += pp[s];
+        f1 += pp[tile + s];
+        f2 += pp[2 * tile + s];
+    }
+    const int64_t o = perm[p];
+    out[o * 3 + 0] = f0;
+    out[o * 3 + 1] = f1;
+    out[o * 3 + 2] = f2;
 }
 
 template <int N>
@@ -133,12 +245,17 @@ hipError_t culled_n(const ngd_mixture *mix, const ngd_cull *c, float *out, hipSt
     (void)mix;
     const int tile = c->params.tile;
     const int per = tile < kEvalThreads ? (tile + 63) / 64 * 64 : kEvalThreads;
-    dim3 grid(unsigned(c->ntiles), unsigned((tile + kEvalThreads - 1) / kEvalThreads));
+    const unsigned gy = unsigned((tile + kEvalThreads - 1) / kEvalThreads);
     // skip when exp2(-M') < tau 2^-margin, i.e. M' > log2(1/tau) + margin
     const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
-    k_eval_culled<N><<<grid, per, 0, s>>>(c->q, tile, c->grec.as<float>(), c->qs.as<float>(),
-                                          c->tile_off.as<int64_t>(), c->cand.as<int32_t>(),
-                                          c->perm.as<int32_t>(), skip, out);
+    if (c->nitems > 0) {
+        k_eval_items<N><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
+            c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
+            c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
+            c->item_off.as<int64_t>(), skip, out, c->fpart.as<float>());
+    }
+    k_eval_reduce<<<dim3(unsigned(c->ntiles), gy), per, 0, s>>>(
+        c->q, tile, c->perm.as<int32_t>(), c->item_off.as<int64_t>(), c->fpart.as<float>(), out);
     return hipGetLastError();
 }
 
@@ -161,7 +278,7 @@ hipError_t launch_eval_dense(const ngd_mixture *mix, const float *queries, int64
 hipError_t launch_eval_culled(const ngd_mixture *mix, const ngd_cull *c, float *out,
                               hipStream_t s)
 {
-    if (c->q == 0) return hipSuccess;
+    if (c->q == 0 || c->ntiles == 0) return hipSuccess;
     switch (mix->n) {
 #define NGD_CASE(NN) \
     case NN: return culled_n<NN>(mix, c, out, s);

@@ -19,6 +19,13 @@ constexpr double kSqrtHalfLog2e = 0.84932180028801904272;
 // are skipped inside the evaluation kernels (see ngd_eval).
 constexpr double kSkipLog2Margin = 20.0;
 
+// Work items: the forward splits each tile's candidate list into items of
+// at most kItemCands candidates; the backward splits each Gaussian's tile
+// list into items of at most kItemTiles tiles.  Items are independent
+// workgroups / waves; their partial sums are combined in a fixed order.
+constexpr int kItemCands = 512;
+constexpr int kItemTiles = 32;
+
 inline int tri(int n) { return n * (n + 1) / 2; }
 
 // Per-Gaussian record read by the evaluation kernels, one row of `stride`
@@ -67,6 +74,8 @@ struct ngd_cull {
     int64_t ntiles = 0;
     int64_t total = 0;
     int64_t max_per_tile = 0;
+    int64_t nitems = 0;        // forward work items
+    int64_t gitems_cap = 0;    // upper bound of backward work items
     int64_t nchunks = 0;       // ceil(k / 64)
     int64_t tpad = 0;          // ntiles rounded up to 64
     int nseg = 0;              // chunk segments used by the list build
@@ -94,9 +103,18 @@ struct ngd_cull {
     ngd::DevBuf g_cnt;         // k int32
     ngd::DevBuf g_off;         // k + 1 int64
     ngd::DevBuf g_tiles;       // total int32
+    ngd::DevBuf item_cnt;      // ntiles int32: forward items per tile
+    ngd::DevBuf item_off;      // ntiles + 1 int64
+    ngd::DevBuf item_tile;     // nitems int32
+    ngd::DevBuf fpart;         // nitems x 3 x tile float: forward partial sums
+    ngd::DevBuf gitem_cnt;     // k int32: backward items per Gaussian
+    ngd::DevBuf gitem_off;     // k + 1 int64
+    ngd::DevBuf gitem_g;       // gitems_cap int32: sorted Gaussian of each item
+    ngd::DevBuf gpart;         // gitems_cap x (n + tri + 3) float: moments
+    ngd::DevBuf gflag;         // gitems_cap int32: item had contributing pairs
     ngd::DevBuf scan_tmp;      // scan block sums
     ngd::DevBuf stats;         // 2 int64: total, max per tile
-    int64_t *stats_host = nullptr;  // pinned
+    int64_t *stats_host = nullptr;  // pinned: total, max per tile, items
 };
 
 namespace ngd {

@@ -58,3 +58,19 @@ def per_query_csr(c, q, tile):
         lst = c["cand"][c["tile_off"][t]:c["tile_off"][t + 1]]
         gidx[qoff[p]:qoff[p + 1]] = c["gperm"][lst]
     return qoff, gidx
+
+
+def per_gaussian_csr(c, q, tile):
+    """For every Gaussian with candidate tiles: (sel, qoff, qidx) listing the
+    queries of its tiles (caller's indices), for the oracle's grad_lists."""
+    sel, qoff, qidx = [], [0], []
+    for s_pos in range(len(c["gperm"])):
+        tiles = c["g_tiles"][c["g_off"][s_pos]:c["g_off"][s_pos + 1]]
+        if tiles.size == 0:
+            continue
+        qs = np.concatenate([c["perm"][t * tile:min((t + 1) * tile, q)] for t in tiles])
+        sel.append(c["gperm"][s_pos])
+        qidx.append(qs)
+        qoff.append(qoff[-1] + qs.size)
+    qidx = np.concatenate(qidx) if qidx else np.zeros(0, np.int64)
+    return np.array(sel, np.int64), np.array(qoff, np.int64), qidx.astype(np.int64)

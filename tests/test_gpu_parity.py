@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import case, dev, host, normwise, per_query_csr
+from gpu_helpers import case, dev, host, normwise, per_gaussian_csr, per_query_csr
 from paper_2405_20067_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -48,6 +48,10 @@ CULL_CASES = [
     dict(n=3, k=64, q=70, tile=1),
     dict(n=10, k=65, q=257, tile=64),
     dict(n=2, k=130, q=1000, tile=1024, key_bits=3, key_proj=10),
+    # long lists: tiles with several forward items, Gaussians with several
+    # backward items
+    dict(n=4, k=3000, q=20000, tile=256),
+    dict(n=6, k=2500, q=9000, tile=512),
 ]
 
 
@@ -130,9 +134,14 @@ def test_dense_backward_matches_oracle(torch_cuda, cfg):
         assert normwise(a, b) <= TOL_FP32, name
 
 
-@pytest.mark.parametrize("cfg", [CULL_CASES[0], CULL_CASES[1], CULL_CASES[2], CULL_CASES[4]],
-                         ids=_ids)
+@pytest.mark.parametrize("cfg", [CULL_CASES[i] for i in (0, 1, 2, 4, 6, 7)], ids=_ids)
 def test_culled_backward_matches_oracle(torch_cuda, cfg):
+    """The backward of the culled forward is the gradient of the sum over the
+    candidate pairs: compared with the oracle's gradient over exactly those
+    pairs (the arithmetic error, bar 1e-4).  Against the full oracle the
+    difference also holds the culled pairs' gradient terms, which are small
+    in value but carry z y^T factors that grow with distance; that difference
+    is bounded loosely and reported."""
     from paper_2405_20067_amd import ngd
     n, k, q = cfg["n"], cfg["k"], cfg["q"]
     mix, x, proj = case(n, k, q, seed=n * 7 + k)
@@ -140,10 +149,21 @@ def test_culled_backward_matches_oracle(torch_cuda, cfg):
     m = _mixture(torch_cuda, mix)
     xd = dev(x)
     c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"]))
+    exp = c.export()
+    if cfg["k"] >= 2500:   # the long-list cases really exercise multiple items
+        assert np.diff(exp["tile_off"]).max() > 512
+    if cfg["k"] >= 2500 and n == 4:
+        assert np.diff(exp["g_off"]).max() > 32
     got = [host(t) for t in ngd.eval_backward(m, c, xd, dev(g))]
-    want = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g)
-    for name, a, b in zip(("mean", "factor", "weight", "colour"), got, want):
-        assert normwise(a, b) <= TOL_FP32, name
+    sel, qoff, qidx = per_gaussian_csr(exp, q, cfg["tile"])
+    part = oracle.grad_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g,
+                             sel, qoff, qidx)
+    full = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g)
+    for name, a, b, f in zip(("mean", "factor", "weight", "colour"), got, part, full):
+        want = np.zeros_like(f)
+        want[sel] = b
+        assert normwise(a, want) <= TOL_FP32, name
+        assert normwise(a, f) <= 2e-3, name
 
 
 def test_repeat_runs_are_bitwise_identical(torch_cuda):
