@@ -8,16 +8,17 @@
 //   dl/dL     = tril(S^T B2),                   B2 = sum_x w y y^T
 // (dl/dm = sum w z and dl/dL = tril(sum w z y^T) with z = S^T y.)
 //
-// Atomics-free and Gaussian-major.  Culled: a work item is one Gaussian and
-// at most kItemTiles of the tiles whose candidate list holds it; one wave
-// walks those tiles 64 queries at a time, keeping per-lane partial moments
-// in registers (B1: n, B2: n(n+1)/2, H: 3), reduces them across lanes once
-// and writes them to the item's slot.  k_backward_finalize then adds each
-// Gaussian's items in item order and applies S^T.  Exp terms are recomputed,
-// not stored.  Pairs are dropped with the same staged, certified test and
-// threshold as the forward kernel (same operations in the same order), so
-// forward and backward sum over the same pairs.  Dense: one wave per
-// Gaussian over all queries, no dropping.
+// Atomics-free and Gaussian-major.  Culled: the forward pass records, for
+// every candidate entry (tile, Gaussian) and every 64-query group of the
+// tile, whether it kept the pair group (one byte); the backward visits only
+// the kept groups, so it sums over exactly the pairs the forward summed,
+// recomputing y, G and the exp rather than storing them.  A work item is one
+// Gaussian and at most kItemTiles of its candidate entries (the transposed
+// lists); one wave evaluates the item's kept groups 64 queries at a time,
+// keeps per-lane partial moments in registers (B1: n, B2: n(n+1)/2, H: 3),
+// reduces them across lanes once and writes them to the item's slot.
+// k_backward_finalize then adds each Gaussian's items in item order and
+// applies S^T.  Dense: one wave per Gaussian over all queries.
 #include "ngd_internal.hpp"
 #include "wave.hpp"
 
@@ -213,8 +214,9 @@ template <int N>
 __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
     int64_t k, int64_t q, int tile, const float *__restrict__ grec,
     const float *__restrict__ qs, const float *__restrict__ gs,
-    const int64_t *__restrict__ g_off, const int32_t *__restrict__ g_tiles,
-    const int64_t *__restrict__ gitem_off, const int32_t *__restrict__ gitem_g, float skip,
+    const int64_t *__restrict__ g_off, const int32_t *__restrict__ g_ent,
+    const int32_t *__restrict__ ent_tile, const uint8_t *__restrict__ act,
+    const int64_t *__restrict__ gitem_off, const int32_t *__restrict__ gitem_g,
     float *__restrict__ gpart, int32_t *__restrict__ gflag)
 {
     using Lay = BwdLayout<N>;
@@ -236,63 +238,53 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
     for (int a = 0; a < N; ++a) b1[a] = 0.0f;
 #pragma unroll
     for (int e = 0; e < T; ++e) b2[e] = 0.0f;
-    bool any = false;
 
-    // iterations: (tile e, group of 64 queries gq); coordinates of the next
-    // iteration's first K2 dimensions are loaded one iteration ahead
-    const int ngrp = (tile + kWave - 1) / kWave;
-    const int64_t iters = (e1 - e0) * ngrp;
-    float xn[Lay::K2];
-    int64_t pn = 0;
-    bool vn = false;
-    // the item's tile list (at most kItemTiles <= 64 entries), one per lane
-    const int tiles_v = (e0 + lane < e1) ? g_tiles[e0 + lane] : 0;
-    auto fetch = [&](int64_t i) {
-        const int64_t tt = __builtin_amdgcn_readlane(tiles_v, int(i / ngrp));
-        const int sidx = int(i % ngrp) * kWave + lane;
-        pn = tt * tile + sidx;
-        vn = (sidx < tile) && (pn < q);
-#pragma unroll
-        for (int a = 0; a < Lay::K2; ++a) xn[a] = vn ? qs[a * q + pn] : 0.0f;
-    };
-    if (iters > 0) fetch(0);
-    for (int64_t i = 0; i < iters; ++i) {
-        float x[N], d[N], y[N];
-#pragma unroll
-        for (int a = 0; a < Lay::K2; ++a) x[a] = xn[a];
-        const int64_t p = pn;
-        const bool valid = vn;
-        if (i + 1 < iters) fetch(i + 1);
-        float msq = 0.0f;
-        brows<N, 0, Lay::K1>(r, x, d, y, msq);
-        if constexpr (Lay::K1 < N) {
-            if (ballot(valid && msq <= skip) == 0) continue;
+    // (entry, query group) pairs of this item, 64 per round, lane = pair:
+    // keep the ones the forward kept, then visit them in ascending order
+    const int ngroups = (tile + kWave - 1) / kWave;
+    const int64_t npairs = (e1 - e0) * ngroups;
+    bool any = false;
+    for (int64_t base = 0; base < npairs; base += kWave) {
+        const int64_t pi = base + lane;
+        int ent = 0, tl = 0;
+        bool kept = false;
+        if (pi < npairs) {
+            ent = g_ent[e0 + pi / ngroups];
+            kept = act[int64_t(ent) * ngroups + pi % ngroups] != 0;
+            tl = kept ? ent_tile[ent] : 0;
         }
-        brows<N, Lay::K1, Lay::K2>(r, x, d, y, msq);
-        if constexpr (Lay::K2 < N && Lay::K1 < Lay::K2) {
-            if (ballot(valid && msq <= skip) == 0) continue;
-        }
+        uint64_t m = ballot(kept);
+        while (m) {
+            const int l = __ffsll(static_cast<unsigned long long>(m)) - 1;
+            m &= m - 1;
+            const int64_t tt = __builtin_amdgcn_readlane(tl, l);
+            const int gq = int((base + l) % ngroups);
+            const int sidx = gq * kWave + lane;
+            const int64_t p = tt * tile + sidx;
+            const bool valid = (sidx < tile) && (p < q);
+            float x[N], d[N], y[N];
 #pragma unroll
-        for (int a = Lay::K2; a < N; ++a) x[a] = valid ? qs[a * q + p] : 0.0f;
-        brows<N, Lay::K2, N>(r, x, d, y, msq);
-        if (ballot(valid && msq <= skip) == 0) continue;
-        any = true;
-        const float G = valid ? __builtin_amdgcn_exp2f(-msq) : 0.0f;
-        const float g0v = valid ? gs[p] : 0.0f;
-        const float g1v = valid ? gs[q + p] : 0.0f;
-        const float g2v = valid ? gs[2 * q + p] : 0.0f;
-        const float sdot = fmaf(g2v, c2, fmaf(g1v, c1, g0v * c0));
-        const float w = alpha * G * sdot;
-        h0 = fmaf(G, g0v, h0);
-        h1 = fmaf(G, g1v, h1);
-        h2 = fmaf(G, g2v, h2);
+            for (int a = 0; a < N; ++a) x[a] = valid ? qs[a * q + p] : 0.0f;
+            float msq = 0.0f;
+            brows<N, 0, N>(r, x, d, y, msq);
+            any = true;
+            const float G = valid ? __builtin_amdgcn_exp2f(-msq) : 0.0f;
+            const float g0v = valid ? gs[p] : 0.0f;
+            const float g1v = valid ? gs[q + p] : 0.0f;
+            const float g2v = valid ? gs[2 * q + p] : 0.0f;
+            const float sdot = fmaf(g2v, c2, fmaf(g1v, c1, g0v * c0));
+            const float w = alpha * G * sdot;
+            h0 = fmaf(G, g0v, h0);
+            h1 = fmaf(G, g1v, h1);
+            h2 = fmaf(G, g2v, h2);
 #pragma unroll
-        for (int a = 0; a < N; ++a) {
-            const float wy = w * y[a];
-            b1[a] += wy;
+            for (int a = 0; a < N; ++a) {
+                const float wy = w * y[a];
+                b1[a] += wy;
 #pragma unroll
-            for (int b = 0; b <= a; ++b)
-                b2[a * (a + 1) / 2 + b] = fmaf(wy, y[b], b2[a * (a + 1) / 2 + b]);
+                for (int b = 0; b <= a; ++b)
+                    b2[a * (a + 1) / 2 + b] = fmaf(wy, y[b], b2[a * (a + 1) / 2 + b]);
+            }
         }
     }
     if (!any) {
@@ -402,14 +394,13 @@ hipError_t culled_n(const ngd_mixture *mix, ngd_cull *c, const float *grad_out, 
         k_gather_grad<<<unsigned((c->q + 255) / 256), 256, 0, s>>>(
             c->q, c->perm.as<int32_t>(), grad_out, c->gs.as<float>());
     }
-    const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
     if (c->gitems_cap > 0) {
         const unsigned blocks = unsigned((c->gitems_cap + kWavesPerBlock - 1) / kWavesPerBlock);
         k_backward_items<N><<<blocks, kBwdThreads, 0, s>>>(
             mix->k, c->q, c->params.tile, c->grec.as<float>(), c->qs.as<float>(),
-            c->gs.as<float>(), c->g_off.as<int64_t>(), c->g_tiles.as<int32_t>(),
-            c->gitem_off.as<int64_t>(), c->gitem_g.as<int32_t>(), skip, c->gpart.as<float>(),
-            c->gflag.as<int32_t>());
+            c->gs.as<float>(), c->g_off.as<int64_t>(), c->g_ent.as<int32_t>(),
+            c->ent_tile.as<int32_t>(), c->act.as<uint8_t>(), c->gitem_off.as<int64_t>(),
+            c->gitem_g.as<int32_t>(), c->gpart.as<float>(), c->gflag.as<int32_t>());
     }
     const unsigned fb = unsigned((mix->k + kBwdThreads - 1) / kBwdThreads);
     k_backward_finalize<N><<<fb, kBwdThreads, 0, s>>>(

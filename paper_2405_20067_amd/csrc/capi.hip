@@ -214,7 +214,8 @@ static void cull_release(ngd_cull *c)
                       &c->g_thr_s, &c->masks,    &c->seg_cnt,    &c->tile_cnt, &c->tile_off,
                       &c->cand,    &c->g_cnt,    &c->g_off,      &c->g_tiles, &c->scan_tmp,
                       &c->stats,   &c->item_cnt, &c->item_off,   &c->item_tile, &c->fpart,
-                      &c->gitem_cnt, &c->gitem_off, &c->gitem_g, &c->gpart,   &c->gflag};
+                      &c->gitem_cnt, &c->gitem_off, &c->gitem_g, &c->gpart,   &c->gflag,
+                      &c->g_ent,   &c->ent_tile, &c->act};
     for (DevBuf *b : bufs) b->release();
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     c->stats_host = nullptr;
@@ -306,15 +307,9 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (c->total >= (int64_t(1) << 31))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: %lld candidates exceed 2^31",
                          (long long)c->total));
-    const size_t nm = size_t(c->n + tri(c->n) + 3);
-    if (!c->cand.ensure(sizeof(int32_t) * size_t(c->total)) ||
-        !c->g_tiles.ensure(sizeof(int32_t) * size_t(c->total)) ||
-        !c->item_tile.ensure(sizeof(int32_t) * size_t(c->nitems)) ||
-        !c->fpart.ensure(sizeof(float) * 3 * size_t(c->nitems) * size_t(p->tile)) ||
-        !c->gitem_g.ensure(sizeof(int32_t) * size_t(c->gitems_cap)) ||
-        !c->gpart.ensure(sizeof(float) * nm * size_t(c->gitems_cap)) ||
-        !c->gflag.ensure(sizeof(int32_t) * size_t(c->gitems_cap)))
+    if (!cull_reserve_lists(c))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: candidate list allocation failed"));
+    c->act_version = -1;
     e = launch_cull_build_lists(c, s);
     if (e == hipSuccess) e = launch_cull_build_transpose(c, s);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (lists)"));
@@ -401,6 +396,7 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
         e = launch_zero_f32(out, 3 * q, S(stream));
     } else if (cull) {
         e = launch_eval_culled(mix, cull, out, S(stream));
+        if (e == hipSuccess) cull->act_version = mix->version;
     } else {
         e = launch_eval_dense(mix, queries, q, out, S(stream));
     }
@@ -432,9 +428,18 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull, const float 
     }
     if (mix->k == 0) return NGD_OK;
     hipError_t e;
-    if (cull)
-        e = launch_backward_culled(mix, const_cast<ngd_cull *>(cull), grad_out, g_mean, g_factor,
-                                   g_weight, g_colour, S(stream));
+    if (cull) {
+        // the backward visits the (entry, query group) pairs the forward kept;
+        // without a forward on this cull and mixture version, decide them now
+        e = hipSuccess;
+        if (cull->act_version != mix->version && cull->nitems > 0) {
+            e = launch_eval_culled(mix, cull, nullptr, S(stream));
+            if (e == hipSuccess) cull->act_version = mix->version;
+        }
+        if (e == hipSuccess)
+            e = launch_backward_culled(mix, const_cast<ngd_cull *>(cull), grad_out, g_mean,
+                                       g_factor, g_weight, g_colour, S(stream));
+    }
     else
         e = launch_backward_dense(mix, queries, q, grad_out, g_mean, g_factor, g_weight, g_colour,
                                   S(stream));

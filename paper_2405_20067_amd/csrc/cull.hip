@@ -410,7 +410,8 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
                                                         const uint64_t *__restrict__ masks,
                                                         const int32_t *__restrict__ seg_cnt,
                                                         const int64_t *__restrict__ tile_off,
-                                                        int32_t *__restrict__ cand)
+                                                        int32_t *__restrict__ cand,
+                                                        int32_t *__restrict__ ent_tile)
 {
     const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (t >= ntiles) return;
@@ -423,67 +424,45 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
         uint64_t m = masks[c * tpad + t];
         while (m) {
             const int b = __ffsll(static_cast<unsigned long long>(m)) - 1;
-            if (pos < end) cand[pos] = int32_t(c * kWave + b);
+            if (pos < end) {
+                cand[pos] = int32_t(c * kWave + b);
+                ent_tile[pos] = int32_t(t);
+            }
             ++pos;
             m &= m - 1;
         }
     }
 }
 
-// Transposed lists.  One wave per chunk of 64 sorted Gaussians (lane =
-// Gaussian); the chunk's masks are read 64 tiles at a time (lane = tile) and
-// only the nonzero ones are visited, in ascending tile order.
-__global__ __launch_bounds__(kThreads) void k_g_count(int64_t k, int64_t ntiles, int64_t tpad,
-                                                      const uint64_t *__restrict__ masks,
-                                                      int32_t *__restrict__ g_cnt)
+// Transposed lists: entries of the candidate lists grouped by Gaussian.
+// Counts per Gaussian (order-independent integer atomics), then a stable
+// radix sort of (Gaussian, entry) by Gaussian keeps each Gaussian's entries
+// in ascending entry order, i.e. ascending tile order.
+__global__ __launch_bounds__(kThreads) void k_ghist(int64_t total, const int32_t *__restrict__ cand,
+                                                    int32_t *__restrict__ g_cnt)
 {
-    const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t nchunks = (k + kWave - 1) / kWave;
-    const int64_t c = int64_t(blockIdx.x) * (kThreads / kWave) + w;
-    if (c >= nchunks) return;
-    const uint64_t *row = masks + c * tpad;
-    int cnt = 0;
-    for (int64_t t0 = 0; t0 < ntiles; t0 += kWave) {
-        const uint64_t mine = (t0 + lane < ntiles) ? row[t0 + lane] : 0ull;
-        uint64_t nz = ballot(mine != 0ull);
-        while (nz) {
-            const int l = __ffsll(static_cast<unsigned long long>(nz)) - 1;
-            nz &= nz - 1;
-            const uint64_t m = __shfl(mine, l, kWave);
-            cnt += int((m >> lane) & 1ull);
-        }
-    }
-    const int64_t s = c * kWave + lane;
-    if (s < k) g_cnt[s] = cnt;
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (e < total) atomicAdd(&g_cnt[cand[e]], 1);
 }
 
-__global__ __launch_bounds__(kThreads) void k_g_fill(int64_t k, int64_t ntiles, int64_t tpad,
-                                                     const uint64_t *__restrict__ masks,
-                                                     const int64_t *__restrict__ g_off,
-                                                     int32_t *__restrict__ g_tiles)
+__global__ __launch_bounds__(kThreads) void k_ent_init(int64_t total,
+                                                       const int32_t *__restrict__ cand,
+                                                       uint32_t *__restrict__ keys,
+                                                       int32_t *__restrict__ vals)
 {
-    const int w = threadIdx.x / kWave, lane = lane_id();
-    const int64_t nchunks = (k + kWave - 1) / kWave;
-    const int64_t c = int64_t(blockIdx.x) * (kThreads / kWave) + w;
-    if (c >= nchunks) return;
-    const int64_t s = c * kWave + lane;
-    const bool valid = s < k;
-    const uint64_t *row = masks + c * tpad;
-    int64_t pos = valid ? g_off[s] : 0;
-    const int64_t end = valid ? g_off[s + 1] : 0;
-    for (int64_t t0 = 0; t0 < ntiles; t0 += kWave) {
-        const uint64_t mine = (t0 + lane < ntiles) ? row[t0 + lane] : 0ull;
-        uint64_t nz = ballot(mine != 0ull);
-        while (nz) {
-            const int l = __ffsll(static_cast<unsigned long long>(nz)) - 1;
-            nz &= nz - 1;
-            const uint64_t m = __shfl(mine, l, kWave);
-            if (valid && ((m >> lane) & 1ull)) {
-                if (pos < end) g_tiles[pos] = int32_t(t0 + l);
-                ++pos;
-            }
-        }
-    }
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (e >= total) return;
+    keys[e] = uint32_t(cand[e]);
+    vals[e] = int32_t(e);
+}
+
+__global__ __launch_bounds__(kThreads) void k_ent_gather(int64_t total,
+                                                         const int32_t *__restrict__ g_ent,
+                                                         const int32_t *__restrict__ ent_tile,
+                                                         int32_t *__restrict__ g_tiles)
+{
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < total) g_tiles[i] = ent_tile[g_ent[i]];
 }
 
 // Work items: ceil(count / per) items for each row of a CSR.
@@ -695,42 +674,74 @@ hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s)
     dim3 sgrid(nblk(c->ntiles, kThreads), unsigned(c->nseg));
     k_fill_cand<<<sgrid, kThreads, 0, s>>>(c->ntiles, c->tpad, c->nchunks, per_seg,
                                            c->masks.as<uint64_t>(), c->seg_cnt.as<int32_t>(),
-                                           c->tile_off.as<int64_t>(), c->cand.as<int32_t>());
+                                           c->tile_off.as<int64_t>(), c->cand.as<int32_t>(),
+                                           c->ent_tile.as<int32_t>());
     return hipGetLastError();
 }
 
 hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s)
 {
     const int64_t k = c->k;
-    if (k == 0) {
-        hipError_t e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), 0,
-                                   c->scan_tmp.p, s);
+    hipError_t e;
+    if (k > 0) k_zero_i32<<<nblk(k, kThreads), kThreads, 0, s>>>(c->g_cnt.as<int32_t>(), k);
+    if (c->total > 0) {
+        k_ghist<<<nblk(c->total, kThreads), kThreads, 0, s>>>(c->total, c->cand.as<int32_t>(),
+                                                             c->g_cnt.as<int32_t>());
+        k_ent_init<<<nblk(c->total, kThreads), kThreads, 0, s>>>(
+            c->total, c->cand.as<int32_t>(), c->keys0.as<uint32_t>(), c->vals0.as<int32_t>());
+        int nbits = 0;
+        while ((int64_t(1) << nbits) < k) ++nbits;
+        int which = 0;
+        e = radix_sort(c->total, nbits, c->keys0.as<uint32_t>(), c->keys1.as<uint32_t>(),
+                       c->vals0.as<int32_t>(), c->vals1.as<int32_t>(),
+                       c->radix_hist.as<int32_t>(), c->radix_off.as<int64_t>(), c->scan_tmp.p, s,
+                       &which);
         if (e != hipSuccess) return e;
-        return scan_counts(c->gitem_cnt.as<int32_t>(), c->gitem_off.as<int64_t>(), 0,
-                           c->scan_tmp.p, s);
-    }
-    if (c->ntiles == 0 || c->total == 0) {
-        // no candidates: every Gaussian has an empty tile list and no items
-        k_zero_i32<<<nblk(k, kThreads), kThreads, 0, s>>>(c->g_cnt.as<int32_t>(), k);
-        hipError_t e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k,
-                                   c->scan_tmp.p, s);
+        e = hipMemcpyAsync(c->g_ent.p, which ? c->vals1.p : c->vals0.p,
+                           sizeof(int32_t) * c->total, hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
-        return launch_items(k, c->g_off.as<int64_t>(), kItemTiles, c->gitem_cnt.as<int32_t>(),
-                            c->gitem_off.as<int64_t>(), c->scan_tmp.p, s);
+        k_ent_gather<<<nblk(c->total, kThreads), kThreads, 0, s>>>(
+            c->total, c->g_ent.as<int32_t>(), c->ent_tile.as<int32_t>(), c->g_tiles.as<int32_t>());
     }
-    const unsigned gb = nblk(c->nchunks, kThreads / kWave);
-    k_g_count<<<gb, kThreads, 0, s>>>(k, c->ntiles, c->tpad, c->masks.as<uint64_t>(),
-                                      c->g_cnt.as<int32_t>());
-    hipError_t e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k, c->scan_tmp.p, s);
+    e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k, c->scan_tmp.p, s);
     if (e != hipSuccess) return e;
-    k_g_fill<<<gb, kThreads, 0, s>>>(k, c->ntiles, c->tpad, c->masks.as<uint64_t>(),
-                                     c->g_off.as<int64_t>(), c->g_tiles.as<int32_t>());
     e = launch_items(k, c->g_off.as<int64_t>(), kItemTiles, c->gitem_cnt.as<int32_t>(),
                      c->gitem_off.as<int64_t>(), c->scan_tmp.p, s);
     if (e != hipSuccess) return e;
-    k_item_fill<<<nblk(k, kThreads), kThreads, 0, s>>>(k, c->gitem_off.as<int64_t>(),
-                                                       c->gitems_cap, c->gitem_g.as<int32_t>());
+    if (k > 0 && c->gitems_cap > 0)
+        k_item_fill<<<nblk(k, kThreads), kThreads, 0, s>>>(k, c->gitem_off.as<int64_t>(),
+                                                           c->gitems_cap,
+                                                           c->gitem_g.as<int32_t>());
     return hipGetLastError();
+}
+
+bool cull_reserve_lists(ngd_cull *c)
+{
+    const int64_t tot = c->total > 0 ? c->total : 1;
+    const int64_t groups = (c->params.tile + kWave - 1) / kWave;
+    const int64_t nb = (tot + kRadixPerBlock - 1) / kRadixPerBlock;
+    const int64_t kk = c->k > 0 ? c->k : 1;
+    const int64_t T = c->ntiles > 0 ? c->ntiles : 1;
+    const size_t nm = size_t(c->n + tri(c->n) + 3);
+    bool ok = true;
+    ok &= c->cand.ensure(sizeof(int32_t) * tot);
+    ok &= c->ent_tile.ensure(sizeof(int32_t) * tot);
+    ok &= c->g_ent.ensure(sizeof(int32_t) * tot);
+    ok &= c->g_tiles.ensure(sizeof(int32_t) * tot);
+    ok &= c->act.ensure(size_t(tot) * size_t(groups));
+    ok &= c->keys0.ensure(sizeof(uint32_t) * tot);
+    ok &= c->keys1.ensure(sizeof(uint32_t) * tot);
+    ok &= c->vals0.ensure(sizeof(int32_t) * tot);
+    ok &= c->vals1.ensure(sizeof(int32_t) * tot);
+    ok &= c->radix_hist.ensure(sizeof(int32_t) * 256 * nb);
+    ok &= c->radix_off.ensure(sizeof(int64_t) * (256 * nb + 1));
+    ok &= c->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>({256 * nb, T, kk})));
+    ok &= c->item_tile.ensure(sizeof(int32_t) * size_t(c->nitems > 0 ? c->nitems : 1));
+    ok &= c->fpart.ensure(sizeof(float) * 3 * size_t(c->nitems) * size_t(c->params.tile));
+    ok &= c->gitem_g.ensure(sizeof(int32_t) * size_t(c->gitems_cap > 0 ? c->gitems_cap : 1));
+    ok &= c->gpart.ensure(sizeof(float) * nm * size_t(c->gitems_cap));
+    ok &= c->gflag.ensure(sizeof(int32_t) * size_t(c->gitems_cap > 0 ? c->gitems_cap : 1));
+    return ok;
 }
 
 bool cull_reserve_front(ngd_cull *c)

@@ -75,8 +75,9 @@ __device__ __forceinline__ void rows(const float (&blk)[RecLayout<N>::PF],
 
 // Accumulates one Gaussian into f for this lane's query x.  With SKIP,
 // returns early when the whole wave can drop the pair.
-template <int N, bool SKIP>
-__device__ __forceinline__ void eval_pair(const float (&blk)[RecLayout<N>::PF],
+// Returns whether the wave kept the pair (the same for every lane).
+template <int N, bool SKIP, bool ACC = true>
+__device__ __forceinline__ bool eval_pair(const float (&blk)[RecLayout<N>::PF],
                                           const float *__restrict__ r, const float (&x)[N],
                                           bool valid, float skip, float &f0, float &f1,
                                           float &f2)
@@ -86,20 +87,23 @@ __device__ __forceinline__ void eval_pair(const float (&blk)[RecLayout<N>::PF],
     float msq = 0.0f;
     rows<N, 0, Lay::K1>(blk, r, x, d, y, msq);
     if constexpr (SKIP && Lay::K1 < N) {
-        if (ballot(valid && msq <= skip) == 0) return;
+        if (ballot(valid && msq <= skip) == 0) return false;
     }
     rows<N, Lay::K1, Lay::K2>(blk, r, x, d, y, msq);
     if constexpr (SKIP && Lay::K2 < N && Lay::K1 < Lay::K2) {
-        if (ballot(valid && msq <= skip) == 0) return;
+        if (ballot(valid && msq <= skip) == 0) return false;
     }
     rows<N, Lay::K2, N>(blk, r, x, d, y, msq);
     if constexpr (SKIP) {
-        if (ballot(valid && msq <= skip) == 0) return;
+        if (ballot(valid && msq <= skip) == 0) return false;
     }
-    const float g = __builtin_amdgcn_exp2f(-msq);
-    f0 = fmaf(g, field<N, Lay::AC + 0>(blk, r), f0);
-    f1 = fmaf(g, field<N, Lay::AC + 1>(blk, r), f1);
-    f2 = fmaf(g, field<N, Lay::AC + 2>(blk, r), f2);
+    if constexpr (ACC) {
+        const float g = __builtin_amdgcn_exp2f(-msq);
+        f0 = fmaf(g, field<N, Lay::AC + 0>(blk, r), f0);
+        f1 = fmaf(g, field<N, Lay::AC + 1>(blk, r), f1);
+        f2 = fmaf(g, field<N, Lay::AC + 2>(blk, r), f2);
+    }
+    return true;
 }
 
 template <int N>
@@ -138,13 +142,15 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t 
     }
 }
 
-template <int N>
+// OUT = false: only the keep/skip flags are written (the backward pass needs
+// them when no forward ran on this cull).
+template <int N, bool OUT>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     int64_t q, int tile, const float *__restrict__ grec, const float *__restrict__ qs,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ cand,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ item_tile,
     const int64_t *__restrict__ item_off, float skip, float *__restrict__ out,
-    float *__restrict__ part)
+    float *__restrict__ part, uint8_t *__restrict__ act)
 {
     using Lay = RecLayout<N>;
     const int64_t it = blockIdx.x;
@@ -168,10 +174,15 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     // of two register blocks.  Uniform loads may complete out of order, so
     // the wait for the current block is placed before the next block's load
     // is issued: the wait then never covers the load still in flight.
+    // keep/skip flag of each (candidate entry, 64-query group), one byte each
+    const int ngroups = (tile + kWave - 1) / kWave;
+    const int grp = s / kWave;
     float bufA[Lay::PF], bufB[Lay::PF];
     for (int64_t ch = e0; ch < e1; ch += kWave) {
         const int n = int((e1 - ch < kWave) ? e1 - ch : kWave);
-        const int vidx = (lane_id() < n) ? cand[ch + lane_id()] : 0;
+        const int lane = lane_id();
+        const int vidx = (lane < n) ? cand[ch + lane] : 0;
+        uint32_t kept = 0;
         int64_t ia = __builtin_amdgcn_readlane(vidx, 0);
         load_block<N>(bufA, grec + ia * Lay::R);
         for (int j = 0; j < n; j += 2) {
@@ -181,16 +192,20 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
                 ib = __builtin_amdgcn_readlane(vidx, j + 1);
                 load_block<N>(bufB, grec + ib * Lay::R);
             }
-            eval_pair<N, true>(bufA, grec + ia * Lay::R, x, valid, skip, f0, f1, f2);
+            if (eval_pair<N, true, OUT>(bufA, grec + ia * Lay::R, x, valid, skip, f0, f1, f2))
+                kept = (lane == j) ? 1u : kept;
             if (j + 1 >= n) break;
             __builtin_amdgcn_s_waitcnt(kWaitScalar);
             if (j + 2 < n) {
                 ia = __builtin_amdgcn_readlane(vidx, j + 2);
                 load_block<N>(bufA, grec + ia * Lay::R);
             }
-            eval_pair<N, true>(bufB, grec + ib * Lay::R, x, valid, skip, f0, f1, f2);
+            if (eval_pair<N, true, OUT>(bufB, grec + ib * Lay::R, x, valid, skip, f0, f1, f2))
+                kept = (lane == j + 1) ? 1u : kept;
         }
+        if (lane < n && grp < ngroups) act[(ch + lane) * ngroups + grp] = uint8_t(kept);
     }
+    if constexpr (!OUT) return;
     if (!valid) return;
     if (nit == 1) {
         const int64_t o = perm[p];
@@ -248,14 +263,23 @@ hipError_t culled_n(const ngd_mixture *mix, const ngd_cull *c, float *out, hipSt
     const unsigned gy = unsigned((tile + kEvalThreads - 1) / kEvalThreads);
     // skip when exp2(-M') < tau 2^-margin, i.e. M' > log2(1/tau) + margin
     const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
+    uint8_t *act = c->act.as<uint8_t>();
     if (c->nitems > 0) {
-        k_eval_items<N><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
-            c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
-            c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
-            c->item_off.as<int64_t>(), skip, out, c->fpart.as<float>());
+        if (out)
+            k_eval_items<N, true><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
+                c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
+                c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
+                c->item_off.as<int64_t>(), skip, out, c->fpart.as<float>(), act);
+        else
+            k_eval_items<N, false><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
+                c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
+                c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
+                c->item_off.as<int64_t>(), skip, nullptr, c->fpart.as<float>(), act);
     }
-    k_eval_reduce<<<dim3(unsigned(c->ntiles), gy), per, 0, s>>>(
-        c->q, tile, c->perm.as<int32_t>(), c->item_off.as<int64_t>(), c->fpart.as<float>(), out);
+    if (out)
+        k_eval_reduce<<<dim3(unsigned(c->ntiles), gy), per, 0, s>>>(
+            c->q, tile, c->perm.as<int32_t>(), c->item_off.as<int64_t>(), c->fpart.as<float>(),
+            out);
     return hipGetLastError();
 }
 

@@ -102,7 +102,11 @@ struct ngd_cull {
     ngd::DevBuf cand;          // total int32
     ngd::DevBuf g_cnt;         // k int32
     ngd::DevBuf g_off;         // k + 1 int64
-    ngd::DevBuf g_tiles;       // total int32
+    ngd::DevBuf g_tiles;       // total int32: tile of each transposed entry
+    ngd::DevBuf g_ent;         // total int32: candidate entry of each transposed entry
+    ngd::DevBuf ent_tile;      // total int32: tile of each candidate entry
+    ngd::DevBuf act;           // total x groups uint8: forward kept (entry, group)
+    mutable int64_t act_version = -1;  // mixture version the flags belong to
     ngd::DevBuf item_cnt;      // ntiles int32: forward items per tile
     ngd::DevBuf item_off;      // ntiles + 1 int64
     ngd::DevBuf item_tile;     // nitems int32
@@ -131,6 +135,7 @@ hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s);
 
 hipError_t launch_eval_dense(const ngd_mixture *mix, const float *queries, int64_t q,
                              float *out, hipStream_t s);
+// Culled forward; with out == nullptr only the keep/skip flags are written.
 hipError_t launch_eval_culled(const ngd_mixture *mix, const ngd_cull *c, float *out,
                               hipStream_t s);
 hipError_t launch_backward_dense(const ngd_mixture *mix, const float *queries, int64_t q,
@@ -149,7 +154,9 @@ size_t scan_tmp_bytes(int64_t n);
 hipError_t scan_counts(const int32_t *in, int64_t *out, int64_t n, void *tmp,
                        hipStream_t s);
 
-// Sizes the cull's buffers need before the lists are built.
+// Sizes the cull's buffers need before the lists are built, and after the
+// number of candidates is known.
 bool cull_reserve_front(ngd_cull *c);
+bool cull_reserve_lists(ngd_cull *c);
 
 }  // namespace ngd
