@@ -214,7 +214,7 @@ template <int N>
 __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
     int64_t k, int64_t q, int tile, const float *__restrict__ grec,
     const float *__restrict__ qs, const float *__restrict__ gs,
-    const int64_t *__restrict__ g_off, const int32_t *__restrict__ g_ent,
+    const int64_t *__restrict__ a_off, const int32_t *__restrict__ a_ent,
     const int32_t *__restrict__ ent_tile, const uint8_t *__restrict__ act,
     const int64_t *__restrict__ gitem_off, const int32_t *__restrict__ gitem_g,
     float *__restrict__ gpart, int32_t *__restrict__ gflag)
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
     if (it >= uniform64(gitem_off[k])) return;
     const int64_t g = uniform(gitem_g[it]);
     const int64_t j0 = uniform64(gitem_off[g]);
-    const int64_t t0 = uniform64(g_off[g]), t1 = uniform64(g_off[g + 1]);
+    const int64_t t0 = uniform64(a_off[g]), t1 = uniform64(a_off[g + 1]);
     const int64_t e0 = t0 + (it - j0) * kItemTiles;
     const int64_t e1 = (e0 + kItemTiles < t1) ? e0 + kItemTiles : t1;
     const float *__restrict__ r = grec + g * Lay::R;
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
         int ent = 0, tl = 0;
         bool kept = false;
         if (pi < npairs) {
-            ent = g_ent[e0 + pi / ngroups];
+            ent = a_ent[e0 + pi / ngroups];
             kept = act[int64_t(ent) * ngroups + pi % ngroups] != 0;
             tl = kept ? ent_tile[ent] : 0;
         }
@@ -394,11 +394,14 @@ hipError_t culled_n(const ngd_mixture *mix, ngd_cull *c, const float *grad_out, 
         k_gather_grad<<<unsigned((c->q + 255) / 256), 256, 0, s>>>(
             c->q, c->perm.as<int32_t>(), grad_out, c->gs.as<float>());
     }
+    hipError_t err = launch_backward_prepare(c, s);
+    if (err != hipSuccess) return err;
     if (c->gitems_cap > 0) {
         const unsigned blocks = unsigned((c->gitems_cap + kWavesPerBlock - 1) / kWavesPerBlock);
+        const int32_t *a_ent = c->a_ent_buf ? c->vals1.as<int32_t>() : c->vals0.as<int32_t>();
         k_backward_items<N><<<blocks, kBwdThreads, 0, s>>>(
             mix->k, c->q, c->params.tile, c->grec.as<float>(), c->qs.as<float>(),
-            c->gs.as<float>(), c->g_off.as<int64_t>(), c->g_ent.as<int32_t>(),
+            c->gs.as<float>(), c->a_off.as<int64_t>(), a_ent,
             c->ent_tile.as<int32_t>(), c->act.as<uint8_t>(), c->gitem_off.as<int64_t>(),
             c->gitem_g.as<int32_t>(), c->gpart.as<float>(), c->gflag.as<int32_t>());
     }

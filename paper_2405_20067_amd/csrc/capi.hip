@@ -310,8 +310,8 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (!cull_reserve_lists(c))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: candidate list allocation failed"));
     c->act_version = -1;
+    c->transposed = false;
     e = launch_cull_build_lists(c, s);
-    if (e == hipSuccess) e = launch_cull_build_transpose(c, s);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (lists)"));
     *inout = c;
     return NGD_OK;
@@ -346,7 +346,13 @@ int ngd_cull_export(const ngd_cull *c, int32_t *perm, int32_t *gperm, int64_t *t
         {tile_lo, c->tile_lo.p, sizeof(float) * size_t(c->ntiles * c->params.n_proj)},
         {tile_hi, c->tile_hi.p, sizeof(float) * size_t(c->ntiles * c->params.n_proj)},
     };
-    hipError_t e = hipDeviceSynchronize();
+    hipError_t e = hipSuccess;
+    if ((g_off || g_tiles) && !c->transposed) {
+        ngd_cull *cm = const_cast<ngd_cull *>(c);
+        e = launch_cull_transpose_full(cm, nullptr);
+        if (e == hipSuccess) cm->transposed = true;
+    }
+    if (e == hipSuccess) e = hipDeviceSynchronize();
     for (const Item &it : items) {
         if (e != hipSuccess) break;
         if (it.dst && it.bytes) e = hipMemcpy(it.dst, it.src, it.bytes, hipMemcpyDeviceToHost);

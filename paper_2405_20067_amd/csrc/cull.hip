@@ -175,82 +175,6 @@ __global__ __launch_bounds__(kThreads) void k_keys(int64_t n, int P,
     idx[i] = int32_t(i);
 }
 
-// ---- stable LSD radix sort (8-bit digits) ------------------------------
-constexpr int kRadixItems = 16;                        // per lane
-constexpr int kRadixPerWave = kRadixItems * kWave;     // 1024
-constexpr int kRadixPerBlock = kRadixPerWave * (kThreads / kWave);   // 4096
-
-__global__ __launch_bounds__(kThreads) void k_radix_count(int64_t n, int shift,
-                                                          const uint32_t *__restrict__ keys,
-                                                          int32_t *__restrict__ hist,
-                                                          int64_t nblocks)
-{
-    __shared__ int cnt[256];
-    cnt[threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t base = int64_t(blockIdx.x) * kRadixPerBlock;
-    for (int it = threadIdx.x; it < kRadixPerBlock; it += kThreads) {
-        const int64_t i = base + it;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1);
-    }
-    __syncthreads();
-    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
-}
-
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(
-    int64_t n, int shift, const uint32_t *__restrict__ keys_in,
-    const int32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
-    int32_t *__restrict__ vals_out, const int64_t *__restrict__ off, int64_t nblocks)
-{
-    constexpr int W = kThreads / kWave;
-    __shared__ int wcnt[W][256];
-    __shared__ int wbase[W][256];
-    const int w = threadIdx.x / kWave, lane = lane_id();
-#pragma unroll
-    for (int i = 0; i < W; ++i) wcnt[i][threadIdx.x] = 0;
-    __syncthreads();
-    const int64_t wstart = int64_t(blockIdx.x) * kRadixPerBlock + int64_t(w) * kRadixPerWave;
-    for (int it = 0; it < kRadixItems; ++it) {
-        const int64_t i = wstart + int64_t(it) * kWave + lane;
-        if (i < n) atomicAdd(&wcnt[w][(keys_in[i] >> shift) & 0xffu], 1);
-    }
-    __syncthreads();
-    {
-        const int d = threadIdx.x;
-        int run = int(off[int64_t(d) * nblocks + blockIdx.x]);
-#pragma unroll
-        for (int i = 0; i < W; ++i) {
-            wbase[i][d] = run;
-            run += wcnt[i][d];
-        }
-    }
-    __syncthreads();
-    for (int it = 0; it < kRadixItems; ++it) {
-        const int64_t i = wstart + int64_t(it) * kWave + lane;
-        const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
-        const int d = int((key >> shift) & 0xffu);
-        uint64_t match = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool bit = (d >> b) & 1;
-            const uint64_t m = ballot(valid && bit);
-            match &= bit ? m : ~m;
-        }
-        if (valid) {
-            const int rank = __popcll(match & lanemask_lt());
-            const int64_t dest = int64_t(wbase[w][d]) + rank;
-            if (dest < n) {
-                keys_out[dest] = key;
-                vals_out[dest] = vals_in[i];
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-        if (valid && ((match >> lane) >> 1) == 0) wbase[w][d] += __popcll(match);
-        __builtin_amdgcn_wave_barrier();
-    }
-}
-
 // ---- tiles ---------------------------------------------------------------
 template <int N, int PMAX>
 __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P,
@@ -326,6 +250,9 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gather(
 }
 
 // ---- the interval test (Eq. 5 per tile) -----------------------------------
+// One wave per chunk of 64 sorted Gaussians (lane = Gaussian, its projected
+// means and thresholds in registers) walks a range of tiles with the tile
+// bounds wave-uniform; it leaves a tile as soon as no lane survives.
 template <int PMAX>
 __global__ __launch_bounds__(kThreads) void k_cull_test(
     int64_t k, int64_t ntiles, int64_t tpad, int P, int tiles_per_wave,
@@ -499,35 +426,12 @@ template <typename T> inline unsigned nblk(T n, int per)
     return unsigned((int64_t(n) + per - 1) / per);
 }
 
-// Sorts (keys, vals) by the low `nbits` bits of the keys; returns which
-// ping-pong buffer holds the result (0 or 1).
-hipError_t radix_sort(int64_t n, int nbits, uint32_t *k0, uint32_t *k1, int32_t *v0,
-                      int32_t *v1, int32_t *hist, int64_t *off, void *scan_tmp, hipStream_t s,
-                      int *which)
-{
-    *which = 0;
-    if (n == 0) return hipSuccess;
-    const int64_t nb = (n + kRadixPerBlock - 1) / kRadixPerBlock;
-    uint32_t *kin = k0, *kout = k1;
-    int32_t *vin = v0, *vout = v1;
-    for (int shift = 0; shift < nbits; shift += 8) {
-        k_radix_count<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, shift, kin, hist, nb);
-        hipError_t e = scan_counts(hist, off, 256 * nb, scan_tmp, s);
-        if (e != hipSuccess) return e;
-        k_radix_scatter<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, shift, kin, vin, kout, vout,
-                                                               off, nb);
-        std::swap(kin, kout);
-        std::swap(vin, vout);
-        *which ^= 1;
-    }
-    return hipGetLastError();
-}
-
 // items per CSR row -> exclusive offsets (n + 1)
-hipError_t launch_items(int64_t n, const int64_t *off, int per, int32_t *cnt, int64_t *ioff,
-                        void *scan_tmp, hipStream_t s)
+hipError_t launch_items(int64_t n, const int64_t *off, int per, DevBuf &cnt, DevBuf &ioff,
+                        DevBuf &scan_tmp, hipStream_t s)
 {
-    if (n > 0) k_item_count<<<nblk(n, kThreads), kThreads, 0, s>>>(n, off, per, cnt);
+    if (cnt.cap < sizeof(int32_t) * size_t(n)) return hipErrorInvalidValue;
+    if (n > 0) k_item_count<<<nblk(n, kThreads), kThreads, 0, s>>>(n, off, per, cnt.as<int32_t>());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     return scan_counts(cnt, ioff, n, scan_tmp, s);
@@ -566,9 +470,8 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
                                                       c->qrange.as<float>(), c->params.key_proj,
                                                       c->params.key_bits, c->keys0.as<uint32_t>(),
                                                       c->vals0.as<int32_t>());
-        e = radix_sort(q, nbits, c->keys0.as<uint32_t>(), c->keys1.as<uint32_t>(),
-                       c->vals0.as<int32_t>(), c->vals1.as<int32_t>(), c->radix_hist.as<int32_t>(),
-                       c->radix_off.as<int64_t>(), c->scan_tmp.p, s, &which);
+        e = radix_sort(q, nullptr, nbits, c->keys0, c->keys1, c->vals0, c->vals1, c->radix_hist,
+                       c->radix_off, c->scan_tmp, s, &which);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(c->perm.p, which ? c->vals1.p : c->vals0.p, sizeof(int32_t) * q,
                            hipMemcpyDeviceToDevice, s);
@@ -580,9 +483,8 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
                                                       c->qrange.as<float>(), c->params.key_proj,
                                                       c->params.key_bits, c->keys0.as<uint32_t>(),
                                                       c->vals0.as<int32_t>());
-        e = radix_sort(k, nbits, c->keys0.as<uint32_t>(), c->keys1.as<uint32_t>(),
-                       c->vals0.as<int32_t>(), c->vals1.as<int32_t>(), c->radix_hist.as<int32_t>(),
-                       c->radix_off.as<int64_t>(), c->scan_tmp.p, s, &which);
+        e = radix_sort(k, nullptr, nbits, c->keys0, c->keys1, c->vals0, c->vals1, c->radix_hist,
+                       c->radix_off, c->scan_tmp, s, &which);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(c->gperm.p, which ? c->vals1.p : c->vals0.p, sizeof(int32_t) * k,
                            hipMemcpyDeviceToDevice, s);
@@ -613,12 +515,9 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         if (c->ntiles > 0)
             k_zero_i32<<<nblk(c->ntiles, kThreads), kThreads, 0, s>>>(c->tile_cnt.as<int32_t>(),
                                                                      c->ntiles);
-        e = scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
-                        c->scan_tmp.p, s);
+        e = scan_counts(c->tile_cnt, c->tile_off, c->ntiles, c->scan_tmp, s);
         if (e != hipSuccess) return e;
-        return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands,
-                            c->item_cnt.as<int32_t>(), c->item_off.as<int64_t>(), c->scan_tmp.p,
-                            s);
+        return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands, c->item_cnt, c->item_off, c->scan_tmp, s);
     }
     // interval test
     const int tiles_per_wave = 512;
@@ -642,11 +541,9 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         c->ntiles, c->nseg, c->seg_cnt.as<int32_t>(), c->tile_cnt.as<int32_t>(),
         reinterpret_cast<unsigned long long *>(c->stats.as<int64_t>() + 1));
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    e = scan_counts(c->tile_cnt.as<int32_t>(), c->tile_off.as<int64_t>(), c->ntiles,
-                    c->scan_tmp.p, s);
+    e = scan_counts(c->tile_cnt, c->tile_off, c->ntiles, c->scan_tmp, s);
     if (e != hipSuccess) return e;
-    return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands,
-                        c->item_cnt.as<int32_t>(), c->item_off.as<int64_t>(), c->scan_tmp.p, s);
+    return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands, c->item_cnt, c->item_off, c->scan_tmp, s);
 }
 
 }  // namespace
@@ -679,7 +576,7 @@ hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s)
+hipError_t launch_cull_transpose_full(ngd_cull *c, hipStream_t s)
 {
     const int64_t k = c->k;
     hipError_t e;
@@ -692,9 +589,8 @@ hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s)
         int nbits = 0;
         while ((int64_t(1) << nbits) < k) ++nbits;
         int which = 0;
-        e = radix_sort(c->total, nbits, c->keys0.as<uint32_t>(), c->keys1.as<uint32_t>(),
-                       c->vals0.as<int32_t>(), c->vals1.as<int32_t>(),
-                       c->radix_hist.as<int32_t>(), c->radix_off.as<int64_t>(), c->scan_tmp.p, s,
+        e = radix_sort(c->total, nullptr, nbits, c->keys0, c->keys1, c->vals0, c->vals1, c->radix_hist,
+                       c->radix_off, c->scan_tmp, s,
                        &which);
         if (e != hipSuccess) return e;
         e = hipMemcpyAsync(c->g_ent.p, which ? c->vals1.p : c->vals0.p,
@@ -703,10 +599,77 @@ hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s)
         k_ent_gather<<<nblk(c->total, kThreads), kThreads, 0, s>>>(
             c->total, c->g_ent.as<int32_t>(), c->ent_tile.as<int32_t>(), c->g_tiles.as<int32_t>());
     }
-    e = scan_counts(c->g_cnt.as<int32_t>(), c->g_off.as<int64_t>(), k, c->scan_tmp.p, s);
+    e = scan_counts(c->g_cnt, c->g_off, k, c->scan_tmp, s);
     if (e != hipSuccess) return e;
-    e = launch_items(k, c->g_off.as<int64_t>(), kItemTiles, c->gitem_cnt.as<int32_t>(),
-                     c->gitem_off.as<int64_t>(), c->scan_tmp.p, s);
+    return hipGetLastError();
+}
+
+namespace {
+
+// ---- backward preparation -------------------------------------------------
+// Entries with at least one kept query group, compacted in entry order and
+// then stably sorted by Gaussian: each Gaussian's kept entries in ascending
+// tile order, without transposing the (much longer) full candidate lists.
+__global__ __launch_bounds__(kThreads) void k_eflag(int64_t total, int groups,
+                                                    const uint8_t *__restrict__ act,
+                                                    int32_t *__restrict__ eflag)
+{
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (e >= total) return;
+    int any = 0;
+    for (int g = 0; g < groups; ++g) any |= act[e * groups + g];
+    eflag[e] = any ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_ecompact(int64_t total,
+                                                       const int32_t *__restrict__ eflag,
+                                                       const int64_t *__restrict__ eoff,
+                                                       const int32_t *__restrict__ cand,
+                                                       uint32_t *__restrict__ keys,
+                                                       int32_t *__restrict__ vals,
+                                                       int32_t *__restrict__ a_cnt)
+{
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (e >= total || !eflag[e]) return;
+    const int64_t o = eoff[e];
+    const int32_t g = cand[e];
+    keys[o] = uint32_t(g);
+    vals[o] = int32_t(e);
+    atomicAdd(&a_cnt[g], 1);
+}
+
+}  // namespace
+
+hipError_t launch_backward_prepare(ngd_cull *c, hipStream_t s)
+{
+    const int64_t k = c->k, total = c->total;
+    const int groups = (c->params.tile + kWave - 1) / kWave;
+    if (k > 0) k_zero_i32<<<nblk(k, kThreads), kThreads, 0, s>>>(c->a_cnt.as<int32_t>(), k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (total > 0) {
+        k_eflag<<<nblk(total, kThreads), kThreads, 0, s>>>(total, groups, c->act.as<uint8_t>(),
+                                                           c->eflag.as<int32_t>());
+        e = scan_counts(c->eflag, c->eoff, total, c->scan_tmp, s);
+        if (e != hipSuccess) return e;
+        k_ecompact<<<nblk(total, kThreads), kThreads, 0, s>>>(
+            total, c->eflag.as<int32_t>(), c->eoff.as<int64_t>(), c->cand.as<int32_t>(),
+            c->keys0.as<uint32_t>(), c->vals0.as<int32_t>(), c->a_cnt.as<int32_t>());
+        int nbits = 0;
+        while ((int64_t(1) << nbits) < k) ++nbits;
+        int which = 0;
+        // the kept-entry count stays on the device: eoff[total]
+        e = radix_sort(total, c->eoff.as<int64_t>() + total, nbits, c->keys0, c->keys1, c->vals0, c->vals1, c->radix_hist,
+                       c->radix_off, c->scan_tmp, s,
+                       &which);
+        if (e != hipSuccess) return e;
+        c->a_ent_buf = which;
+    } else {
+        c->a_ent_buf = 0;
+    }
+    e = scan_counts(c->a_cnt, c->a_off, k, c->scan_tmp, s);
+    if (e != hipSuccess) return e;
+    e = launch_items(k, c->a_off.as<int64_t>(), kItemTiles, c->gitem_cnt, c->gitem_off, c->scan_tmp, s);
     if (e != hipSuccess) return e;
     if (k > 0 && c->gitems_cap > 0)
         k_item_fill<<<nblk(k, kThreads), kThreads, 0, s>>>(k, c->gitem_off.as<int64_t>(),
@@ -729,13 +692,17 @@ bool cull_reserve_lists(ngd_cull *c)
     ok &= c->g_ent.ensure(sizeof(int32_t) * tot);
     ok &= c->g_tiles.ensure(sizeof(int32_t) * tot);
     ok &= c->act.ensure(size_t(tot) * size_t(groups));
+    ok &= c->eflag.ensure(sizeof(int32_t) * tot);
+    ok &= c->eoff.ensure(sizeof(int64_t) * (tot + 1));
+    ok &= c->a_cnt.ensure(sizeof(int32_t) * kk);
+    ok &= c->a_off.ensure(sizeof(int64_t) * (kk + 1));
     ok &= c->keys0.ensure(sizeof(uint32_t) * tot);
     ok &= c->keys1.ensure(sizeof(uint32_t) * tot);
     ok &= c->vals0.ensure(sizeof(int32_t) * tot);
     ok &= c->vals1.ensure(sizeof(int32_t) * tot);
     ok &= c->radix_hist.ensure(sizeof(int32_t) * 256 * nb);
     ok &= c->radix_off.ensure(sizeof(int64_t) * (256 * nb + 1));
-    ok &= c->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>({256 * nb, T, kk})));
+    ok &= c->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>({256 * nb, T, kk, tot})));
     ok &= c->item_tile.ensure(sizeof(int32_t) * size_t(c->nitems > 0 ? c->nitems : 1));
     ok &= c->fpart.ensure(sizeof(float) * 3 * size_t(c->nitems) * size_t(c->params.tile));
     ok &= c->gitem_g.ensure(sizeof(int32_t) * size_t(c->gitems_cap > 0 ? c->gitems_cap : 1));

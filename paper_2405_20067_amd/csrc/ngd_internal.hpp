@@ -107,6 +107,13 @@ struct ngd_cull {
     ngd::DevBuf ent_tile;      // total int32: tile of each candidate entry
     ngd::DevBuf act;           // total x groups uint8: forward kept (entry, group)
     mutable int64_t act_version = -1;  // mixture version the flags belong to
+    bool transposed = false;   // g_off / g_tiles hold the full transposed lists
+    // backward: the entries with a kept group, grouped by Gaussian
+    ngd::DevBuf eflag;         // total int32: entry has a kept group
+    ngd::DevBuf eoff;          // total + 1 int64
+    ngd::DevBuf a_cnt;         // k int32
+    ngd::DevBuf a_off;         // k + 1 int64
+    int a_ent_buf = 0;         // which sort buffer (vals0 / vals1) holds them
     ngd::DevBuf item_cnt;      // ntiles int32: forward items per tile
     ngd::DevBuf item_off;      // ntiles + 1 int64
     ngd::DevBuf item_tile;     // nitems int32
@@ -131,7 +138,9 @@ hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *fact
 hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix,
                                    const float *queries, hipStream_t s);
 hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s);
-hipError_t launch_cull_build_transpose(ngd_cull *c, hipStream_t s);
+// Gaussian -> tile lists of all candidates (g_off, g_tiles); built on
+// demand for ngd_cull_export.
+hipError_t launch_cull_transpose_full(ngd_cull *c, hipStream_t s);
 
 hipError_t launch_eval_dense(const ngd_mixture *mix, const float *queries, int64_t q,
                              float *out, hipStream_t s);
@@ -145,14 +154,30 @@ hipError_t launch_backward_culled(const ngd_mixture *mix, ngd_cull *c,
                                   const float *grad_out, float *g_mean, float *g_factor,
                                   float *g_weight, float *g_colour, hipStream_t s);
 hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
+// Groups the entries with a kept query group by Gaussian (a_cnt, a_off, the
+// sorted entries in vals0/vals1) and builds the backward work items.
+hipError_t launch_backward_prepare(ngd_cull *c, hipStream_t s);
 hipError_t launch_l2_loss(const float *f, const float *target, int64_t q, float *loss,
                           float *grad, float *partials, int nparts, hipStream_t s);
 
+// Stable LSD radix sort of (key, value) pairs by the low nbits of the keys,
+// kRadixPerBlock keys per block.  n is the count, or an upper bound when
+// n_dev (a device count) is given.  Buffers: keys/vals ping-pong of n,
+// hist 256 x blocks int32, off 256 x blocks + 1 int64, scan_tmp for a scan
+// of 256 x blocks.  *which tells which ping-pong buffer holds the result.
+constexpr int kRadixPerBlock = 4096;
+// Every buffer's capacity is checked on the host first (hipErrorInvalidValue
+// when one is too small).
+hipError_t radix_sort(int64_t n, const int64_t *n_dev, int nbits, DevBuf &k0, DevBuf &k1,
+                      DevBuf &v0, DevBuf &v1, DevBuf &hist, DevBuf &off, DevBuf &scan_tmp,
+                      hipStream_t s, int *which);
+
 // Exclusive scan of `n` int32 counts into n + 1 int64 offsets (out[n] is
 // the total).  `tmp` must hold scan_tmp_bytes(n) bytes.
+// The capacities of in (n int32), out (n + 1 int64) and tmp are checked on
+// the host first (hipErrorInvalidValue when one is too small).
 size_t scan_tmp_bytes(int64_t n);
-hipError_t scan_counts(const int32_t *in, int64_t *out, int64_t n, void *tmp,
-                       hipStream_t s);
+hipError_t scan_counts(const DevBuf &in, DevBuf &out, int64_t n, DevBuf &tmp, hipStream_t s);
 
 // Sizes the cull's buffers need before the lists are built, and after the
 // number of candidates is known.

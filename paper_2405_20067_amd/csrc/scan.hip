@@ -161,8 +161,16 @@ size_t scan_tmp_bytes(int64_t n)
     return size_t(nb > 0 ? nb : 1) * sizeof(int64_t);
 }
 
-hipError_t scan_counts(const int32_t *in, int64_t *out, int64_t n, void *tmp, hipStream_t s)
+hipError_t scan_counts(const DevBuf &in_buf, DevBuf &out_buf, int64_t n, DevBuf &tmp_buf,
+                       hipStream_t s)
 {
+    // every buffer must hold what the launches below touch
+    if (n < 0 || out_buf.cap < sizeof(int64_t) * size_t(n + 1) ||
+        in_buf.cap < sizeof(int32_t) * size_t(n) || tmp_buf.cap < scan_tmp_bytes(n))
+        return hipErrorInvalidValue;
+    const int32_t *in = in_buf.as<int32_t>();
+    int64_t *out = out_buf.as<int64_t>();
+    void *tmp = tmp_buf.p;
     if (n == 0) {
         k_fill_i64<<<1, 64, 0, s>>>(out, 1, 0);
         return hipGetLastError();
