@@ -29,6 +29,23 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3   # published dense FP32 vector peak (packed)
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_10d_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2405_20067_amd", "csrc", "eval.hip")
+
+
+def stage_flops(n: int):
+    """float32 flops one lane spends on each stage of a (query, Gaussian) pair
+    in the forward kernel: rows [a, b) of y = S'(x - m) cost, per row r,
+    1 subtraction, 1 multiply + r fmas, and 1 fma into the squared norm;
+    the kept pair adds exp2 and 3 fmas.  Stage boundaries 3 and 6."""
+    k1, k2 = min(3, n), min(6, n)
+    rows = lambda a, b: sum(1 + 1 + 2 * r + 2 for r in range(a, b))
+    return rows(0, k1), rows(k1, k2), rows(k2, n), 1 + 6
+
+
+def source_hash(path):
+    import hashlib
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
 
 
 def log(*a):
@@ -83,7 +100,9 @@ def cpu_baseline(w, mix, x, budget_s: float):
         oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], xs, gs)
         t2 = time.perf_counter()
         return t1 - t0, t2 - t1
-    probe = 16
+    # probe with enough queries to keep every core busy, then scale the
+    # sample to the time budget
+    probe = 256
     a, b = run(probe)
     nq = int(max(probe, min(w.q, probe * budget_s / max(a + b, 1e-6))))
     tf, tb = run(nq)
@@ -105,7 +124,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3 (3 steps, 1 warmup, no CPU/dense legs) "
+                         "plus one 256 MiB device copy to calibrate memory counters")
     args = ap.parse_args()
+    if args.profile:
+        args.steps, args.warmup, args.no_cpu_baseline, args.no_dense = 3, 1, True, True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(run with --gpus 1)", file=sys.stderr)
@@ -193,9 +217,37 @@ def main():
             f"bwd {dense['backward_ms']:.1f} ms")
 
     fwd_pairs_s = cand_pairs / (stage_ms["forward"] * 1e-3)
-    roofline = dict(
-        bound="alu", kernel="k_eval_culled (forward)",
-        achieved=None, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=None, traffic=None)
+    roofline = None
+    work = None
+    if w.culled:
+        # the forward's executed work, counted by the same kernel on the same cull
+        cnt = ngd.eval_stats(m, cull, dev["x"])
+        f1, f2, f3, f4 = stage_flops(w.n)
+        lane_flops = 64 * (f1 * cnt["examined"] + f2 * cnt["pass1"] + f3 * cnt["pass2"]
+                           + f4 * cnt["kept"])
+        t_fwd = stage_ms["forward"] * 1e-3
+        achieved = lane_flops / t_fwd / 1e12
+        traffic = None
+        if os.path.exists(TRAFFIC_FILE):
+            tr = json.load(open(TRAFFIC_FILE))
+            if tr.get("source_sha256_16") == source_hash(KERNEL_SRC) and \
+                    tr.get("workload") == w.name:
+                traffic = tr.get("hbm_bytes_per_launch")
+        roofline = dict(
+            bound="alu", kernel="forward: k_eval_items + k_eval_reduce (ngd_eval)",
+            achieved=achieved, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+            frac=achieved / FP32_VALU_PEAK_TFLOPS, traffic=traffic,
+            units=dict(group_candidate_pairs=cnt, flops_per_lane_per_stage=[f1, f2, f3, f4],
+                       lanes_per_pair=64, flops_per_launch=lane_flops,
+                       launch_ms=stage_ms["forward"]))
+        work = cnt
+        log(f"forward work: {cnt}; {achieved:.1f} TFLOP/s executed")
+    if args.profile:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("calibration copy: 268435456 bytes read, 268435456 bytes written")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -218,6 +270,8 @@ def main():
                   survivor_fraction=st["total"] / max(st["ntiles"] * w.k, 1)),
         candidate_pairs_per_s_forward=fwd_pairs_s,
         dense_fp32=dense, roofline=roofline, cpu_baseline=cpu)
+    if cpu is not None:
+        out["speedup_vs_cpu_oracle"] = value / cpu["value"]
     print(json.dumps(out), flush=True)
 
 

@@ -174,6 +174,16 @@ int ngd_cull_destroy(ngd_cull *cull);
 int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
              int64_t q, int precision, float *out, void *stream);
 
+/* Work counters of the culled forward, for measurement (synchronises).
+ * Runs the forward kernel on the same cull in a counting mode (no colours
+ * written) and returns in counts (host, 4 x int64): the (64-query group,
+ * candidate) pairs examined, those that passed the first and the second
+ * Mahalanobis-bound check (marginals over the first 3 and 6 coordinates),
+ * and those kept (evaluated with exp and accumulated).  `cull` and
+ * `queries`/q as for ngd_eval. */
+int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
+                   int64_t q, int64_t *counts, void *stream);
+
 /* Gradients of a loss l given grad_out = dl/df (device, q x 3), with respect
  * to every Gaussian's mean, factor, weight and colour (the analytic
  * gradients of Sec. 4.1; no query gradient):

@@ -410,6 +410,38 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
     return NGD_OK;
 }
 
+int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
+                   int64_t q, int64_t *counts, void *stream)
+{
+    if (!mix || !cull || !counts) return fail(NGD_E_INVAL, "ngd_eval_stats: NULL argument");
+    if (q < 0 || q >= (int64_t(1) << 31))
+        return fail(NGD_E_INVAL, "ngd_eval_stats: q=%lld outside [0, 2^31)", (long long)q);
+    const int rc = check_cull("ngd_eval_stats", mix, cull, queries, q);
+    if (rc) return rc;
+    for (int i = 0; i < 4; ++i) counts[i] = 0;
+    if (q == 0 || mix->k == 0 || cull->nitems == 0) return NGD_OK;
+    static std::mutex mu;
+    static DevBuf buf[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "ngd_eval_stats");
+    if (dev < 0 || dev >= 64) return fail(NGD_E_INVAL, "ngd_eval_stats: device %d", dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!buf[dev].ensure(4 * sizeof(unsigned long long)))
+        return fail(NGD_E_NOMEM, "ngd_eval_stats: workspace allocation failed");
+    unsigned long long host[4] = {0, 0, 0, 0};
+    e = hipMemcpyAsync(buf[dev].p, host, sizeof(host), hipMemcpyHostToDevice, S(stream));
+    if (e == hipSuccess)
+        e = launch_eval_stats(mix, cull, buf[dev].as<unsigned long long>(), S(stream));
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(host, buf[dev].p, sizeof(host), hipMemcpyDeviceToHost, S(stream));
+    if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
+    if (e != hipSuccess) return hip_fail(e, "ngd_eval_stats");
+    cull->act_version = mix->version;
+    for (int i = 0; i < 4; ++i) counts[i] = int64_t(host[i]);
+    return NGD_OK;
+}
+
 int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
                       int64_t q, const float *grad_out, int precision, float *g_mean,
                       float *g_factor, float *g_weight, float *g_colour, void *stream)

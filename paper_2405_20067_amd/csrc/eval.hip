@@ -75,12 +75,14 @@ __device__ __forceinline__ void rows(const float (&blk)[RecLayout<N>::PF],
 
 // Accumulates one Gaussian into f for this lane's query x.  With SKIP,
 // returns early when the whole wave can drop the pair.
-// Returns whether the wave kept the pair (the same for every lane).
-template <int N, bool SKIP, bool ACC = true>
+// Returns whether the wave kept the pair (the same for every lane).  With
+// COUNT, st[0..2] count the pairs that passed the first and second checks
+// and were kept (wave-uniform counters).
+template <int N, bool SKIP, bool ACC = true, bool COUNT = false>
 __device__ __forceinline__ bool eval_pair(const float (&blk)[RecLayout<N>::PF],
                                           const float *__restrict__ r, const float (&x)[N],
                                           bool valid, float skip, float &f0, float &f1,
-                                          float &f2)
+                                          float &f2, uint32_t *st = nullptr)
 {
     using Lay = RecLayout<N>;
     float d[N], y[N];
@@ -89,14 +91,17 @@ __device__ __forceinline__ bool eval_pair(const float (&blk)[RecLayout<N>::PF],
     if constexpr (SKIP && Lay::K1 < N) {
         if (ballot(valid && msq <= skip) == 0) return false;
     }
+    if constexpr (COUNT) ++st[0];
     rows<N, Lay::K1, Lay::K2>(blk, r, x, d, y, msq);
     if constexpr (SKIP && Lay::K2 < N && Lay::K1 < Lay::K2) {
         if (ballot(valid && msq <= skip) == 0) return false;
     }
+    if constexpr (COUNT) ++st[1];
     rows<N, Lay::K2, N>(blk, r, x, d, y, msq);
     if constexpr (SKIP) {
         if (ballot(valid && msq <= skip) == 0) return false;
     }
+    if constexpr (COUNT) ++st[2];
     if constexpr (ACC) {
         const float g = __builtin_amdgcn_exp2f(-msq);
         f0 = fmaf(g, field<N, Lay::AC + 0>(blk, r), f0);
@@ -143,14 +148,17 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t 
 }
 
 // OUT = false: only the keep/skip flags are written (the backward pass needs
-// them when no forward ran on this cull).
-template <int N, bool OUT>
+// them when no forward ran on this cull).  COUNT (with OUT = false): the
+// flags are written and the stage counters of every wave are added to
+// stats[0..3] = (pairs examined, passed check 1, passed check 2, kept).
+template <int N, bool OUT, bool COUNT = false>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     int64_t q, int tile, const float *__restrict__ grec, const float *__restrict__ qs,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ cand,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ item_tile,
     const int64_t *__restrict__ item_off, float skip, float *__restrict__ out,
-    float *__restrict__ part, uint8_t *__restrict__ act)
+    float *__restrict__ part, uint8_t *__restrict__ act,
+    unsigned long long *__restrict__ stats = nullptr)
 {
     using Lay = RecLayout<N>;
     const int64_t it = blockIdx.x;
@@ -178,6 +186,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     const int ngroups = (tile + kWave - 1) / kWave;
     const int grp = s / kWave;
     float bufA[Lay::PF], bufB[Lay::PF];
+    uint32_t st[3] = {0u, 0u, 0u};
     for (int64_t ch = e0; ch < e1; ch += kWave) {
         const int n = int((e1 - ch < kWave) ? e1 - ch : kWave);
         const int lane = lane_id();
@@ -192,7 +201,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
                 ib = __builtin_amdgcn_readlane(vidx, j + 1);
                 load_block<N>(bufB, grec + ib * Lay::R);
             }
-            if (eval_pair<N, true, OUT>(bufA, grec + ia * Lay::R, x, valid, skip, f0, f1, f2))
+            if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0, f1,
+                                               f2, st))
                 kept = (lane == j) ? 1u : kept;
             if (j + 1 >= n) break;
             __builtin_amdgcn_s_waitcnt(kWaitScalar);
@@ -200,10 +210,19 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
                 ia = __builtin_amdgcn_readlane(vidx, j + 2);
                 load_block<N>(bufA, grec + ia * Lay::R);
             }
-            if (eval_pair<N, true, OUT>(bufB, grec + ib * Lay::R, x, valid, skip, f0, f1, f2))
+            if (eval_pair<N, true, OUT, COUNT>(bufB, grec + ib * Lay::R, x, valid, skip, f0, f1,
+                                               f2, st))
                 kept = (lane == j + 1) ? 1u : kept;
         }
         if (lane < n && grp < ngroups) act[(ch + lane) * ngroups + grp] = uint8_t(kept);
+    }
+    if constexpr (COUNT) {
+        if (lane_id() == 0 && grp < ngroups) {
+            atomicAdd(&stats[0], static_cast<unsigned long long>(e1 - e0));
+            atomicAdd(&stats[1], static_cast<unsigned long long>(st[0]));
+            atomicAdd(&stats[2], static_cast<unsigned long long>(st[1]));
+            atomicAdd(&stats[3], static_cast<unsigned long long>(st[2]));
+        }
     }
     if constexpr (!OUT) return;
     if (!valid) return;
@@ -283,7 +302,37 @@ hipError_t culled_n(const ngd_mixture *mix, const ngd_cull *c, float *out, hipSt
     return hipGetLastError();
 }
 
+template <int N>
+hipError_t stats_n(const ngd_cull *c, unsigned long long *stats, hipStream_t s)
+{
+    const int tile = c->params.tile;
+    const int per = tile < kEvalThreads ? (tile + 63) / 64 * 64 : kEvalThreads;
+    const unsigned gy = unsigned((tile + kEvalThreads - 1) / kEvalThreads);
+    const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
+    if (c->nitems > 0)
+        k_eval_items<N, false, true><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
+            c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
+            c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
+            c->item_off.as<int64_t>(), skip, nullptr, c->fpart.as<float>(), c->act.as<uint8_t>(),
+            stats);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_eval_stats(const ngd_mixture *mix, const ngd_cull *c,
+                             unsigned long long *stats, hipStream_t s)
+{
+    if (c->q == 0 || c->ntiles == 0) return hipSuccess;
+    switch (mix->n) {
+#define NGD_CASE(NN) \
+    case NN: return stats_n<NN>(c, stats, s);
+        NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
+        NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
+#undef NGD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_eval_dense(const ngd_mixture *mix, const float *queries, int64_t q, float *out,
                              hipStream_t s)

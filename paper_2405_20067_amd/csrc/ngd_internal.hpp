@@ -144,6 +144,10 @@ hipError_t launch_cull_transpose_full(ngd_cull *c, hipStream_t s);
 
 hipError_t launch_eval_dense(const ngd_mixture *mix, const float *queries, int64_t q,
                              float *out, hipStream_t s);
+// Counting run of the culled forward (flags written, no colours): adds
+// (pairs examined, passed check 1, passed check 2, kept) to stats[0..3].
+hipError_t launch_eval_stats(const ngd_mixture *mix, const ngd_cull *c,
+                             unsigned long long *stats, hipStream_t s);
 // Culled forward; with out == nullptr only the keep/skip flags are written.
 hipError_t launch_eval_culled(const ngd_mixture *mix, const ngd_cull *c, float *out,
                               hipStream_t s);

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "NgdError", "CullParams", "Mixture", "Cull", "lib", "LIB_PATH",
-    "eval_mixture", "eval_backward", "l2_loss", "FP32",
+    "eval_mixture", "eval_backward", "eval_stats", "l2_loss", "FP32",
     "E_INVAL", "E_SINGULAR", "E_HIP", "E_NOMEM", "E_STALE",
 ]
 
@@ -69,6 +69,9 @@ _SIGS = [
     ("ngd_eval", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
       ctypes.c_void_p, ctypes.c_void_p]),
+    ("ngd_eval_stats", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+      ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     ("ngd_eval_backward", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
       ctypes.c_int] + [ctypes.c_void_p] * 5),
@@ -251,6 +254,16 @@ def eval_mixture(mix: Mixture, cull: Cull | None, queries, out=None, precision=F
                           _ptr(queries, "queries", q * mix.n), q, int(precision),
                           _ptr(out, "out", q * 3), _stream(stream)))
     return out
+
+
+def eval_stats(mix: Mixture, cull: Cull, queries, stream=None):
+    """Work counters of the culled forward: dict(examined, pass1, pass2, kept),
+    counted in (64-query group, candidate) pairs."""
+    q = queries.numel() // mix.n
+    counts = (ctypes.c_int64 * 4)()
+    _check(lib().ngd_eval_stats(mix.handle, cull.handle, _ptr(queries, "queries", q * mix.n),
+                                q, counts, _stream(stream)))
+    return dict(examined=counts[0], pass1=counts[1], pass2=counts[2], kept=counts[3])
 
 
 def eval_backward(mix: Mixture, cull: Cull | None, queries, grad_out, grads=None,
