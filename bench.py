@@ -255,15 +255,15 @@ def main():
         cpu = cpu_baseline(w, mix, x, args.cpu_seconds)
 
     out = dict(
-        metric="Gaussian-query evals/sec, culled fwd+bwd 10-D",
+        metric="Gaussian-query evals/sec, culled fwd+bwd 10-D, + % HBM/MFMA roofline",
         value=value, unit="Gaussian-query evals/s (dense-equivalent Q*K per step time)",
         n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
         higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
         data="synthetic",
         config=dict(workload=w.name, description=w.description, n=w.n, k=w.k, q=w.q,
                     k_target=w.k_target, near_frac=w.near_frac, n_proj=params.n_proj,
-                    tau=params.tau, tile=params.tile, key_proj=params.key_proj,
-                    key_bits=params.key_bits),
+                    tau=params.tau, tile=params.tile,
+                    tiling="k-d" if params.tiling == 0 else "morton"),
         stages_ms=stage_ms,
         cull=dict(candidates=st["total"], ntiles=st["ntiles"], max_per_tile=st["max_per_tile"],
                   candidate_pairs=cand_pairs,

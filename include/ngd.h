@@ -66,8 +66,14 @@ typedef struct {
                        half-width is kappa sigma_r with kappa^2 = 2 ln(1/tau)
                        (tau = exp(-4.5) gives the paper's 3 sigma). (1e-4) */
     int tile;       /* queries per tile: 256 (the paper's 16 x 16 pixel tile) */
-    int key_proj;   /* projections in the query locality key, 0..n_proj (16) */
-    int key_bits;   /* bits per key projection; key_proj*key_bits <= 32 (2) */
+    int key_proj;   /* tiling 1: projections in the locality key, 0..n_proj (16) */
+    int key_bits;   /* tiling 1: bits per key projection; key_proj*key_bits <= 32 (2) */
+    int tiling;     /* how tiles are formed from queries without an image (0):
+                       0  k-d: recursive exact-rank splits of the queries on the
+                          projection of largest extent, down to runs of `tile`;
+                          Gaussians ordered the same way in runs of 64
+                       1  Morton: stable sort on key_proj projections quantised
+                          to key_bits each, bits interleaved */
 } ngd_cull_params;
 
 /* Message for the last failing call on this thread ("" if none). */
@@ -129,8 +135,8 @@ int ngd_mixture_destroy(ngd_mixture *mix);
  *   proj    host, p->n_proj x n: the random projection vectors r_j (any
  *           length; Eq. 5 does not depend on it).  Copied.
  * Steps on the device: query and mean projections (Eq. 3), projected
- * variances in float64 (Eq. 4), locality keys and stable radix sorts of
- * queries and Gaussians, tiles of p->tile consecutive sorted queries with
+ * variances in float64 (Eq. 4), a locality order of queries and Gaussians
+ * (p->tiling), tiles of p->tile consecutive ordered queries with
  * their projected bounds, the (tile, Gaussian) interval test (Eq. 5), the
  * per-tile candidate lists (CSR, ascending) and their transpose.
  * Synchronises once, to read the number of candidates.  q = 0 or k = 0

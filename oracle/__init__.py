@@ -69,14 +69,14 @@ def lib():
                "ngd_oracle_grad_lists", "ngd_oracle_msq_pairs"):
         getattr(L, fn).restype = ctypes.c_int
     L.ngd_cull_ref_run.argtypes = [i, i64, _f32p, _f32p, i64, _f32p, i, _f32p,
-                                   ctypes.c_float, i, i, i]
+                                   ctypes.c_float, i, i, i, i]
     L.ngd_cull_ref_run.restype = p
     L.ngd_cull_ref_total.argtypes = [p]
     L.ngd_cull_ref_total.restype = i64
     L.ngd_cull_ref_ntiles.argtypes = [p]
     L.ngd_cull_ref_ntiles.restype = i64
     L.ngd_cull_ref_get.argtypes = [p, _i32p, _i32p, _i64p, _i32p, _i64p, _i32p, _f32p,
-                                   _f32p, _f32p, _f32p, _u32p, _u32p, _f32p, _f32p]
+                                   _f32p, _f32p, _f32p, _u32p, _u32p, _f32p, _f32p, _f32p]
     L.ngd_cull_ref_get.restype = None
     L.ngd_cull_ref_free.argtypes = [p]
     L.ngd_cull_ref_free.restype = None
@@ -207,8 +207,9 @@ def kappa2_from_tau(tau: float) -> np.float32:
     return np.float32(-2.0 * math.log(float(tau)))
 
 
-def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=2):
-    """CPU re-implementation of the tile cull.  Returns a dict of arrays:
+def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=2, tiling=0):
+    """CPU re-implementation of the tile cull (tiling 0: k-d order, 1: Morton
+    key).  Returns a dict of arrays:
     perm, gperm, tile_off, cand, g_off, g_tiles, tile_lo, tile_hi, g_mr,
     g_thr, qkey, gkey, qlo, qhi (see ngd_cull_ref.c)."""
     mean = np.ascontiguousarray(mean, dtype=np.float32)
@@ -220,7 +221,8 @@ def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=
     L = lib()
     h = L.ngd_cull_ref_run(n, k, _p(mean, _f32p), _p(factor, _f32p), q,
                            _p(queries, _f32p), n_proj, _p(proj, _f32p),
-                           ctypes.c_float(kappa2_from_tau(tau)), tile, key_proj, key_bits)
+                           ctypes.c_float(kappa2_from_tau(tau)), tile, key_proj, key_bits,
+                           tiling)
     if not h:
         raise ValueError("invalid cull arguments")
     try:
@@ -235,7 +237,8 @@ def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=
             g_mr=np.zeros((max(k, 1), n_proj), np.float32),
             g_thr=np.zeros((max(k, 1), n_proj), np.float32),
             qkey=np.zeros(max(q, 1), np.uint32), gkey=np.zeros(max(k, 1), np.uint32),
-            qlo=np.zeros(n_proj, np.float32), qhi=np.zeros(n_proj, np.float32))
+            qlo=np.zeros(n_proj, np.float32), qhi=np.zeros(n_proj, np.float32),
+            q_r=np.zeros((max(q, 1), n_proj), np.float32))
         o = out
         L.ngd_cull_ref_get(h, _p(o["perm"], _i32p), _p(o["gperm"], _i32p),
                            _p(o["tile_off"], _i64p), _p(o["cand"], _i32p),
@@ -243,7 +246,7 @@ def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=
                            _p(o["tile_lo"], _f32p), _p(o["tile_hi"], _f32p),
                            _p(o["g_mr"], _f32p), _p(o["g_thr"], _f32p),
                            _p(o["qkey"], _u32p), _p(o["gkey"], _u32p),
-                           _p(o["qlo"], _f32p), _p(o["qhi"], _f32p))
+                           _p(o["qlo"], _f32p), _p(o["qhi"], _f32p), _p(o["q_r"], _f32p))
     finally:
         L.ngd_cull_ref_free(h)
     out["cand"] = out["cand"][:total]
@@ -253,6 +256,7 @@ def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=
     out["g_mr"] = out["g_mr"][:k]
     out["g_thr"] = out["g_thr"][:k]
     out["qkey"] = out["qkey"][:q]
+    out["q_r"] = out["q_r"][:q]
     out["gkey"] = out["gkey"][:k]
     out["ntiles"] = T
     out["total"] = total

@@ -25,14 +25,20 @@
  *        dist_j = max(lo_tj - m_rj, m_rj - hi_tj, 0)
  *        keep   iff  dist_j * dist_j <= kappa^2 * sigma_rj^2   for every j
  *     with kappa^2 * sigma^2 rounded once to float32 per (Gaussian, j).
- *   - Queries carry no image, so tiles are formed by sorting the queries
- *     (stable, ties by original index) on a locality key: key_proj of the
- *     query projections quantised to key_bits each over the queries' range,
- *     bits interleaved most-significant first (a Morton code in projection
- *     space).  Tile t = sorted queries [t*tile, (t+1)*tile).
- *   - Gaussians are sorted the same way by the key of their projected means
- *     (clamped to the queries' range).  Candidate lists hold sorted Gaussian
- *     positions, ascending; the sort does not change any candidate *set*.
+ *   - Queries carry no image, so tiles are formed by ordering the queries in
+ *     projection space and cutting the order into runs of `tile`:
+ *     tiling 0 (k-d): recursive exact-rank splits on the projection of
+ *       largest extent (see kd_split) until runs hold at most `tile` queries,
+ *       and inside those runs on to runs of 64 (groups of 64 consecutive
+ *       queries in a tile are then compact too);
+ *     tiling 1 (Morton): a stable sort (ties by original index) on key_proj
+ *       projections quantised to key_bits each over the queries' range, bits
+ *       interleaved most-significant first.
+ *     Tile t = ordered queries [t*tile, (t+1)*tile).
+ *   - Gaussians are ordered the same way by their projected means (k-d runs
+ *     of 64; or the Morton key clamped to the queries' range).  Candidate
+ *     lists hold ordered Gaussian positions, ascending; the order does not
+ *     change any candidate *set*.
  *
  * Rounding recipe:
  *   q_r, m_r : float32 fma chain over dims 0..n-1 starting from 0
@@ -65,6 +71,7 @@ typedef struct {
     float *tile_hi;     /* ntiles x n_proj */
     float *g_mr;        /* k x n_proj (original order) */
     float *g_thr;       /* k x n_proj (original order) */
+    float *q_r;         /* q x n_proj (original order) */
     int64_t *tile_off;  /* ntiles + 1 */
     int32_t *cand;      /* total: sorted Gaussian positions */
     int64_t *g_off;     /* k + 1, by sorted Gaussian position */
@@ -85,6 +92,82 @@ static void stable_sort_by_key(const uint32_t *key, int64_t count, int32_t *orde
     for (int64_t i = 0; i < count; ++i) tmp[i] = ((uint64_t)key[i] << 32) | (uint64_t)i;
     qsort(tmp, (size_t)count, sizeof(uint64_t), cmp_key_idx);
     for (int64_t i = 0; i < count; ++i) order[i] = (int32_t)(tmp[i] & 0xffffffffu);
+    free(tmp);
+}
+
+/* Order-preserving map of a float to an unsigned key (larger float, larger
+ * key; -0 sorts just below +0; NaNs sort above +inf or below -inf). */
+static uint32_t orderable(float v)
+{
+    uint32_t u;
+    memcpy(&u, &v, sizeof u);
+    return (u >> 31) ? ~u : (u | 0x80000000u);
+}
+
+static int cmp_u64(const void *a, const void *b)
+{
+    const uint64_t x = *(const uint64_t *)a, y = *(const uint64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* k-d ordering: recursively split a run of points (the current order
+ * order[lo..hi)) until a run holds at most `sub` points.  A run of n points
+ * is cut in units of u = leaf while n > leaf, else of u = sub (sub <= leaf):
+ * it needs T = ceil(n/u) units; its first ceil(T/2)*u points in the order
+ * (value on the split projection, then current position) go left, the rest
+ * right, each side keeping its relative order.  So runs of at most `leaf`
+ * points (the tiles) are exactly those of a split with sub = leaf, and the
+ * finer splits only reorder points inside them.  The split projection is
+ * the one of largest extent (max - min) over the run, the first such on
+ * ties. */
+static void kd_split(int P, int64_t nall, const float *vals, int32_t *order, int64_t lo,
+                     int64_t hi, int leaf, int sub, uint64_t *pairs, int32_t *tmp)
+{
+    const int64_t n = hi - lo;
+    if (n <= sub) return;
+    const int64_t u = n > leaf ? leaf : sub;
+    const int64_t T = (n + u - 1) / u, nl = ((T + 1) / 2) * u;
+    int best = 0;
+    float best_ext = 0.0f;
+    for (int j = 0; j < P; ++j) {
+        float mn = INFINITY, mx = -INFINITY;
+        for (int64_t i = lo; i < hi; ++i) {
+            const float v = vals[(int64_t)j * nall + order[i]];
+            mn = fminf(mn, v);
+            mx = fmaxf(mx, v);
+        }
+        const float ext = mx - mn;
+        if (j == 0 || ext > best_ext) {
+            best = j;
+            best_ext = ext;
+        }
+    }
+    for (int64_t i = lo; i < hi; ++i)
+        pairs[i - lo] = ((uint64_t)orderable(vals[(int64_t)best * nall + order[i]]) << 32) |
+                        (uint64_t)(i - lo);
+    qsort(pairs, (size_t)n, sizeof(uint64_t), cmp_u64);
+    const uint64_t pivot = pairs[nl];   /* first point that goes right */
+    int64_t l = 0, r = nl;
+    for (int64_t i = lo; i < hi; ++i) {
+        const uint64_t key =
+            ((uint64_t)orderable(vals[(int64_t)best * nall + order[i]]) << 32) | (uint64_t)(i - lo);
+        if (key < pivot)
+            tmp[l++] = order[i];
+        else
+            tmp[r++] = order[i];
+    }
+    memcpy(order + lo, tmp, sizeof(int32_t) * (size_t)n);
+    kd_split(P, nall, vals, order, lo, lo + nl, leaf, sub, pairs, tmp);
+    kd_split(P, nall, vals, order, lo + nl, hi, leaf, sub, pairs, tmp);
+}
+
+static void kd_order(int P, int64_t n, const float *vals, int leaf, int sub, int32_t *order)
+{
+    for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)i;
+    uint64_t *pairs = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n ? n : 1));
+    int32_t *tmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    kd_split(P, n, vals, order, 0, n, leaf, sub, pairs, tmp);
+    free(pairs);
     free(tmp);
 }
 
@@ -111,7 +194,7 @@ void ngd_cull_ref_free(cull_ref *c)
     if (!c) return;
     free(c->perm); free(c->gperm); free(c->qkey); free(c->gkey);
     free(c->qlo); free(c->qhi); free(c->tile_lo); free(c->tile_hi);
-    free(c->g_mr); free(c->g_thr); free(c->tile_off); free(c->cand);
+    free(c->g_mr); free(c->g_thr); free(c->q_r); free(c->tile_off); free(c->cand);
     free(c->g_off); free(c->g_tiles);
     free(c);
 }
@@ -120,11 +203,11 @@ void ngd_cull_ref_free(cull_ref *c)
 cull_ref *ngd_cull_ref_run(int n, int64_t k, const float *mean, const float *factor,
                            int64_t q, const float *queries, int n_proj,
                            const float *proj, float kappa2, int tile, int key_proj,
-                           int key_bits)
+                           int key_bits, int tiling)
 {
     if (n < 1 || n > CULL_MAX_N || n_proj < 1 || n_proj > CULL_MAX_PROJ || tile < 1 ||
         key_proj < 0 || key_proj > n_proj || key_bits < 0 || key_proj * key_bits > 32 ||
-        k < 0 || q < 0)
+        k < 0 || q < 0 || tiling < 0 || tiling > 1)
         return NULL;
     const int64_t tri = (int64_t)n * (n + 1) / 2;
     cull_ref *c = (cull_ref *)calloc(1, sizeof(cull_ref));
@@ -189,8 +272,23 @@ cull_ref *ngd_cull_ref_run(int n, int64_t k, const float *mean, const float *fac
         c->gkey[i] = morton_key(c->g_mr + i * n_proj, c->qlo, scale, key_proj, key_bits);
     c->perm = (int32_t *)malloc(sizeof(int32_t) * qq);
     c->gperm = (int32_t *)malloc(sizeof(int32_t) * kk);
-    stable_sort_by_key(c->qkey, q, c->perm);
-    stable_sort_by_key(c->gkey, k, c->gperm);
+    if (tiling == 0) {
+        /* k-d order of the query projections (leaves = tiles) and of the
+         * projected means (leaves of 64 Gaussians) */
+        float *qr_soa = (float *)malloc(sizeof(float) * qq * n_proj);
+        for (int64_t p = 0; p < q; ++p)
+            for (int j = 0; j < n_proj; ++j) qr_soa[(int64_t)j * q + p] = q_r[p * n_proj + j];
+        float *mr_soa = (float *)malloc(sizeof(float) * kk * n_proj);
+        for (int64_t i = 0; i < k; ++i)
+            for (int j = 0; j < n_proj; ++j) mr_soa[(int64_t)j * k + i] = c->g_mr[i * n_proj + j];
+        kd_order(n_proj, q, qr_soa, tile, tile < 64 ? tile : 64, c->perm);
+        kd_order(n_proj, k, mr_soa, 64, 64, c->gperm);
+        free(qr_soa);
+        free(mr_soa);
+    } else {
+        stable_sort_by_key(c->qkey, q, c->perm);
+        stable_sort_by_key(c->gkey, k, c->gperm);
+    }
 
     /* Tile bounds: the extent of each tile's projected queries. */
     c->tile_lo = (float *)malloc(sizeof(float) * (size_t)(T ? T : 1) * n_proj);
@@ -253,7 +351,7 @@ cull_ref *ngd_cull_ref_run(int n, int64_t k, const float *mean, const float *fac
             if (keep[t * k + s]) c->g_tiles[w++] = (int32_t)t;
     }
     free(keep);
-    free(q_r);
+    c->q_r = q_r;
     return c;
 }
 
@@ -264,7 +362,7 @@ int64_t ngd_cull_ref_ntiles(const cull_ref *c) { return c->ntiles; }
 void ngd_cull_ref_get(const cull_ref *c, int32_t *perm, int32_t *gperm, int64_t *tile_off,
                       int32_t *cand, int64_t *g_off, int32_t *g_tiles, float *tile_lo,
                       float *tile_hi, float *g_mr, float *g_thr, uint32_t *qkey,
-                      uint32_t *gkey, float *qlo, float *qhi)
+                      uint32_t *gkey, float *qlo, float *qhi, float *q_r)
 {
     const int64_t T = c->ntiles, P = c->n_proj;
     if (perm) memcpy(perm, c->perm, sizeof(int32_t) * (size_t)c->q);
@@ -281,4 +379,5 @@ void ngd_cull_ref_get(const cull_ref *c, int32_t *perm, int32_t *gperm, int64_t 
     if (gkey) memcpy(gkey, c->gkey, sizeof(uint32_t) * (size_t)c->k);
     if (qlo) memcpy(qlo, c->qlo, sizeof(float) * (size_t)P);
     if (qhi) memcpy(qhi, c->qhi, sizeof(float) * (size_t)P);
+    if (q_r) memcpy(q_r, c->q_r, sizeof(float) * (size_t)(c->q * P));
 }

@@ -18,8 +18,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libngd.so")
-SOURCES = ["capi.hip", "prepare.hip", "cull.hip", "sort.hip", "eval.hip", "backward.hip",
-           "scan.hip"]
+SOURCES = ["capi.hip", "prepare.hip", "cull.hip", "kd.hip", "sort.hip", "eval.hip",
+           "backward.hip", "scan.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

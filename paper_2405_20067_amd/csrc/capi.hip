@@ -110,6 +110,7 @@ int ngd_cull_params_default(ngd_cull_params *p)
     p->tile = 256;
     p->key_proj = 16;
     p->key_bits = 2;
+    p->tiling = 0;
     return NGD_OK;
 }
 
@@ -215,7 +216,13 @@ static void cull_release(ngd_cull *c)
                       &c->cand,    &c->g_cnt,    &c->g_off,      &c->g_tiles, &c->scan_tmp,
                       &c->stats,   &c->item_cnt, &c->item_off,   &c->item_tile, &c->fpart,
                       &c->gitem_cnt, &c->gitem_off, &c->gitem_g, &c->gpart,   &c->gflag,
-                      &c->g_ent,   &c->ent_tile, &c->act};
+                      &c->g_ent,   &c->ent_tile, &c->act,
+                      &c->kd_q.node_tab, &c->kd_q.slice_tab, &c->kd_g.node_tab,
+                      &c->kd_g.slice_tab, &c->kd_work.idx[0], &c->kd_work.idx[1],
+                      &c->kd_work.val[0], &c->kd_work.val[1], &c->kd_work.ext[0],
+                      &c->kd_work.ext[1], &c->kd_work.hist, &c->kd_work.done, &c->kd_work.cnt,
+                      &c->kd_work.dim,
+                      &c->kd_work.prefix, &c->kd_work.rank};
     for (DevBuf *b : bufs) b->release();
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     c->stats_host = nullptr;
@@ -242,6 +249,8 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
         p->key_proj * p->key_bits > 32 || (p->key_proj > 0 && p->key_bits > 16))
         return fail(NGD_E_INVAL, "ngd_cull_build: key_proj=%d key_bits=%d invalid", p->key_proj,
                     p->key_bits);
+    if (p->tiling != 0 && p->tiling != 1)
+        return fail(NGD_E_INVAL, "ngd_cull_build: tiling=%d (0: k-d, 1: Morton)", p->tiling);
     for (int i = 0; i < p->n_proj * mix->n; ++i)
         if (!std::isfinite(proj[i]))
             return fail(NGD_E_INVAL, "ngd_cull_build: projection vectors must be finite");

@@ -415,6 +415,12 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
+__global__ void k_iota(int32_t *p, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = int32_t(i);
+}
+
 __global__ void k_zero_i32(int32_t *p, int64_t n)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -463,9 +469,28 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
                                          c->range_part.as<float>(), c->qrange.as<float>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    // queries: keys, sort -> perm
     int which = 0;
-    if (q > 0) {
+    if (c->params.tiling == 0) {
+        // k-d order of the query projections (runs of `tile`, and of 64
+        // inside those) and of the projected means (runs of 64, the chunks
+        // of the interval test)
+        if (q > 0) {
+            if (q <= std::min(c->params.tile, kWave))
+                k_iota<<<nblk(q, kThreads), kThreads, 0, s>>>(c->perm.as<int32_t>(), q);
+            else if ((e = kd_order(c->kd_q, c->kd_work, P, c->qr.as<float>(), q,
+                                   c->perm.as<int32_t>(), s)) != hipSuccess)
+                return e;
+        }
+        if (k > 0) {
+            if (k <= kWave)
+                k_iota<<<nblk(k, kThreads), kThreads, 0, s>>>(c->gperm.as<int32_t>(), k);
+            else if ((e = kd_order(c->kd_g, c->kd_work, P, c->g_mr.as<float>(), k,
+                                   c->gperm.as<int32_t>(), s)) != hipSuccess)
+                return e;
+        }
+    }
+    // Morton: queries: keys, sort -> perm
+    if (c->params.tiling == 1 && q > 0) {
         k_keys<<<nblk(q, kThreads), kThreads, 0, s>>>(q, P, c->qr.as<float>(),
                                                       c->qrange.as<float>(), c->params.key_proj,
                                                       c->params.key_bits, c->keys0.as<uint32_t>(),
@@ -477,8 +502,8 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
                            hipMemcpyDeviceToDevice, s);
         if (e != hipSuccess) return e;
     }
-    // Gaussians: keys of the projected means, sort -> gperm
-    if (k > 0) {
+    // Morton: Gaussians: keys of the projected means, sort -> gperm
+    if (c->params.tiling == 1 && k > 0) {
         k_keys<<<nblk(k, kThreads), kThreads, 0, s>>>(k, P, c->g_mr.as<float>(),
                                                       c->qrange.as<float>(), c->params.key_proj,
                                                       c->params.key_bits, c->keys0.as<uint32_t>(),
@@ -756,6 +781,11 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->gitem_off.ensure(sizeof(int64_t) * (kk + 1));
     ok &= c->scan_tmp.ensure(scan_tmp_bytes(scan_n));
     ok &= c->stats.ensure(sizeof(int64_t) * 2);
+    if (c->params.tiling == 0) {
+        ok &= kd_plan(c->kd_q, q, c->params.tile, std::min(c->params.tile, kWave)) &&
+              kd_plan(c->kd_g, k, kWave, kWave);
+        ok = ok && kd_reserve(c->kd_work, c->kd_q, q, P) && kd_reserve(c->kd_work, c->kd_g, k, P);
+    }
     return ok;
 }
 

@@ -1,0 +1,868 @@
+// k-d ordering of points in projection space, the tiling of the cull.
+//
+// Definition (shared with the CPU re-implementation): a run of n points is
+// cut in units of u = leaf while n > leaf, else of u = sub (sub <= leaf);
+// it needs T = ceil(n/u) units, and its first ceil(T/2)*u points in the
+// order (value on the split projection, then position in the run) go left
+// and the rest right, each side keeping its relative order.  The split
+// projection is the one of largest extent (max - min) over the run, the
+// first such on ties.  Runs of at most `sub` points are leaves; the runs of
+// at most `leaf` points (tiles) are those of a split with sub = leaf, the
+// finer splits only reorder inside them.  Because every split is an exact
+// rank split on a stable order, run boundaries depend only on
+// (n, leaf, sub), and the host lays them out level by level.
+//
+// Upper levels (nodes of more than kLocalMax points) run one level at a
+// time over all of the level's nodes, each node cut into slices of kSlice
+// points (one workgroup each):
+//   split    per node: the projection of largest extent, from the node's
+//            min / max (accumulated by the previous level's scatter; for
+//            the root by a pass over its slices)
+//   hist     per slice: histogram of one radix digit (11, 11, 10 bits of
+//            the order-preserving key) among the points that match the
+//            digits found so far, added into the node's histogram; the
+//            node's last slice then selects the bin that holds the rank
+//            n_left.  Three rounds give the pivot key (the first point that
+//            goes right)
+//   count    per slice: points below / equal to the pivot
+//   scatter  per slice: offsets from the node's earlier slices' counts,
+//            stable ranks by workgroup prefix sums in position order; index
+//            and projection values move to the next buffer, and the
+//            children's min / max are accumulated for the next split
+// Nodes of at most kLocalMax points finish their whole subtree in one
+// workgroup each (k_kd_local): the order and the sort keys stay in LDS, and
+// every level of the subtree is one bitonic sort of (run, key, position).
+#include <algorithm>
+#include <map>
+#include <vector>
+
+#include "ngd_internal.hpp"
+#include "wave.hpp"
+
+namespace ngd {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSlice = 1024;
+constexpr int kBins = 2048;
+constexpr int kShift[3] = {21, 10, 0};
+constexpr int kWidth[3] = {11, 11, 10};
+
+constexpr int kLocalThreads = 1024;
+constexpr int kLocalMax = 4096;     // points per subtree workgroup (12-bit positions)
+constexpr int kLocalRuns = 128;     // runs per subtree (8-bit run ids)
+constexpr int kLocalSplit = 64;     // runs split at one level of a subtree
+
+// node table row: start, size, n_left (-1: leaf), first slice, end slice,
+// first child's index in the next level (-1: none)
+constexpr int kNodeCols = 6;
+// slice table row: start, length, node
+constexpr int kSliceCols = 3;
+
+__device__ __forceinline__ uint32_t orderable(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (u >> 31) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float from_orderable(uint32_t k)
+{
+    return __uint_as_float((k >> 31) ? (k & 0x7fffffffu) : ~k);
+}
+
+__device__ __forceinline__ uint32_t wave_umin(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = min(v, uint32_t(__shfl_xor(int(v), m, kWave)));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_umax(uint32_t v)
+{
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v = max(v, uint32_t(__shfl_xor(int(v), m, kWave)));
+    return v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_kd_zero(int32_t *__restrict__ p, int64_t n)
+{
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// min / max key slots of `count` (node, projection) pairs to their identities
+__global__ __launch_bounds__(kThreads) void k_kd_ext_reset(uint32_t *__restrict__ ext,
+                                                           int64_t count)
+{
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i < count) {
+        ext[2 * i + 0] = 0xffffffffu;
+        ext[2 * i + 1] = 0u;
+    }
+}
+
+// Workgroup min / max of per-thread keys for projections j < P, merged into
+// ext[(node * P + j) * 2 + {0, 1}] by atomics (order-independent).
+template <int PMAX>
+__device__ void block_merge_ext(const uint32_t (&kmin)[PMAX], const uint32_t (&kmax)[PMAX],
+                                int P, uint32_t *ext, int64_t node)
+{
+    __shared__ uint32_t smin[kThreads / kWave][PMAX], smax[kThreads / kWave][PMAX];
+    const int w = threadIdx.x / kWave;
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        if (j < P) {
+            const uint32_t a = wave_umin(kmin[j]), b = wave_umax(kmax[j]);
+            if (lane_id() == 0) {
+                smin[w][j] = a;
+                smax[w][j] = b;
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < P) {
+        const int j = threadIdx.x;
+        uint32_t a = 0xffffffffu, b = 0u;
+#pragma unroll
+        for (int i = 0; i < kThreads / kWave; ++i) {
+            a = min(a, smin[i][j]);
+            b = max(b, smax[i][j]);
+        }
+        if (a != 0xffffffffu) atomicMin(&ext[(node * P + j) * 2 + 0], a);
+        if (b != 0u) atomicMax(&ext[(node * P + j) * 2 + 1], b);
+    }
+    __syncthreads();
+}
+
+// The root's min / max over its slices.
+template <int PMAX>
+__global__ __launch_bounds__(kThreads) void k_kd_root_ext(const int64_t *__restrict__ slices,
+                                                          int64_t n, int P,
+                                                          const float *__restrict__ vin,
+                                                          uint32_t *__restrict__ ext)
+{
+    const int64_t sl = blockIdx.x;
+    const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
+    uint32_t kmin[PMAX], kmax[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        kmin[j] = 0xffffffffu;
+        kmax[j] = 0u;
+    }
+    for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+#pragma unroll
+        for (int j = 0; j < PMAX; ++j) {
+            if (j < P) {
+                const uint32_t key = orderable(vin[int64_t(j) * n + s0 + i]);
+                kmin[j] = min(kmin[j], key);
+                kmax[j] = max(kmax[j], key);
+            }
+        }
+    }
+    block_merge_ext<PMAX>(kmin, kmax, P, ext, 0);
+}
+
+// One thread per node: the split projection; resets the children's min /
+// max slots (filled by this level's scatter) when the next level has them.
+__global__ __launch_bounds__(kThreads) void k_kd_split(const int64_t *__restrict__ nodes,
+                                                       int64_t nnodes, int P,
+                                                       const uint32_t *__restrict__ ext,
+                                                       uint32_t *__restrict__ ext_next,
+                                                       int32_t *__restrict__ dim,
+                                                       uint32_t *__restrict__ prefix,
+                                                       int64_t *__restrict__ rank)
+{
+    const int64_t nd = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (nd >= nnodes) return;
+    const int64_t *row = nodes + nd * kNodeCols;
+    const int64_t nleft = row[2];
+    if (nleft < 0) {
+        dim[nd] = -1;
+        return;
+    }
+    int best = 0;
+    float best_ext = 0.0f;
+    for (int j = 0; j < P; ++j) {
+        const float mn = from_orderable(ext[(nd * P + j) * 2 + 0]);
+        const float mx = from_orderable(ext[(nd * P + j) * 2 + 1]);
+        const float e = mx - mn;
+        if (j == 0 || e > best_ext) {
+            best = j;
+            best_ext = e;
+        }
+    }
+    dim[nd] = best;
+    prefix[nd] = 0u;
+    rank[nd] = nleft;
+    const int64_t ch = row[5];
+    if (ext_next && ch >= 0) {
+        for (int j = 0; j < 2 * P; ++j) {   // both children's P slots
+            ext_next[(ch * P + j) * 2 + 0] = 0xffffffffu;
+            ext_next[(ch * P + j) * 2 + 1] = 0u;
+        }
+    }
+}
+
+// Block exclusive scan of one int64 per thread (256 threads).
+__device__ int64_t block_exscan(int64_t v, int64_t *total)
+{
+    __shared__ int64_t wt[kThreads / kWave];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    int64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int64_t y = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += y;
+    }
+    if (lane == kWave - 1) wt[w] = inc;
+    __syncthreads();
+    int64_t before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kThreads / kWave; ++i) {
+        before += (i < w) ? wt[i] : 0;
+        all += wt[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+// Per slice: histogram of one digit among the matching points, added into
+// the node's histogram.  The node's last slice to finish (device-scope
+// counter after a fence; nothing waits) then finds the bin that holds the
+// rank, clears the histogram and the counter for the next round.
+__global__ __launch_bounds__(kThreads) void k_kd_hist_select(
+    const int64_t *__restrict__ nodes, const int64_t *__restrict__ slices, int64_t node0,
+    int64_t n, int round, const float *__restrict__ vin, const int32_t *__restrict__ dim,
+    uint32_t *__restrict__ prefix, int64_t *__restrict__ rank, int32_t *__restrict__ node_hist,
+    int32_t *__restrict__ node_done)
+{
+    __shared__ int h[kBins];
+    __shared__ int last;
+    const int64_t sl = blockIdx.x;
+    const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
+    const int64_t nd = slices[sl * kSliceCols + 2] - node0;
+    const int d = dim[nd];
+    if (d < 0) return;   // uniform over the workgroup
+    for (int b = threadIdx.x; b < kBins; b += kThreads) h[b] = 0;
+    __syncthreads();
+    const int shift = kShift[round], width = kWidth[round];
+    const uint32_t pre = prefix[nd];
+    const uint32_t mask = (1u << width) - 1u;
+    for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+        const uint32_t key = orderable(vin[int64_t(d) * n + s0 + i]);
+        const bool match = (round == 0) || ((key >> (shift + width)) == pre);
+        if (match) atomicAdd(&h[(key >> shift) & mask], 1);
+    }
+    __syncthreads();
+    int32_t *nh = node_hist + nd * kBins;
+    for (int b = threadIdx.x; b < kBins; b += kThreads)
+        if (h[b]) atomicAdd(&nh[b], h[b]);
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t *row = nodes + nd * kNodeCols;
+        const int nsl = int(row[4] - row[3]);
+        last = atomicAdd(&node_done[nd], 1) == nsl - 1;
+    }
+    __syncthreads();
+    if (!last) return;   // uniform
+    __threadfence();
+    const int64_t r = rank[nd];
+    const int per = (1 << width) / kThreads;   // 8 or 4
+    int64_t cnt[kBins / kThreads];
+    int64_t mine = 0;
+    for (int i = 0; i < per; ++i) {
+        const int b = threadIdx.x * per + i;
+        cnt[i] = atomicExch(&nh[b], 0);
+        mine += cnt[i];
+    }
+    int64_t tot;
+    int64_t cum = block_exscan(mine, &tot);
+    for (int i = 0; i < per; ++i) {
+        if (r >= cum && r < cum + cnt[i]) {
+            prefix[nd] = (pre << width) | uint32_t(threadIdx.x * per + i);
+            rank[nd] = r - cum;
+        }
+        cum += cnt[i];
+    }
+    if (threadIdx.x == 0) node_done[nd] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_kd_count(const int64_t *__restrict__ slices,
+                                                       int64_t node0, int64_t n,
+                                                       const float *__restrict__ vin,
+                                                       const int32_t *__restrict__ dim,
+                                                       const uint32_t *__restrict__ prefix,
+                                                       int64_t *__restrict__ cnt)
+{
+    const int64_t sl = blockIdx.x;
+    const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
+    const int64_t nd = slices[sl * kSliceCols + 2] - node0;
+    const int d = dim[nd];
+    int64_t less = 0, eq = 0;
+    if (d >= 0) {
+        const uint32_t pivot = prefix[nd];
+        for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+            const uint32_t key = orderable(vin[int64_t(d) * n + s0 + i]);
+            less += key < pivot;
+            eq += key == pivot;
+        }
+    }
+    int64_t tl, te;
+    block_exscan(less, &tl);
+    block_exscan(eq, &te);
+    if (threadIdx.x == 0) {
+        cnt[sl * 2 + 0] = tl;
+        cnt[sl * 2 + 1] = te;
+    }
+}
+
+// Block-wide exclusive prefix count of a flag (position order), with total.
+__device__ __forceinline__ int block_flag_scan(bool f, int *total)
+{
+    __shared__ int wc[kThreads / kWave];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const uint64_t b = ballot(f);
+    const int before_lane = __popcll(b & lanemask_lt());
+    if (lane == 0) wc[w] = __popcll(b);
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kThreads / kWave; ++i) {
+        before += (i < w) ? wc[i] : 0;
+        all += wc[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + before_lane;
+}
+
+template <int PMAX>
+__global__ __launch_bounds__(kThreads) void k_kd_scatter(
+    const int64_t *__restrict__ nodes, const int64_t *__restrict__ slices, int64_t node0,
+    int64_t slice0, int64_t n, int P, const int32_t *__restrict__ idx_in,
+    const float *__restrict__ vin, const int32_t *__restrict__ dim,
+    const uint32_t *__restrict__ prefix, const int64_t *__restrict__ rank,
+    const int64_t *__restrict__ cnt, int32_t *__restrict__ idx_out, float *__restrict__ vout,
+    uint32_t *__restrict__ ext_next)
+{
+    const int64_t sl = blockIdx.x;
+    const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
+    const int64_t nd = slices[sl * kSliceCols + 2] - node0;
+    const int64_t *row = nodes + nd * kNodeCols;
+    const int64_t start = row[0], size = row[1], nleft = row[2];
+    const int d = dim[nd];
+    if (d < 0) {   // a leaf: its points stay where they are
+        for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+            const int64_t pos = s0 + i;
+            idx_out[pos] = idx_in ? idx_in[pos] : int32_t(pos);
+#pragma unroll
+            for (int j = 0; j < PMAX; ++j)
+                if (j < P) vout[int64_t(j) * n + pos] = vin[int64_t(j) * n + pos];
+        }
+        return;
+    }
+    // points below the pivot, and equal to it, in the node's earlier slices
+    const int64_t sb = row[3] - slice0;
+    int64_t l_mine = 0, e_mine = 0;
+    for (int64_t s = sb + threadIdx.x; s < sl; s += kThreads) {
+        l_mine += cnt[s * 2 + 0];
+        e_mine += cnt[s * 2 + 1];
+    }
+    int64_t l_before, e_before;
+    block_exscan(l_mine, &l_before);
+    block_exscan(e_mine, &e_before);
+    const uint32_t pivot = prefix[nd];
+    const int64_t need = rank[nd];   // pivot-equal points that go left
+    const int64_t lo = l_before + (need < e_before ? need : e_before);
+    const int64_t ro = (s0 - start) - lo;
+    const int64_t ch = row[5];
+    const bool track = ext_next != nullptr && ch >= 0;
+    uint32_t lmin[PMAX], lmax[PMAX], rmin[PMAX], rmax[PMAX];
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        lmin[j] = rmin[j] = 0xffffffffu;
+        lmax[j] = rmax[j] = 0u;
+    }
+    int64_t run_eq = 0, run_left = 0;
+    for (int64_t base = 0; base < len; base += kThreads) {
+        const int64_t i = base + threadIdx.x;
+        const bool valid = i < len;
+        const int64_t pos = s0 + i;
+        const uint32_t key = valid ? orderable(vin[int64_t(d) * n + pos]) : 0xffffffffu;
+        const bool is_less = valid && key < pivot;
+        const bool is_eq = valid && key == pivot;
+        int teq, tleft;
+        const int64_t eq_rank = e_before + run_eq + block_flag_scan(is_eq, &teq);
+        const bool left = is_less || (is_eq && eq_rank < need);
+        const int64_t left_rank = run_left + block_flag_scan(left, &tleft);
+        const int64_t dest = left ? start + lo + left_rank : start + nleft + ro + (i - left_rank);
+        run_eq += teq;
+        run_left += tleft;
+        // every destination lies in the node's own run (the counts agree);
+        // the test only guards the buffers should they ever not
+        if (valid && dest >= start && dest < start + size) {
+            idx_out[dest] = idx_in ? idx_in[pos] : int32_t(pos);
+#pragma unroll
+            for (int j = 0; j < PMAX; ++j) {
+                if (j < P) {
+                    const float v = vin[int64_t(j) * n + pos];
+                    vout[int64_t(j) * n + dest] = v;
+                    if (track) {
+                        const uint32_t k = orderable(v);
+                        if (left) {
+                            lmin[j] = min(lmin[j], k);
+                            lmax[j] = max(lmax[j], k);
+                        } else {
+                            rmin[j] = min(rmin[j], k);
+                            rmax[j] = max(rmax[j], k);
+                        }
+                    }
+                }
+            }
+        }
+    }
+    if (track) {   // uniform
+        block_merge_ext<PMAX>(lmin, lmax, P, ext_next, ch);
+        block_merge_ext<PMAX>(rmin, rmax, P, ext_next, ch + 1);
+    }
+}
+
+// ---- subtrees of at most kLocalMax points, one workgroup each -------------
+
+__device__ int local_exscan(int v, int *total)
+{
+    __shared__ int wt[kLocalThreads / kWave];
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    const int inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) wt[w] = inc;
+    __syncthreads();
+    int before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < kLocalThreads / kWave; ++i) {
+        before += (i < w) ? wt[i] : 0;
+        all += wt[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + inc - v;
+}
+
+template <int PMAX>
+__global__ __launch_bounds__(kLocalThreads) void k_kd_local(
+    const int64_t *__restrict__ nodes, int64_t n, int P, int leaf, int sub,
+    const int32_t *__restrict__ idx_in, const float *__restrict__ vin,
+    int32_t *__restrict__ idx_out)
+{
+    __shared__ uint64_t keys[kLocalMax];
+    __shared__ uint16_t ord[2][kLocalMax];
+    __shared__ uint16_t lpre[kLocalMax];
+    __shared__ uint8_t flag[kLocalMax];
+    __shared__ uint8_t run_of[kLocalMax];
+    __shared__ int rs[kLocalRuns], rl[kLocalRuns], rn[kLocalRuns], rd[kLocalRuns], rsi[kLocalRuns];
+    __shared__ int split_list[kLocalSplit];
+    __shared__ uint32_t emin[kLocalSplit][PMAX], emax[kLocalSplit][PMAX];
+    __shared__ int nruns_s, nsplit_s;
+
+    const int64_t *row = nodes + int64_t(blockIdx.x) * kNodeCols;
+    const int64_t start = row[0];
+    const int m = int(row[1]);   // <= kLocalMax, with at most kLocalRuns leaves (host plan)
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    constexpr int kWaves = kLocalThreads / kWave;
+    int m2 = 1;
+    while (m2 < m) m2 <<= 1;
+
+    for (int i = tid; i < m; i += kLocalThreads) {
+        ord[0][i] = uint16_t(i);
+        run_of[i] = 0;
+    }
+    if (tid == 0) {
+        rs[0] = 0;
+        rl[0] = m;
+        nruns_s = 1;
+    }
+    __syncthreads();
+    int cur = 0;
+    while (true) {
+        // runs that split at this level, and where
+        if (tid == 0) {
+            int ns = 0;
+            for (int b = 0; b < nruns_s; ++b) {
+                const int len = rl[b];
+                if (len > sub && ns < kLocalSplit) {
+                    const int u = len > leaf ? leaf : sub;
+                    const int T = (len + u - 1) / u;
+                    rn[b] = ((T + 1) / 2) * u;
+                    rsi[b] = ns;
+                    split_list[ns++] = b;
+                } else {
+                    rn[b] = -1;
+                    rsi[b] = -1;
+                }
+            }
+            nsplit_s = ns;
+        }
+        __syncthreads();
+        const int nsplit = nsplit_s;
+        if (nsplit == 0) break;
+        // extent of every projection over every splitting run: one wave per
+        // 64 consecutive positions loads all projections of its points, then
+        // reduces per run present in the wave and merges by LDS atomics
+        for (int t = tid; t < nsplit * PMAX; t += kLocalThreads) {
+            emin[t / PMAX][t % PMAX] = 0xffffffffu;
+            emax[t / PMAX][t % PMAX] = 0u;
+        }
+        __syncthreads();
+        for (int base = w * kWave; base < m; base += kLocalThreads) {
+            const int i = base + lane;
+            const int si = i < m ? rsi[run_of[i]] : -1;
+            uint32_t kv[PMAX];
+#pragma unroll
+            for (int j = 0; j < PMAX; ++j)
+                kv[j] = (j < P && si >= 0) ? orderable(vin[int64_t(j) * n + start + ord[cur][i]])
+                                           : 0u;
+            uint64_t todo = ballot(si >= 0);
+            while (todo) {
+                const int src = __ffsll((unsigned long long)todo) - 1;
+                const int cur_si = __builtin_amdgcn_readlane(si, src);
+                const bool mine = si == cur_si;
+                todo &= ~ballot(mine);
+#pragma unroll
+                for (int j = 0; j < PMAX; ++j) {
+                    if (j < P) {
+                        const uint32_t a = wave_umin(mine ? kv[j] : 0xffffffffu);
+                        const uint32_t c = wave_umax(mine ? kv[j] : 0u);
+                        if (lane == 0) {
+                            atomicMin(&emin[cur_si][j], a);
+                            atomicMax(&emax[cur_si][j], c);
+                        }
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        for (int si = tid; si < nsplit; si += kLocalThreads) {
+            int best = 0;
+            float best_ext = 0.0f;
+            for (int j = 0; j < P; ++j) {
+                const float e = from_orderable(emax[si][j]) - from_orderable(emin[si][j]);
+                if (j == 0 || e > best_ext) {
+                    best = j;
+                    best_ext = e;
+                }
+            }
+            rd[split_list[si]] = best;
+        }
+        __syncthreads();
+        // sort keys (run, key on the run's split projection, position); runs
+        // that do not split sort by (run, position), i.e. stay in place
+        for (int i = tid; i < m2; i += kLocalThreads) {
+            uint64_t key = ~uint64_t(0);
+            if (i < m) {
+                const int b = run_of[i];
+                key = (uint64_t(b) << 44) | uint64_t(i);
+                if (rn[b] >= 0) {
+                    const float v = vin[int64_t(rd[b]) * n + start + ord[cur][i]];
+                    key |= uint64_t(orderable(v)) << 12;
+                }
+            }
+            keys[i] = key;
+        }
+        __syncthreads();
+        for (int k = 2; k <= m2; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int i = tid; i < m2; i += kLocalThreads) {
+                    const int l = i ^ j;
+                    if (l > i) {
+                        const uint64_t a = keys[i], c = keys[l];
+                        const bool up = (i & k) == 0;
+                        if ((a > c) == up) {
+                            keys[i] = c;
+                            keys[l] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        // left flags by old position: sorted rank inside the run < n_left
+        for (int r = tid; r < m; r += kLocalThreads) {
+            const uint64_t key = keys[r];
+            const int i = int(key & 0xfffu), b = int(key >> 44);
+            flag[i] = (rn[b] >= 0 && r - rs[b] < rn[b]) ? 1 : 0;
+        }
+        __syncthreads();
+        {
+            int c[4], sum = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * tid + q;
+                c[q] = i < m ? flag[i] : 0;
+                sum += c[q];
+            }
+            int tot;
+            int run = local_exscan(sum, &tot);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 4 * tid + q;
+                if (i < m) lpre[i] = uint16_t(run);
+                run += c[q];
+            }
+        }
+        __syncthreads();
+        // stable partition of every splitting run
+        for (int i = tid; i < m; i += kLocalThreads) {
+            const int b = run_of[i];
+            int np = i;
+            if (rn[b] >= 0) {
+                const int s = rs[b];
+                const int lb = int(lpre[i]) - int(lpre[s]);
+                np = flag[i] ? s + lb : s + rn[b] + (i - s - lb);
+            }
+            ord[cur ^ 1][np] = ord[cur][i];
+        }
+        __syncthreads();
+        cur ^= 1;
+        // next level's runs, in order of their starts
+        if (tid == 0) {
+            const int nr = nruns_s;
+            int out = nr + nsplit;   // every splitting run becomes two
+            for (int b = nr - 1; b >= 0; --b) {
+                if (rn[b] >= 0) {
+                    out -= 2;
+                    const int s = rs[b], len = rl[b], nl = rn[b];
+                    rs[out + 1] = s + nl;
+                    rl[out + 1] = len - nl;
+                    rs[out] = s;
+                    rl[out] = nl;
+                } else {
+                    out -= 1;
+                    rs[out] = rs[b];
+                    rl[out] = rl[b];
+                }
+            }
+            nruns_s = nr + nsplit;
+        }
+        __syncthreads();
+        for (int b = w; b < nruns_s; b += kWaves)
+            for (int i = rs[b] + lane; i < rs[b] + rl[b]; i += kWave) run_of[i] = uint8_t(b);
+        __syncthreads();
+    }
+    for (int p = tid; p < m; p += kLocalThreads) {
+        const int64_t o = start + ord[cur][p];
+        idx_out[start + p] = idx_in ? idx_in[o] : int32_t(o);
+    }
+}
+
+inline unsigned nb(int64_t n, int per) { return unsigned((n + per - 1) / per); }
+
+// Leaves of a run of `size` points (the split rule above).
+int64_t count_leaves(int64_t size, int leaf, int sub, std::map<int64_t, int64_t> &memo)
+{
+    if (size <= sub) return 1;
+    auto it = memo.find(size);
+    if (it != memo.end()) return it->second;
+    const int64_t u = size > leaf ? leaf : sub;
+    const int64_t T = (size + u - 1) / u, nl = ((T + 1) / 2) * u;
+    const int64_t r = count_leaves(nl, leaf, sub, memo) + count_leaves(size - nl, leaf, sub, memo);
+    memo[size] = r;
+    return r;
+}
+
+}  // namespace
+
+bool kd_plan(KdPlan &pl, int64_t n, int leaf, int sub)
+{
+    if (pl.n == n && pl.leaf == leaf && pl.sub == sub) return true;
+    pl.n = n;
+    pl.leaf = leaf;
+    pl.sub = sub;
+    pl.levels.clear();
+    pl.local = KdLevel{};
+    pl.has_local = false;
+    std::vector<int64_t> nodes, slices;
+    std::vector<std::pair<int64_t, int64_t>> cur;
+    if (n > 0) cur.push_back({0, n});
+    int64_t max_nodes = 0, max_slices = 0;
+    std::map<int64_t, int64_t> memo;
+    while (true) {
+        bool any = false;
+        int64_t biggest = 0, most_leaves = 0;
+        for (auto &nd : cur) {
+            any |= nd.second > sub;
+            biggest = std::max(biggest, nd.second);
+            if (nd.second <= kLocalMax)
+                most_leaves = std::max(most_leaves, count_leaves(nd.second, leaf, sub, memo));
+        }
+        if (!any) break;
+        if (biggest <= kLocalMax && most_leaves <= kLocalRuns) {
+            // the rest of every subtree in one workgroup each
+            pl.local.node0 = int64_t(nodes.size()) / kNodeCols;
+            for (auto &nd : cur) nodes.insert(nodes.end(), {nd.first, nd.second, -1, 0, 0, -1});
+            pl.local.node1 = int64_t(nodes.size()) / kNodeCols;
+            pl.has_local = true;
+            break;
+        }
+        KdLevel lv;
+        lv.node0 = int64_t(nodes.size()) / kNodeCols;
+        lv.slice0 = int64_t(slices.size()) / kSliceCols;
+        std::vector<std::pair<int64_t, int64_t>> next;
+        for (auto &nd : cur) {
+            const int64_t st = nd.first, sz = nd.second;
+            const int64_t node_id = int64_t(nodes.size()) / kNodeCols;
+            int64_t nl = -1, child = -1;
+            if (sz > sub) {
+                const int64_t u = sz > leaf ? leaf : sub;
+                const int64_t T = (sz + u - 1) / u;
+                nl = ((T + 1) / 2) * u;
+                child = int64_t(next.size());
+                next.push_back({st, nl});
+                next.push_back({st + nl, sz - nl});
+            } else {
+                next.push_back({st, sz});
+            }
+            const int64_t sb = int64_t(slices.size()) / kSliceCols;
+            for (int64_t s = st; s < st + sz; s += kSlice) {
+                slices.push_back(s);
+                slices.push_back(std::min<int64_t>(kSlice, st + sz - s));
+                slices.push_back(node_id);
+            }
+            const int64_t se = int64_t(slices.size()) / kSliceCols;
+            nodes.insert(nodes.end(), {st, sz, nl, sb, se, child});
+        }
+        lv.node1 = int64_t(nodes.size()) / kNodeCols;
+        lv.slice1 = int64_t(slices.size()) / kSliceCols;
+        max_nodes = std::max(max_nodes, lv.node1 - lv.node0);
+        max_slices = std::max(max_slices, lv.slice1 - lv.slice0);
+        pl.levels.push_back(lv);
+        cur.swap(next);
+    }
+    // the last upper level's children are not upper-level nodes: no slots
+    if (!pl.levels.empty()) {
+        const KdLevel &last = pl.levels.back();
+        for (int64_t i = last.node0; i < last.node1; ++i) nodes[i * kNodeCols + 5] = -1;
+    }
+    pl.max_nodes = max_nodes;
+    pl.max_slices = max_slices;
+    if (!pl.node_tab.ensure(sizeof(int64_t) * std::max<size_t>(nodes.size(), 1)) ||
+        !pl.slice_tab.ensure(sizeof(int64_t) * std::max<size_t>(slices.size(), 1))) {
+        pl.n = -1;
+        return false;
+    }
+    if ((!nodes.empty() && hipMemcpy(pl.node_tab.p, nodes.data(), sizeof(int64_t) * nodes.size(),
+                                     hipMemcpyHostToDevice) != hipSuccess) ||
+        (!slices.empty() && hipMemcpy(pl.slice_tab.p, slices.data(),
+                                      sizeof(int64_t) * slices.size(),
+                                      hipMemcpyHostToDevice) != hipSuccess)) {
+        pl.n = -1;
+        return false;
+    }
+    return true;
+}
+
+bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P)
+{
+    const int64_t nn = std::max<int64_t>(n, 1);
+    const int64_t ms = std::max<int64_t>(pl.max_slices, 1), mn = std::max<int64_t>(pl.max_nodes, 1);
+    bool ok = true;
+    ok &= w.idx[0].ensure(sizeof(int32_t) * nn);
+    ok &= w.idx[1].ensure(sizeof(int32_t) * nn);
+    ok &= w.val[0].ensure(sizeof(float) * P * nn);
+    ok &= w.val[1].ensure(sizeof(float) * P * nn);
+    ok &= w.ext[0].ensure(sizeof(uint32_t) * 2 * P * mn);
+    ok &= w.ext[1].ensure(sizeof(uint32_t) * 2 * P * mn);
+    ok &= w.hist.ensure(sizeof(int32_t) * kBins * mn);
+    ok &= w.cnt.ensure(sizeof(int64_t) * 2 * ms);
+    ok &= w.dim.ensure(sizeof(int32_t) * mn);
+    ok &= w.prefix.ensure(sizeof(uint32_t) * mn);
+    ok &= w.rank.ensure(sizeof(int64_t) * mn);
+    ok &= w.done.ensure(sizeof(int32_t) * mn);
+    return ok;
+}
+
+hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
+                    int32_t *perm, hipStream_t s)
+{
+    if (n == 0) return hipSuccess;
+    const int64_t mn = std::max<int64_t>(pl.max_nodes, 1), ms = std::max<int64_t>(pl.max_slices, 1);
+    if (pl.n != n || (pl.levels.empty() && !pl.has_local) || P < 1 || P > 32 ||
+        w.idx[0].cap < sizeof(int32_t) * size_t(n) || w.idx[1].cap < sizeof(int32_t) * size_t(n) ||
+        w.val[0].cap < sizeof(float) * P * size_t(n) ||
+        w.val[1].cap < sizeof(float) * P * size_t(n) ||
+        w.ext[0].cap < sizeof(uint32_t) * 2 * P * size_t(mn) ||
+        w.ext[1].cap < sizeof(uint32_t) * 2 * P * size_t(mn) ||
+        w.hist.cap < sizeof(int32_t) * kBins * size_t(mn) ||
+        w.cnt.cap < sizeof(int64_t) * 2 * size_t(ms) || w.dim.cap < sizeof(int32_t) * size_t(mn) ||
+        w.prefix.cap < sizeof(uint32_t) * size_t(mn) || w.rank.cap < sizeof(int64_t) * size_t(mn) ||
+        w.done.cap < sizeof(int32_t) * size_t(mn))
+        return hipErrorInvalidValue;
+    const int32_t *idx_in = nullptr;   // level 0 reads the identity order
+    const float *vin = vals;
+    int cur = 0;
+    const int64_t *nodes = pl.node_tab.as<int64_t>();
+    const int64_t *slices = pl.slice_tab.as<int64_t>();
+    int32_t *hist = w.hist.as<int32_t>();
+    int32_t *done = w.done.as<int32_t>();
+    int32_t *dim = w.dim.as<int32_t>();
+    uint32_t *prefix = w.prefix.as<uint32_t>();
+    int64_t *rank = w.rank.as<int64_t>();
+    int64_t *cnt = w.cnt.as<int64_t>();
+    if (!pl.levels.empty()) {
+        k_kd_zero<<<nb(kBins * mn, kThreads), kThreads, 0, s>>>(hist, kBins * mn);
+        k_kd_zero<<<nb(mn, kThreads), kThreads, 0, s>>>(done, mn);
+        k_kd_ext_reset<<<nb(P, kThreads), kThreads, 0, s>>>(w.ext[0].as<uint32_t>(), P);
+        const KdLevel &lv = pl.levels[0];
+        const int64_t *st = slices + lv.slice0 * kSliceCols;
+        if (P <= 16)
+            k_kd_root_ext<16><<<unsigned(lv.slice1 - lv.slice0), kThreads, 0, s>>>(
+                st, n, P, vals, w.ext[0].as<uint32_t>());
+        else
+            k_kd_root_ext<32><<<unsigned(lv.slice1 - lv.slice0), kThreads, 0, s>>>(
+                st, n, P, vals, w.ext[0].as<uint32_t>());
+    }
+    for (size_t li = 0; li < pl.levels.size(); ++li) {
+        const KdLevel &lv = pl.levels[li];
+        const int64_t nn = lv.node1 - lv.node0, ns = lv.slice1 - lv.slice0;
+        const int64_t *nt = nodes + lv.node0 * kNodeCols;
+        const int64_t *st = slices + lv.slice0 * kSliceCols;
+        uint32_t *ext = w.ext[li & 1].as<uint32_t>();
+        uint32_t *ext_next = (li + 1 < pl.levels.size()) ? w.ext[(li + 1) & 1].as<uint32_t>()
+                                                          : nullptr;
+        k_kd_split<<<nb(nn, kThreads), kThreads, 0, s>>>(nt, nn, P, ext, ext_next, dim, prefix,
+                                                          rank);
+        for (int r = 0; r < 3; ++r)
+            k_kd_hist_select<<<unsigned(ns), kThreads, 0, s>>>(nt, st, lv.node0, n, r, vin, dim,
+                                                              prefix, rank, hist, done);
+        k_kd_count<<<unsigned(ns), kThreads, 0, s>>>(st, lv.node0, n, vin, dim, prefix, cnt);
+        int32_t *idx_out = w.idx[cur].as<int32_t>();
+        float *vout = w.val[cur].as<float>();
+        if (P <= 16)
+            k_kd_scatter<16><<<unsigned(ns), kThreads, 0, s>>>(nt, st, lv.node0, lv.slice0, n, P,
+                                                               idx_in, vin, dim, prefix, rank,
+                                                               cnt, idx_out, vout, ext_next);
+        else
+            k_kd_scatter<32><<<unsigned(ns), kThreads, 0, s>>>(nt, st, lv.node0, lv.slice0, n, P,
+                                                               idx_in, vin, dim, prefix, rank,
+                                                               cnt, idx_out, vout, ext_next);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        idx_in = idx_out;
+        vin = vout;
+        cur ^= 1;
+    }
+    if (pl.has_local) {
+        const int64_t *nt = nodes + pl.local.node0 * kNodeCols;
+        const unsigned nl = unsigned(pl.local.node1 - pl.local.node0);
+        if (P <= 16)
+            k_kd_local<16><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, idx_in, vin,
+                                                        perm);
+        else
+            k_kd_local<32><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, idx_in, vin,
+                                                        perm);
+        return hipGetLastError();
+    }
+    return hipMemcpyAsync(perm, idx_in, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+}
+
+}  // namespace ngd

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "../../include/ngd.h"
 
@@ -48,6 +49,34 @@ struct DevBuf {
     void release();
     template <typename T> T *as() const { return static_cast<T *>(p); }
 };
+
+// k-d ordering (kd.hip): per-level node and slice tables of the upper
+// levels, and the nodes whose subtrees finish in one workgroup each; laid
+// out on the host from (n, leaf, sub) alone and kept while they stay the same.
+struct KdLevel {
+    int64_t node0 = 0, node1 = 0, slice0 = 0, slice1 = 0;
+};
+struct KdPlan {
+    int64_t n = -1;
+    int leaf = 0, sub = 0;
+    std::vector<KdLevel> levels;   // upper levels
+    bool has_local = false;
+    KdLevel local;                 // node rows of the subtree workgroups
+    int64_t max_nodes = 0, max_slices = 0;
+    DevBuf node_tab;    // rows: start, size, n_left (-1 leaf), slice begin, slice end, child
+    DevBuf slice_tab;   // rows: start, length, node
+};
+struct KdWork {
+    DevBuf idx[2], val[2], ext[2];
+    DevBuf hist, done, cnt, dim, prefix, rank;
+};
+bool kd_plan(KdPlan &pl, int64_t n, int leaf, int sub);
+bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P);
+// Orders n points with P <= 32 projections (vals: P x n, point order) and
+// writes the order (position -> point) to perm.  Needs a plan with at least
+// one split (n > sub).
+hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
+                    int32_t *perm, hipStream_t s);
 
 }  // namespace ngd
 
@@ -126,6 +155,8 @@ struct ngd_cull {
     ngd::DevBuf scan_tmp;      // scan block sums
     ngd::DevBuf stats;         // 2 int64: total, max per tile
     int64_t *stats_host = nullptr;  // pinned: total, max per tile, items
+    ngd::KdPlan kd_q, kd_g;    // k-d tiling plans of the queries and the Gaussians
+    ngd::KdWork kd_work;
 };
 
 namespace ngd {

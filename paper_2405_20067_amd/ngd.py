@@ -34,11 +34,11 @@ class NgdError(RuntimeError):
 
 class CullParams(ctypes.Structure):
     _fields_ = [("n_proj", ctypes.c_int), ("tau", ctypes.c_float), ("tile", ctypes.c_int),
-                ("key_proj", ctypes.c_int), ("key_bits", ctypes.c_int)]
+                ("key_proj", ctypes.c_int), ("key_bits", ctypes.c_int), ("tiling", ctypes.c_int)]
 
     def __repr__(self):
         return (f"CullParams(n_proj={self.n_proj}, tau={self.tau:g}, tile={self.tile}, "
-                f"key_proj={self.key_proj}, key_bits={self.key_bits})")
+                f"key_proj={self.key_proj}, key_bits={self.key_bits}, tiling={self.tiling})")
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)

@@ -34,10 +34,11 @@ def _mixture(torch_cuda, mix):
     return m
 
 
-def _params(tile=256, tau=1e-4, n_proj=16, key_proj=16, key_bits=2):
+def _params(tile=256, tau=1e-4, n_proj=16, key_proj=16, key_bits=2, tiling=0):
     from paper_2405_20067_amd import ngd
     p = ngd.default_params()
     p.tile, p.tau, p.n_proj, p.key_proj, p.key_bits = tile, tau, n_proj, key_proj, key_bits
+    p.tiling = tiling
     return p
 
 
@@ -47,16 +48,25 @@ CULL_CASES = [
     dict(n=10, k=1500, q=4100, tile=256),
     dict(n=3, k=64, q=70, tile=1),
     dict(n=10, k=65, q=257, tile=64),
-    dict(n=2, k=130, q=1000, tile=1024, key_bits=3, key_proj=10),
-    # long lists: tiles with several forward items, Gaussians with several
-    # backward items
-    dict(n=4, k=3000, q=20000, tile=256),
-    dict(n=6, k=2500, q=9000, tile=512),
+    dict(n=2, k=130, q=1000, tile=1024, key_bits=3, key_proj=10, tiling=1),
+    dict(n=10, k=1500, q=4100, tile=256, tiling=1),
+    dict(n=6, k=5000, q=70000, tile=256),
+    # long lists: tiles with several forward items (more than 512 candidates)
+    # and, where marked, Gaussians with several backward items (more than 32
+    # tiles)
+    dict(n=4, k=3000, q=20000, tile=256, long=2),
+    dict(n=6, k=2500, q=9000, tile=512, long=1),
+    dict(n=10, k=3000, q=9000, tile=256, sdiag=(3.0, 30.0), long=2),
 ]
 
 
+def _case(cfg):
+    return case(cfg["n"], cfg["k"], cfg["q"], seed=cfg["n"] * 7 + cfg["k"], sdiag=cfg.get("sdiag"))
+
+
 def _ids(c):
-    return "-".join(f"{k}{v}" for k, v in c.items())
+    fmt = lambda v: "-".join(f"{x:g}" for x in v) if isinstance(v, tuple) else v
+    return "-".join(f"{k}{fmt(v)}" for k, v in c.items())
 
 
 @pytest.mark.parametrize("cfg", CULL_CASES, ids=_ids)
@@ -65,14 +75,15 @@ def test_cull_bit_exact(torch_cuda, cfg):
     n, k, q = cfg["n"], cfg["k"], cfg["q"]
     key_bits = cfg.get("key_bits", 2)
     key_proj = cfg.get("key_proj", 16)
-    mix, x, proj = case(n, k, q, seed=n * 7 + k)
+    tiling = cfg.get("tiling", 0)
+    mix, x, proj = _case(cfg)
     m = _mixture(torch_cuda, mix)
     xd = dev(x)
     c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"], key_bits=key_bits,
-                                               key_proj=key_proj))
+                                               key_proj=key_proj, tiling=tiling))
     got = c.export()
     want = oracle.cull(mix["mean"], mix["factor"], x, proj, tau=1e-4, tile=cfg["tile"],
-                       key_proj=key_proj, key_bits=key_bits)
+                       key_proj=key_proj, key_bits=key_bits, tiling=tiling)
     assert got["ntiles"] == want["ntiles"]
     assert got["total"] == want["total"]
     for key in ("perm", "gperm", "tile_off", "cand", "g_off", "g_tiles", "tile_lo", "tile_hi"):
@@ -81,14 +92,14 @@ def test_cull_bit_exact(torch_cuda, cfg):
     assert got["max_per_tile"] == (lens.max() if lens.size else 0)
 
 
-@pytest.mark.parametrize("cfg", CULL_CASES[:3] + CULL_CASES[4:], ids=_ids)
+@pytest.mark.parametrize("cfg", [c for c in CULL_CASES if c["tile"] > 1], ids=_ids)
 def test_culled_forward_matches_oracle(torch_cuda, cfg):
     from paper_2405_20067_amd import ngd
     n, k, q = cfg["n"], cfg["k"], cfg["q"]
-    mix, x, proj = case(n, k, q, seed=n * 7 + k)
+    mix, x, proj = _case(cfg)
     m = _mixture(torch_cuda, mix)
     xd = dev(x)
-    c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"]))
+    c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"], tiling=cfg.get("tiling", 0)))
     f = host(ngd.eval_mixture(m, c, xd))
     full = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x)
     assert normwise(f, full) <= TOL_FP32
@@ -134,7 +145,7 @@ def test_dense_backward_matches_oracle(torch_cuda, cfg):
         assert normwise(a, b) <= TOL_FP32, name
 
 
-@pytest.mark.parametrize("cfg", [CULL_CASES[i] for i in (0, 1, 2, 4, 6, 7)], ids=_ids)
+@pytest.mark.parametrize("cfg", [c for c in CULL_CASES if c["tile"] > 1 and c["n"] > 2], ids=_ids)
 def test_culled_backward_matches_oracle(torch_cuda, cfg):
     """The backward of the culled forward is the gradient of the sum over the
     candidate pairs: compared with the oracle's gradient over exactly those
@@ -144,15 +155,15 @@ def test_culled_backward_matches_oracle(torch_cuda, cfg):
     is bounded loosely and reported."""
     from paper_2405_20067_amd import ngd
     n, k, q = cfg["n"], cfg["k"], cfg["q"]
-    mix, x, proj = case(n, k, q, seed=n * 7 + k)
+    mix, x, proj = _case(cfg)
     g = inputs.gen_grad_out(q, seed=k)
     m = _mixture(torch_cuda, mix)
     xd = dev(x)
-    c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"]))
+    c = ngd.Cull().build(m, xd, proj, _params(tile=cfg["tile"], tiling=cfg.get("tiling", 0)))
     exp = c.export()
-    if cfg["k"] >= 2500:   # the long-list cases really exercise multiple items
+    if cfg.get("long", 0) >= 1:   # the long-list cases really exercise multiple items
         assert np.diff(exp["tile_off"]).max() > 512
-    if cfg["k"] >= 2500 and n == 4:
+    if cfg.get("long", 0) >= 2:
         assert np.diff(exp["g_off"]).max() > 32
     got = [host(t) for t in ngd.eval_backward(m, c, xd, dev(g))]
     sel, qoff, qidx = per_gaussian_csr(exp, q, cfg["tile"])
