@@ -180,6 +180,7 @@ template <int N, int PMAX>
 __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P,
                                                       const int32_t *__restrict__ perm,
                                                       const float *__restrict__ qr,
+                                                      const float *__restrict__ qr_s,
                                                       const float *__restrict__ queries,
                                                       float *__restrict__ qs,
                                                       float *__restrict__ tlo,
@@ -202,7 +203,8 @@ __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P
 #pragma unroll
         for (int j = 0; j < PMAX; ++j) {
             if (j < P) {
-                const float v = qr[j * q + idx];
+                // projections in tile order when the ordering left them so
+                const float v = qr_s ? qr_s[j * q + p] : qr[j * q + idx];
                 lo[j] = fminf(lo[j], v);
                 hi[j] = fmaxf(hi[j], v);
             }
@@ -244,20 +246,68 @@ __global__ __launch_bounds__(kThreads) void k_gauss_gather(
         *reinterpret_cast<float4 *>(grec + s * R + e) =
             *reinterpret_cast<const float4 *>(rec + i * R + e);
     for (int j = 0; j < P; ++j) {
-        g_mr_s[j * k + s] = g_mr[j * k + i];
+        if (g_mr) g_mr_s[j * k + s] = g_mr[j * k + i];   // null: already in order
         g_thr_s[j * k + s] = g_thr[j * k + i];
     }
 }
 
+// Bounds of every super-tile: the union of its tiles' bounds.
+__global__ __launch_bounds__(kThreads) void k_super_bounds(int64_t ntiles, int P,
+                                                           const float *__restrict__ tlo,
+                                                           const float *__restrict__ thi,
+                                                           float *__restrict__ slo,
+                                                           float *__restrict__ shi)
+{
+    const int64_t nsup = (ntiles + kSuperTiles - 1) / kSuperTiles;
+    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (i >= nsup * P) return;
+    const int64_t sp = i / P;
+    const int j = int(i - sp * P);
+    const int64_t t1 = (sp + 1) * kSuperTiles < ntiles ? (sp + 1) * kSuperTiles : ntiles;
+    float a = INFINITY, b = -INFINITY;
+    for (int64_t t = sp * kSuperTiles; t < t1; ++t) {
+        a = fminf(a, tlo[t * P + j]);
+        b = fmaxf(b, thi[t * P + j]);
+    }
+    slo[i] = a;
+    shi[i] = b;
+}
+
 // ---- the interval test (Eq. 5 per tile) -----------------------------------
-// One wave per chunk of 64 sorted Gaussians (lane = Gaussian, its projected
-// means and thresholds in registers) walks a range of tiles with the tile
-// bounds wave-uniform; it leaves a tile as soon as no lane survives.
+// One wave per chunk of 64 ordered Gaussians (lane = Gaussian, its projected
+// means and thresholds in registers) walks a range of tiles with the bounds
+// wave-uniform, first per super-tile of kSuperTiles tiles, then per tile for
+// the lanes still alive; every test stops as soon as no lane survives.  A
+// super-tile's interval contains each of its tiles' intervals, so its
+// distance is never larger (rounding is monotone): a lane culled for the
+// super-tile is culled for each tile, and the masks are those of the plain
+// per-tile test bit for bit.
+template <int PMAX>
+__device__ __forceinline__ bool interval_test(bool alive, int P, const float (&mr)[PMAX],
+                                              const float (&thr)[PMAX],
+                                              const float *__restrict__ lo,
+                                              const float *__restrict__ hi)
+{
+#pragma unroll
+    for (int j = 0; j < PMAX; ++j) {
+        if (j < P) {
+            const float a = lo[j] - mr[j];
+            const float b = mr[j] - hi[j];
+            const float dist = fmaxf(fmaxf(a, b), 0.0f);
+            const float d2 = dist * dist;
+            alive = alive && (d2 <= thr[j]);
+            if (ballot(alive) == 0) break;
+        }
+    }
+    return alive;
+}
+
 template <int PMAX>
 __global__ __launch_bounds__(kThreads) void k_cull_test(
     int64_t k, int64_t ntiles, int64_t tpad, int P, int tiles_per_wave,
     const float *__restrict__ g_mr_s, const float *__restrict__ g_thr_s,
-    const float *__restrict__ tlo, const float *__restrict__ thi, uint64_t *__restrict__ masks)
+    const float *__restrict__ tlo, const float *__restrict__ thi,
+    const float *__restrict__ slo, const float *__restrict__ shi, uint64_t *__restrict__ masks)
 {
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t nchunks = (k + kWave - 1) / kWave;
@@ -271,31 +321,24 @@ __global__ __launch_bounds__(kThreads) void k_cull_test(
         mr[j] = (valid && j < P) ? g_mr_s[j * k + s] : 0.0f;
         thr[j] = (valid && j < P) ? g_thr_s[j * k + s] : -1.0f;
     }
+    // tiles_per_wave is a multiple of 64 (and so of kSuperTiles)
     const int64_t t0 = int64_t(blockIdx.y) * tiles_per_wave;
     const int64_t t1 = (t0 + tiles_per_wave < ntiles) ? t0 + tiles_per_wave : ntiles;
-    uint64_t mine = 0;
-    for (int64_t t = t0; t < t1; ++t) {
-        const float *lo = tlo + t * P;
-        const float *hi = thi + t * P;
-        bool alive = valid;
-#pragma unroll
-        for (int j = 0; j < PMAX; ++j) {
-            if (j < P) {
-                const float a = lo[j] - mr[j];
-                const float b = mr[j] - hi[j];
-                const float dist = fmaxf(fmaxf(a, b), 0.0f);
-                const float d2 = dist * dist;
-                alive = alive && (d2 <= thr[j]);
-                if (ballot(alive) == 0) break;
+    for (int64_t tb = t0; tb < t1; tb += kWave) {
+        const int64_t te = (tb + kWave < t1) ? tb + kWave : t1;
+        uint64_t mine = 0;   // lane l: mask of tile tb + l
+        for (int64_t sb = tb; sb < te; sb += kSuperTiles) {
+            const int64_t sp = sb / kSuperTiles;
+            const bool sup = interval_test<PMAX>(valid, P, mr, thr, slo + sp * P, shi + sp * P);
+            if (ballot(sup) == 0) continue;
+            const int64_t se = (sb + kSuperTiles < te) ? sb + kSuperTiles : te;
+            for (int64_t t = sb; t < se; ++t) {
+                const bool alive = interval_test<PMAX>(sup, P, mr, thr, tlo + t * P, thi + t * P);
+                const uint64_t m = ballot(alive);
+                if (lane == int(t - tb)) mine = m;
             }
         }
-        const uint64_t m = ballot(alive);
-        const int slot = int((t - t0) & (kWave - 1));
-        if (lane == slot) mine = m;
-        if (slot == kWave - 1 || t == t1 - 1) {
-            const int64_t tb = t - slot;
-            if (tb + lane <= t) masks[c * tpad + tb + lane] = mine;
-        }
+        if (tb + lane < te) masks[c * tpad + tb + lane] = mine;
     }
 }
 
@@ -470,6 +513,10 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     int which = 0;
+    // the k-d order leaves the projections in order: tile bounds and the
+    // ordered means read them without a gather
+    const float *qr_s = nullptr;
+    bool g_sorted = false;
     if (c->params.tiling == 0) {
         // k-d order of the query projections (runs of `tile`, and of 64
         // inside those) and of the projected means (runs of 64, the chunks
@@ -478,15 +525,20 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
             if (q <= std::min(c->params.tile, kWave))
                 k_iota<<<nblk(q, kThreads), kThreads, 0, s>>>(c->perm.as<int32_t>(), q);
             else if ((e = kd_order(c->kd_q, c->kd_work, P, c->qr.as<float>(), q,
-                                   c->perm.as<int32_t>(), s)) != hipSuccess)
+                                   c->perm.as<int32_t>(), c->qr_s.as<float>(), s)) != hipSuccess)
                 return e;
+            else
+                qr_s = c->qr_s.as<float>();
         }
         if (k > 0) {
             if (k <= kWave)
                 k_iota<<<nblk(k, kThreads), kThreads, 0, s>>>(c->gperm.as<int32_t>(), k);
             else if ((e = kd_order(c->kd_g, c->kd_work, P, c->g_mr.as<float>(), k,
-                                   c->gperm.as<int32_t>(), s)) != hipSuccess)
+                                   c->gperm.as<int32_t>(), c->g_mr_s.as<float>(), s)) !=
+                     hipSuccess)
                 return e;
+            else
+                g_sorted = true;
         }
     }
     // Morton: queries: keys, sort -> perm
@@ -520,18 +572,22 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         const int bt = int(std::min<int64_t>(1024, (int64_t(c->params.tile) + 63) / 64 * 64));
         if (P <= 16)
             k_tile_bounds<N, 16><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
-                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), queries,
+                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s, queries,
                 c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>());
         else
             k_tile_bounds<N, 32><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
-                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), queries,
+                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s, queries,
                 c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>());
+        const int64_t nsup = (c->ntiles + kSuperTiles - 1) / kSuperTiles;
+        k_super_bounds<<<nblk(nsup * P, kThreads), kThreads, 0, s>>>(
+            c->ntiles, P, c->tile_lo.as<float>(), c->tile_hi.as<float>(), c->sup_lo.as<float>(),
+            c->sup_hi.as<float>());
     }
     if (k > 0) {
         k_gauss_gather<<<nblk(k, kThreads), kThreads, 0, s>>>(
-            k, R, P, c->gperm.as<int32_t>(), mix->rec.as<float>(), c->g_mr.as<float>(),
-            c->g_thr.as<float>(), c->grec.as<float>(), c->g_mr_s.as<float>(),
-            c->g_thr_s.as<float>());
+            k, R, P, c->gperm.as<int32_t>(), mix->rec.as<float>(),
+            g_sorted ? nullptr : c->g_mr.as<float>(), c->g_thr.as<float>(), c->grec.as<float>(),
+            c->g_mr_s.as<float>(), c->g_thr_s.as<float>());
     }
     k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long *>(c->stats.p), 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -551,11 +607,13 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         k_cull_test<16><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,
                                                    c->g_mr_s.as<float>(), c->g_thr_s.as<float>(),
                                                    c->tile_lo.as<float>(), c->tile_hi.as<float>(),
+                                                   c->sup_lo.as<float>(), c->sup_hi.as<float>(),
                                                    c->masks.as<uint64_t>());
     else
         k_cull_test<32><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,
                                                    c->g_mr_s.as<float>(), c->g_thr_s.as<float>(),
                                                    c->tile_lo.as<float>(), c->tile_hi.as<float>(),
+                                                   c->sup_lo.as<float>(), c->sup_hi.as<float>(),
                                                    c->masks.as<uint64_t>());
     // per-tile counts -> offsets
     const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
@@ -765,6 +823,9 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->gs.ensure(sizeof(float) * 3 * qq);
     ok &= c->tile_lo.ensure(sizeof(float) * T * P);
     ok &= c->tile_hi.ensure(sizeof(float) * T * P);
+    ok &= c->sup_lo.ensure(sizeof(float) * ((T + kSuperTiles - 1) / kSuperTiles) * P);
+    ok &= c->sup_hi.ensure(sizeof(float) * ((T + kSuperTiles - 1) / kSuperTiles) * P);
+    if (c->params.tiling == 0) ok &= c->qr_s.ensure(sizeof(float) * P * qq);
     ok &= c->grec.ensure(sizeof(float) * kk * rec_stride(int(n)));
     ok &= c->g_mr_s.ensure(sizeof(float) * P * kk);
     ok &= c->g_thr_s.ensure(sizeof(float) * P * kk);

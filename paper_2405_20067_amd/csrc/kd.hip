@@ -18,7 +18,7 @@
 //   split    per node: the projection of largest extent, from the node's
 //            min / max (accumulated by the previous level's scatter; for
 //            the root by a pass over its slices)
-//   hist     per slice: histogram of one radix digit (11, 11, 10 bits of
+//   hist     per slice of kHistSlice points: histogram of one radix digit (11, 11, 10 bits of
 //            the order-preserving key) among the points that match the
 //            digits found so far, added into the node's histogram; the
 //            node's last slice then selects the bin that holds the rank
@@ -31,7 +31,8 @@
 //            children's min / max are accumulated for the next split
 // Nodes of at most kLocalMax points finish their whole subtree in one
 // workgroup each (k_kd_local): the order and the sort keys stay in LDS, and
-// every level of the subtree is one bitonic sort of (run, key, position).
+// every level of the subtree is one bitonic sort of (run, key, position)
+// over blocks of the smallest power-of-two length that holds every run.
 #include <algorithm>
 #include <map>
 #include <vector>
@@ -43,7 +44,8 @@ namespace ngd {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kSlice = 1024;
+constexpr int kSlice = 1024;        // points per scatter / count workgroup
+constexpr int kHistSlice = 8192;    // points per histogram workgroup
 constexpr int kBins = 2048;
 constexpr int kShift[3] = {21, 10, 0};
 constexpr int kWidth[3] = {11, 11, 10};
@@ -54,8 +56,9 @@ constexpr int kLocalRuns = 128;     // runs per subtree (8-bit run ids)
 constexpr int kLocalSplit = 64;     // runs split at one level of a subtree
 
 // node table row: start, size, n_left (-1: leaf), first slice, end slice,
-// first child's index in the next level (-1: none)
-constexpr int kNodeCols = 6;
+// first child's index in the next level (-1: none), first histogram slice,
+// end histogram slice
+constexpr int kNodeCols = 8;
 // slice table row: start, length, node
 constexpr int kSliceCols = 3;
 
@@ -249,6 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_kd_hist_select(
     const int shift = kShift[round], width = kWidth[round];
     const uint32_t pre = prefix[nd];
     const uint32_t mask = (1u << width) - 1u;
+#pragma unroll 8
     for (int64_t i = threadIdx.x; i < len; i += kThreads) {
         const uint32_t key = orderable(vin[int64_t(d) * n + s0 + i]);
         const bool match = (round == 0) || ((key >> (shift + width)) == pre);
@@ -262,7 +266,7 @@ __global__ __launch_bounds__(kThreads) void k_kd_hist_select(
     __syncthreads();
     if (threadIdx.x == 0) {
         const int64_t *row = nodes + nd * kNodeCols;
-        const int nsl = int(row[4] - row[3]);
+        const int nsl = int(row[7] - row[6]);
         last = atomicAdd(&node_done[nd], 1) == nsl - 1;
     }
     __syncthreads();
@@ -453,7 +457,7 @@ template <int PMAX>
 __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
     const int64_t *__restrict__ nodes, int64_t n, int P, int leaf, int sub,
     const int32_t *__restrict__ idx_in, const float *__restrict__ vin,
-    int32_t *__restrict__ idx_out)
+    int32_t *__restrict__ idx_out, float *__restrict__ vout)
 {
     __shared__ uint64_t keys[kLocalMax];
     __shared__ uint16_t ord[2][kLocalMax];
@@ -463,7 +467,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
     __shared__ int rs[kLocalRuns], rl[kLocalRuns], rn[kLocalRuns], rd[kLocalRuns], rsi[kLocalRuns];
     __shared__ int split_list[kLocalSplit];
     __shared__ uint32_t emin[kLocalSplit][PMAX], emax[kLocalSplit][PMAX];
-    __shared__ int nruns_s, nsplit_s;
+    __shared__ int nruns_s, nsplit_s, sortlen_s;
 
     const int64_t *row = nodes + int64_t(blockIdx.x) * kNodeCols;
     const int64_t start = row[0];
@@ -472,6 +476,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
     constexpr int kWaves = kLocalThreads / kWave;
     int m2 = 1;
     while (m2 < m) m2 <<= 1;
+    constexpr int kPer = kLocalMax / kLocalThreads;   // positions per thread
 
     for (int i = tid; i < m; i += kLocalThreads) {
         ord[0][i] = uint16_t(i);
@@ -502,6 +507,15 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
                 }
             }
             nsplit_s = ns;
+            // every run inside one aligned block of L positions (L a power
+            // of two): sorting each block sorts every run
+            int maxlen = 1;
+            for (int b = 0; b < nruns_s; ++b) maxlen = rl[b] > maxlen ? rl[b] : maxlen;
+            int L = 1;
+            while (L < maxlen) L <<= 1;
+            for (int b = 0; b < nruns_s; ++b)
+                if (rs[b] / L != (rs[b] + rl[b] - 1) / L) L = m2;
+            sortlen_s = L < m2 ? L : m2;
         }
         __syncthreads();
         const int nsplit = nsplit_s;
@@ -557,7 +571,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
         __syncthreads();
         // sort keys (run, key on the run's split projection, position); runs
         // that do not split sort by (run, position), i.e. stay in place
-        for (int i = tid; i < m2; i += kLocalThreads) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int i = tid + q * kLocalThreads;
+            if (i >= m2) break;
             uint64_t key = ~uint64_t(0);
             if (i < m) {
                 const int b = run_of[i];
@@ -570,16 +587,22 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
             keys[i] = key;
         }
         __syncthreads();
-        for (int k = 2; k <= m2; k <<= 1) {
+        // bitonic sort of every aligned block of L keys, ascending (the last
+        // merge of a block sorts it up whatever its position)
+        const int L = sortlen_s;
+        for (int k = 2; k <= L; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
-                for (int i = tid; i < m2; i += kLocalThreads) {
-                    const int l = i ^ j;
-                    if (l > i) {
-                        const uint64_t a = keys[i], c = keys[l];
-                        const bool up = (i & k) == 0;
+#pragma unroll
+                for (int q = 0; q < kPer / 2; ++q) {
+                    // pair number -> lower index i (bit j clear), partner i + j
+                    const int pr = tid + q * kLocalThreads;
+                    const int i = ((pr & ~(j - 1)) << 1) | (pr & (j - 1));
+                    if (i + j < m2) {
+                        const uint64_t a = keys[i], c = keys[i + j];
+                        const bool up = k == L || (i & k) == 0;
                         if ((a > c) == up) {
                             keys[i] = c;
-                            keys[l] = a;
+                            keys[i + j] = a;
                         }
                     }
                 }
@@ -587,7 +610,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
             }
         }
         // left flags by old position: sorted rank inside the run < n_left
-        for (int r = tid; r < m; r += kLocalThreads) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int r = tid + q * kLocalThreads;
+            if (r >= m) break;
             const uint64_t key = keys[r];
             const int i = int(key & 0xfffu), b = int(key >> 44);
             flag[i] = (rn[b] >= 0 && r - rs[b] < rn[b]) ? 1 : 0;
@@ -612,7 +638,10 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
         }
         __syncthreads();
         // stable partition of every splitting run
-        for (int i = tid; i < m; i += kLocalThreads) {
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int i = tid + q * kLocalThreads;
+            if (i >= m) break;
             const int b = run_of[i];
             int np = i;
             if (rn[b] >= 0) {
@@ -649,9 +678,21 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
             for (int i = rs[b] + lane; i < rs[b] + rl[b]; i += kWave) run_of[i] = uint8_t(b);
         __syncthreads();
     }
-    for (int p = tid; p < m; p += kLocalThreads) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int p = tid + q * kLocalThreads;
+        if (p >= m) break;
         const int64_t o = start + ord[cur][p];
         idx_out[start + p] = idx_in ? idx_in[o] : int32_t(o);
+        if (vout) {
+            float v[PMAX];
+#pragma unroll
+            for (int j = 0; j < PMAX; ++j)
+                if (j < P) v[j] = vin[int64_t(j) * n + o];
+#pragma unroll
+            for (int j = 0; j < PMAX; ++j)
+                if (j < P) vout[int64_t(j) * n + start + p] = v[j];
+        }
     }
 }
 
@@ -699,7 +740,8 @@ bool kd_plan(KdPlan &pl, int64_t n, int leaf, int sub)
         if (biggest <= kLocalMax && most_leaves <= kLocalRuns) {
             // the rest of every subtree in one workgroup each
             pl.local.node0 = int64_t(nodes.size()) / kNodeCols;
-            for (auto &nd : cur) nodes.insert(nodes.end(), {nd.first, nd.second, -1, 0, 0, -1});
+            for (auto &nd : cur)
+                nodes.insert(nodes.end(), {nd.first, nd.second, -1, 0, 0, -1, 0, 0});
             pl.local.node1 = int64_t(nodes.size()) / kNodeCols;
             pl.has_local = true;
             break;
@@ -729,10 +771,23 @@ bool kd_plan(KdPlan &pl, int64_t n, int leaf, int sub)
                 slices.push_back(node_id);
             }
             const int64_t se = int64_t(slices.size()) / kSliceCols;
-            nodes.insert(nodes.end(), {st, sz, nl, sb, se, child});
+            nodes.insert(nodes.end(), {st, sz, nl, sb, se, child, 0, 0});
         }
         lv.node1 = int64_t(nodes.size()) / kNodeCols;
         lv.slice1 = int64_t(slices.size()) / kSliceCols;
+        // the histogram slices of the level's nodes, after its slices
+        lv.hslice0 = lv.slice1;
+        for (int64_t nd = lv.node0; nd < lv.node1; ++nd) {
+            const int64_t st = nodes[nd * kNodeCols + 0], sz = nodes[nd * kNodeCols + 1];
+            nodes[nd * kNodeCols + 6] = int64_t(slices.size()) / kSliceCols;
+            for (int64_t s = st; s < st + sz; s += kHistSlice) {
+                slices.push_back(s);
+                slices.push_back(std::min<int64_t>(kHistSlice, st + sz - s));
+                slices.push_back(nd);
+            }
+            nodes[nd * kNodeCols + 7] = int64_t(slices.size()) / kSliceCols;
+        }
+        lv.hslice1 = int64_t(slices.size()) / kSliceCols;
         max_nodes = std::max(max_nodes, lv.node1 - lv.node0);
         max_slices = std::max(max_slices, lv.slice1 - lv.slice0);
         pl.levels.push_back(lv);
@@ -782,7 +837,7 @@ bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P)
 }
 
 hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
-                    int32_t *perm, hipStream_t s)
+                    int32_t *perm, float *vals_sorted, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t mn = std::max<int64_t>(pl.max_nodes, 1), ms = std::max<int64_t>(pl.max_slices, 1);
@@ -831,9 +886,11 @@ hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64
                                                           : nullptr;
         k_kd_split<<<nb(nn, kThreads), kThreads, 0, s>>>(nt, nn, P, ext, ext_next, dim, prefix,
                                                           rank);
+        const int64_t *hst = slices + lv.hslice0 * kSliceCols;
+        const unsigned nhs = unsigned(lv.hslice1 - lv.hslice0);
         for (int r = 0; r < 3; ++r)
-            k_kd_hist_select<<<unsigned(ns), kThreads, 0, s>>>(nt, st, lv.node0, n, r, vin, dim,
-                                                              prefix, rank, hist, done);
+            k_kd_hist_select<<<nhs, kThreads, 0, s>>>(nt, hst, lv.node0, n, r, vin, dim, prefix,
+                                                     rank, hist, done);
         k_kd_count<<<unsigned(ns), kThreads, 0, s>>>(st, lv.node0, n, vin, dim, prefix, cnt);
         int32_t *idx_out = w.idx[cur].as<int32_t>();
         float *vout = w.val[cur].as<float>();
@@ -856,13 +913,16 @@ hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64
         const unsigned nl = unsigned(pl.local.node1 - pl.local.node0);
         if (P <= 16)
             k_kd_local<16><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, idx_in, vin,
-                                                        perm);
+                                                        perm, vals_sorted);
         else
             k_kd_local<32><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, idx_in, vin,
-                                                        perm);
+                                                        perm, vals_sorted);
         return hipGetLastError();
     }
-    return hipMemcpyAsync(perm, idx_in, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+    hipError_t e = hipMemcpyAsync(perm, idx_in, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && vals_sorted)
+        e = hipMemcpyAsync(vals_sorted, vin, sizeof(float) * P * n, hipMemcpyDeviceToDevice, s);
+    return e;
 }
 
 }  // namespace ngd

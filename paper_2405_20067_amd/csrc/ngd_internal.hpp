@@ -54,7 +54,7 @@ struct DevBuf {
 // levels, and the nodes whose subtrees finish in one workgroup each; laid
 // out on the host from (n, leaf, sub) alone and kept while they stay the same.
 struct KdLevel {
-    int64_t node0 = 0, node1 = 0, slice0 = 0, slice1 = 0;
+    int64_t node0 = 0, node1 = 0, slice0 = 0, slice1 = 0, hslice0 = 0, hslice1 = 0;
 };
 struct KdPlan {
     int64_t n = -1;
@@ -63,7 +63,8 @@ struct KdPlan {
     bool has_local = false;
     KdLevel local;                 // node rows of the subtree workgroups
     int64_t max_nodes = 0, max_slices = 0;
-    DevBuf node_tab;    // rows: start, size, n_left (-1 leaf), slice begin, slice end, child
+    DevBuf node_tab;    // rows: start, size, n_left (-1 leaf), slice begin / end, child,
+                        // histogram slice begin / end
     DevBuf slice_tab;   // rows: start, length, node
 };
 struct KdWork {
@@ -73,10 +74,11 @@ struct KdWork {
 bool kd_plan(KdPlan &pl, int64_t n, int leaf, int sub);
 bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P);
 // Orders n points with P <= 32 projections (vals: P x n, point order) and
-// writes the order (position -> point) to perm.  Needs a plan with at least
+// writes the order (position -> point) to perm and, when vals_sorted is not
+// null, the projections in that order (P x n).  Needs a plan with at least
 // one split (n > sub).
 hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
-                    int32_t *perm, hipStream_t s);
+                    int32_t *perm, float *vals_sorted, hipStream_t s);
 
 }  // namespace ngd
 
@@ -122,6 +124,8 @@ struct ngd_cull {
     ngd::DevBuf qs;            // n x q float: sorted queries, by dimension
     ngd::DevBuf gs;            // 3 x q float: sorted upstream gradient
     ngd::DevBuf tile_lo, tile_hi;   // ntiles x n_proj float
+    ngd::DevBuf sup_lo, sup_hi;     // ceil(ntiles / kSuperTiles) x n_proj float
+    ngd::DevBuf qr_s;               // n_proj x q float, tile order (k-d tiling)
     ngd::DevBuf grec;          // k x rec_stride float, sorted Gaussians
     ngd::DevBuf g_mr_s, g_thr_s;    // n_proj x k float, sorted Gaussians
     ngd::DevBuf masks;         // nchunks x tpad uint64
@@ -201,6 +205,10 @@ hipError_t launch_l2_loss(const float *f, const float *target, int64_t q, float 
 // hist 256 x blocks int32, off 256 x blocks + 1 int64, scan_tmp for a scan
 // of 256 x blocks.  *which tells which ping-pong buffer holds the result.
 constexpr int kRadixPerBlock = 4096;
+// Tiles per super-tile of the interval test (a k-d node of 16 tiles): a
+// chunk of Gaussians outside a super-tile's bounds is outside each of its
+// tiles' bounds.
+constexpr int kSuperTiles = 16;
 // Every buffer's capacity is checked on the host first (hipErrorInvalidValue
 // when one is too small).
 hipError_t radix_sort(int64_t n, const int64_t *n_dev, int nbits, DevBuf &k0, DevBuf &k1,
