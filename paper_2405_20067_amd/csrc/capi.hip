@@ -220,7 +220,7 @@ static void cull_release(ngd_cull *c)
                       &c->kd_q.node_tab, &c->kd_q.slice_tab, &c->kd_g.node_tab,
                       &c->kd_g.slice_tab, &c->kd_work.idx[0], &c->kd_work.idx[1],
                       &c->kd_work.val[0], &c->kd_work.val[1], &c->kd_work.ext[0],
-                      &c->kd_work.ext[1], &c->kd_work.hist, &c->kd_work.done, &c->kd_work.cnt,
+                      &c->kd_work.ext[1], &c->kd_work.hist, &c->kd_work.cnt,
                       &c->kd_work.dim,
                       &c->kd_work.prefix, &c->kd_work.rank};
     for (DevBuf *b : bufs) b->release();

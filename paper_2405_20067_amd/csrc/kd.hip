@@ -18,12 +18,12 @@
 //   split    per node: the projection of largest extent, from the node's
 //            min / max (accumulated by the previous level's scatter; for
 //            the root by a pass over its slices)
-//   hist     per slice of kHistSlice points: histogram of one radix digit (11, 11, 10 bits of
-//            the order-preserving key) among the points that match the
-//            digits found so far, added into the node's histogram; the
-//            node's last slice then selects the bin that holds the rank
-//            n_left.  Three rounds give the pivot key (the first point that
-//            goes right)
+//   hist     per slice of kHistSlice points: histogram of one radix digit
+//            (11, 11, 10 bits of the order-preserving key) among the points
+//            that match the digits found so far, added into the node's
+//            histogram
+//   select   per node: the bin that holds the rank n_left; three rounds
+//            give the pivot key (the first point that goes right)
 //   count    per slice: points below / equal to the pivot
 //   scatter  per slice: offsets from the node's earlier slices' counts,
 //            stable ranks by workgroup prefix sums in position order; index
@@ -50,8 +50,10 @@ constexpr int kBins = 2048;
 constexpr int kShift[3] = {21, 10, 0};
 constexpr int kWidth[3] = {11, 11, 10};
 
-constexpr int kLocalThreads = 1024;
-constexpr int kLocalMax = 4096;     // points per subtree workgroup (12-bit positions)
+constexpr int kHistThreads = 1024;
+
+constexpr int kLocalThreads = 256;
+constexpr int kLocalMax = 1024;     // points per subtree workgroup (<= 4096: 12-bit positions)
 constexpr int kLocalRuns = 128;     // runs per subtree (8-bit run ids)
 constexpr int kLocalSplit = 64;     // runs split at one level of a subtree
 
@@ -84,6 +86,34 @@ __device__ __forceinline__ uint32_t wave_umax(uint32_t v)
 {
 #pragma unroll
     for (int m = 32; m >= 1; m >>= 1) v = max(v, uint32_t(__shfl_xor(int(v), m, kWave)));
+    return v;
+}
+
+// Min / max over the 64 lanes by DPP (no LDS traffic), valid in lane 63:
+// within each row of 16 lanes a running min over row_shr 1, 2, 4, 8 (lanes
+// shifted in from outside the row take the identity), then row_bcast 15
+// carries rows 0 and 2 into rows 1 and 3 and row_bcast 31 carries lane 31
+// into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_umin_dpp(uint32_t v)
+{
+    const int id = -1;   // 0xffffffff
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr1, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr2, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr4, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr8, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowBcast15, 0xa, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowBcast31, 0xc, 0xf, false)));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_umax_dpp(uint32_t v)
+{
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr1, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr2, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr4, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr8, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowBcast15, 0xa, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowBcast31, 0xc, 0xf, false)));
     return v;
 }
 
@@ -206,10 +236,11 @@ __global__ __launch_bounds__(kThreads) void k_kd_split(const int64_t *__restrict
     }
 }
 
-// Block exclusive scan of one int64 per thread (256 threads).
+// Block exclusive scan of one int64 per thread (THREADS threads).
+template <int THREADS = kThreads>
 __device__ int64_t block_exscan(int64_t v, int64_t *total)
 {
-    __shared__ int64_t wt[kThreads / kWave];
+    __shared__ int64_t wt[THREADS / kWave];
     const int lane = lane_id(), w = threadIdx.x / kWave;
     int64_t inc = v;
 #pragma unroll
@@ -221,7 +252,7 @@ __device__ int64_t block_exscan(int64_t v, int64_t *total)
     __syncthreads();
     int64_t before = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < kThreads / kWave; ++i) {
+    for (int i = 0; i < THREADS / kWave; ++i) {
         before += (i < w) ? wt[i] : 0;
         all += wt[i];
     }
@@ -230,55 +261,58 @@ __device__ int64_t block_exscan(int64_t v, int64_t *total)
     return before + inc - v;
 }
 
-// Per slice: histogram of one digit among the matching points, added into
-// the node's histogram.  The node's last slice to finish (device-scope
-// counter after a fence; nothing waits) then finds the bin that holds the
-// rank, clears the histogram and the counter for the next round.
-__global__ __launch_bounds__(kThreads) void k_kd_hist_select(
-    const int64_t *__restrict__ nodes, const int64_t *__restrict__ slices, int64_t node0,
-    int64_t n, int round, const float *__restrict__ vin, const int32_t *__restrict__ dim,
-    uint32_t *__restrict__ prefix, int64_t *__restrict__ rank, int32_t *__restrict__ node_hist,
-    int32_t *__restrict__ node_done)
+// Per slice of kHistSlice points: histogram of one digit among the points
+// that match the digits found so far, added into the node's histogram
+// (integer atomics: the sum does not depend on their order).
+__global__ __launch_bounds__(kHistThreads) void k_kd_hist(
+    const int64_t *__restrict__ slices, int64_t node0, int64_t n, int round,
+    const float *__restrict__ vin, const int32_t *__restrict__ dim,
+    const uint32_t *__restrict__ prefix, int32_t *__restrict__ node_hist)
 {
     __shared__ int h[kBins];
-    __shared__ int last;
     const int64_t sl = blockIdx.x;
     const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
     const int64_t nd = slices[sl * kSliceCols + 2] - node0;
     const int d = dim[nd];
     if (d < 0) return;   // uniform over the workgroup
-    for (int b = threadIdx.x; b < kBins; b += kThreads) h[b] = 0;
+    for (int b = threadIdx.x; b < kBins; b += kHistThreads) h[b] = 0;
     __syncthreads();
     const int shift = kShift[round], width = kWidth[round];
     const uint32_t pre = prefix[nd];
     const uint32_t mask = (1u << width) - 1u;
 #pragma unroll 8
-    for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+    for (int64_t i = threadIdx.x; i < len; i += kHistThreads) {
         const uint32_t key = orderable(vin[int64_t(d) * n + s0 + i]);
         const bool match = (round == 0) || ((key >> (shift + width)) == pre);
         if (match) atomicAdd(&h[(key >> shift) & mask], 1);
     }
     __syncthreads();
     int32_t *nh = node_hist + nd * kBins;
-    for (int b = threadIdx.x; b < kBins; b += kThreads)
+    for (int b = threadIdx.x; b < kBins; b += kHistThreads)
         if (h[b]) atomicAdd(&nh[b], h[b]);
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int64_t *row = nodes + nd * kNodeCols;
-        const int nsl = int(row[7] - row[6]);
-        last = atomicAdd(&node_done[nd], 1) == nsl - 1;
-    }
-    __syncthreads();
-    if (!last) return;   // uniform
-    __threadfence();
+}
+
+// One workgroup per node: the bin of the node's histogram that holds the
+// rank; clears the bins it read for the next round.
+__global__ __launch_bounds__(kThreads) void k_kd_select(int round,
+                                                        int32_t *__restrict__ node_hist,
+                                                        const int32_t *__restrict__ dim,
+                                                        uint32_t *__restrict__ prefix,
+                                                        int64_t *__restrict__ rank)
+{
+    const int64_t nd = blockIdx.x;
+    if (dim[nd] < 0) return;   // uniform: the whole block returns
+    // read before the scan's barriers: one thread rewrites them below
     const int64_t r = rank[nd];
+    const uint32_t pre = prefix[nd];
+    const int width = kWidth[round];
     const int per = (1 << width) / kThreads;   // 8 or 4
+    int32_t *h = node_hist + nd * kBins + threadIdx.x * per;
     int64_t cnt[kBins / kThreads];
     int64_t mine = 0;
     for (int i = 0; i < per; ++i) {
-        const int b = threadIdx.x * per + i;
-        cnt[i] = atomicExch(&nh[b], 0);
+        cnt[i] = h[i];
+        h[i] = 0;
         mine += cnt[i];
     }
     int64_t tot;
@@ -290,7 +324,6 @@ __global__ __launch_bounds__(kThreads) void k_kd_hist_select(
         }
         cum += cnt[i];
     }
-    if (threadIdx.x == 0) node_done[nd] = 0;
 }
 
 __global__ __launch_bounds__(kThreads) void k_kd_count(const int64_t *__restrict__ slices,
@@ -394,6 +427,11 @@ __global__ __launch_bounds__(kThreads) void k_kd_scatter(
         const int64_t i = base + threadIdx.x;
         const bool valid = i < len;
         const int64_t pos = s0 + i;
+        // the point's values first, so their loads overlap the scans
+        float v[PMAX];
+#pragma unroll
+        for (int j = 0; j < PMAX; ++j) v[j] = (valid && j < P) ? vin[int64_t(j) * n + pos] : 0.0f;
+        const int32_t id = valid ? (idx_in ? idx_in[pos] : int32_t(pos)) : 0;
         const uint32_t key = valid ? orderable(vin[int64_t(d) * n + pos]) : 0xffffffffu;
         const bool is_less = valid && key < pivot;
         const bool is_eq = valid && key == pivot;
@@ -407,14 +445,13 @@ __global__ __launch_bounds__(kThreads) void k_kd_scatter(
         // every destination lies in the node's own run (the counts agree);
         // the test only guards the buffers should they ever not
         if (valid && dest >= start && dest < start + size) {
-            idx_out[dest] = idx_in ? idx_in[pos] : int32_t(pos);
+            idx_out[dest] = id;
 #pragma unroll
             for (int j = 0; j < PMAX; ++j) {
                 if (j < P) {
-                    const float v = vin[int64_t(j) * n + pos];
-                    vout[int64_t(j) * n + dest] = v;
+                    vout[int64_t(j) * n + dest] = v[j];
                     if (track) {
-                        const uint32_t k = orderable(v);
+                        const uint32_t k = orderable(v[j]);
                         if (left) {
                             lmin[j] = min(lmin[j], k);
                             lmax[j] = max(lmax[j], k);
@@ -545,9 +582,9 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
 #pragma unroll
                 for (int j = 0; j < PMAX; ++j) {
                     if (j < P) {
-                        const uint32_t a = wave_umin(mine ? kv[j] : 0xffffffffu);
-                        const uint32_t c = wave_umax(mine ? kv[j] : 0u);
-                        if (lane == 0) {
+                        const uint32_t a = wave_umin_dpp(mine ? kv[j] : 0xffffffffu);
+                        const uint32_t c = wave_umax_dpp(mine ? kv[j] : 0u);
+                        if (lane == kWave - 1) {
                             atomicMin(&emin[cur_si][j], a);
                             atomicMax(&emax[cur_si][j], c);
                         }
@@ -832,7 +869,6 @@ bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P)
     ok &= w.dim.ensure(sizeof(int32_t) * mn);
     ok &= w.prefix.ensure(sizeof(uint32_t) * mn);
     ok &= w.rank.ensure(sizeof(int64_t) * mn);
-    ok &= w.done.ensure(sizeof(int32_t) * mn);
     return ok;
 }
 
@@ -849,8 +885,7 @@ hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64
         w.ext[1].cap < sizeof(uint32_t) * 2 * P * size_t(mn) ||
         w.hist.cap < sizeof(int32_t) * kBins * size_t(mn) ||
         w.cnt.cap < sizeof(int64_t) * 2 * size_t(ms) || w.dim.cap < sizeof(int32_t) * size_t(mn) ||
-        w.prefix.cap < sizeof(uint32_t) * size_t(mn) || w.rank.cap < sizeof(int64_t) * size_t(mn) ||
-        w.done.cap < sizeof(int32_t) * size_t(mn))
+        w.prefix.cap < sizeof(uint32_t) * size_t(mn) || w.rank.cap < sizeof(int64_t) * size_t(mn))
         return hipErrorInvalidValue;
     const int32_t *idx_in = nullptr;   // level 0 reads the identity order
     const float *vin = vals;
@@ -858,14 +893,12 @@ hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64
     const int64_t *nodes = pl.node_tab.as<int64_t>();
     const int64_t *slices = pl.slice_tab.as<int64_t>();
     int32_t *hist = w.hist.as<int32_t>();
-    int32_t *done = w.done.as<int32_t>();
     int32_t *dim = w.dim.as<int32_t>();
     uint32_t *prefix = w.prefix.as<uint32_t>();
     int64_t *rank = w.rank.as<int64_t>();
     int64_t *cnt = w.cnt.as<int64_t>();
     if (!pl.levels.empty()) {
         k_kd_zero<<<nb(kBins * mn, kThreads), kThreads, 0, s>>>(hist, kBins * mn);
-        k_kd_zero<<<nb(mn, kThreads), kThreads, 0, s>>>(done, mn);
         k_kd_ext_reset<<<nb(P, kThreads), kThreads, 0, s>>>(w.ext[0].as<uint32_t>(), P);
         const KdLevel &lv = pl.levels[0];
         const int64_t *st = slices + lv.slice0 * kSliceCols;
@@ -888,9 +921,10 @@ hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64
                                                           rank);
         const int64_t *hst = slices + lv.hslice0 * kSliceCols;
         const unsigned nhs = unsigned(lv.hslice1 - lv.hslice0);
-        for (int r = 0; r < 3; ++r)
-            k_kd_hist_select<<<nhs, kThreads, 0, s>>>(nt, hst, lv.node0, n, r, vin, dim, prefix,
-                                                     rank, hist, done);
+        for (int r = 0; r < 3; ++r) {
+            k_kd_hist<<<nhs, kHistThreads, 0, s>>>(hst, lv.node0, n, r, vin, dim, prefix, hist);
+            k_kd_select<<<unsigned(nn), kThreads, 0, s>>>(r, hist, dim, prefix, rank);
+        }
         k_kd_count<<<unsigned(ns), kThreads, 0, s>>>(st, lv.node0, n, vin, dim, prefix, cnt);
         int32_t *idx_out = w.idx[cur].as<int32_t>();
         float *vout = w.val[cur].as<float>();

@@ -69,7 +69,7 @@ struct KdPlan {
 };
 struct KdWork {
     DevBuf idx[2], val[2], ext[2];
-    DevBuf hist, done, cnt, dim, prefix, rank;
+    DevBuf hist, cnt, dim, prefix, rank;
 };
 bool kd_plan(KdPlan &pl, int64_t n, int leaf, int sub);
 bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P);
