@@ -29,8 +29,11 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK_TFLOPS = 157.3   # published dense FP32 vector peak (packed)
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "forward_10d_traffic.json")
+BF16_MFMA_PEAK_TFLOPS = 2500.0  # published dense BF16 matrix peak
+TRAFFIC_FILES = dict(fp32=os.path.join(ROOT, "profiles", "forward_10d_traffic.json"),
+                     bf16_mfma=os.path.join(ROOT, "profiles", "forward_mfma_10d_traffic.json"))
 KERNEL_SRC = os.path.join(ROOT, "paper_2405_20067_amd", "csrc", "eval.hip")
+MFMA_SRC = os.path.join(ROOT, "paper_2405_20067_amd", "csrc", "eval_mfma.hip")
 
 
 def stage_flops(n: int):
@@ -124,6 +127,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--precision", default="both", choices=["fp32", "bf16_mfma", "both"],
+                    help="forward arithmetic of the timed step; 'both' times the step once "
+                         "with each and reports the faster as the headline")
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3 (3 steps, 1 warmup, no CPU/dense legs) "
                          "plus one 256 MiB device copy to calibrate memory counters")
@@ -153,7 +159,7 @@ def main():
     gout = torch.empty((w.q, 3), device="cuda")
     stages = ["update", "cull_build", "forward", "loss", "backward"]
 
-    def step(ev=None):
+    def step(prec, ev=None):
         def mark(i):
             if ev is not None:
                 ev[i].record()
@@ -164,38 +170,52 @@ def main():
             cull.build(m, dev["x"], proj, params)
         mark(2)
         c = cull if w.culled else None
-        ngd.eval_mixture(m, c, dev["x"], out=f)
+        ngd.eval_mixture(m, c, dev["x"], out=f, precision=prec)
         mark(3)
         if w.backward:
             ngd.l2_loss(f, target, loss=loss, grad=gout)
         mark(4)
         if w.backward:
-            ngd.eval_backward(m, c, dev["x"], gout, grads=grads)
+            ngd.eval_backward(m, c, dev["x"], gout, grads=grads, precision=prec)
         mark(5)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(evs[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    per_stage = {s: [] for s in stages}
-    for e in evs:
-        for j, s in enumerate(stages):
-            per_stage[s].append(e[j].elapsed_time(e[j + 1]))
-    stage_ms = {s: float(np.median(v)) for s, v in per_stage.items()}
-    ms_step = wall * 1e3 / args.steps
-    value = w.q * w.k / (ms_step * 1e-3)
+    def timed(prec):
+        for _ in range(args.warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)]
+               for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.steps):
+            step(prec, evs[i])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        per_stage = {s: [] for s in stages}
+        for e in evs:
+            for j, s in enumerate(stages):
+                per_stage[s].append(e[j].elapsed_time(e[j + 1]))
+        return wall * 1e3 / args.steps, {s: float(np.median(v)) for s, v in per_stage.items()}
+
+    precs = {"fp32": ngd.FP32, "bf16_mfma": ngd.BF16_MFMA}
+    chosen = list(precs) if args.precision == "both" else [args.precision]
+    if not w.culled:
+        chosen = ["fp32"]
+    paths = {}
+    for name in chosen:
+        ms, sm = timed(precs[name])
+        paths[name] = dict(ms_per_step=ms, value=w.q * w.k / (ms * 1e-3), stages_ms=sm)
+        log(f"{name}: step {ms:.3f} ms; stages " +
+            ", ".join(f"{s} {v:.3f}" for s, v in sm.items()))
+    head = min(paths, key=lambda k: paths[k]["ms_per_step"])
+    ms_step, stage_ms = paths[head]["ms_per_step"], paths[head]["stages_ms"]
+    value = paths[head]["value"]
+    prec = precs[head]
 
     st = cull.stats() if w.culled else dict(total=w.k, ntiles=1, max_per_tile=w.k)
     tile = params.tile
     cand_pairs = st["total"] * tile if w.culled else w.q * w.k
-    log(f"step {ms_step:.3f} ms; stages " +
-        ", ".join(f"{s} {v:.3f}" for s, v in stage_ms.items()) +
+    log(f"headline {head}: step {ms_step:.3f} ms"
         f"; candidates {st['total']} ({st['total'] / max(st['ntiles'] * w.k, 1):.4%} of "
         f"tile x Gaussian pairs), max/tile {st['max_per_tile']}")
 
@@ -217,31 +237,56 @@ def main():
             f"bwd {dense['backward_ms']:.1f} ms")
 
     fwd_pairs_s = cand_pairs / (stage_ms["forward"] * 1e-3)
-    roofline = None
-    work = None
-    if w.culled:
-        # the forward's executed work, counted by the same kernel on the same cull
-        cnt = ngd.eval_stats(m, cull, dev["x"])
+
+    def forward_roofline(name):
+        """Roofline of the forward kernel of one path, from the work counted
+        by the same kernel on the same cull and the forward time measured in
+        the timed steps (HIP events on the library's stream)."""
+        cnt = ngd.eval_stats(m, cull, dev["x"], precision=precs[name])
         f1, f2, f3, f4 = stage_flops(w.n)
-        lane_flops = 64 * (f1 * cnt["examined"] + f2 * cnt["pass1"] + f3 * cnt["pass2"]
-                           + f4 * cnt["kept"])
-        t_fwd = stage_ms["forward"] * 1e-3
-        achieved = lane_flops / t_fwd / 1e12
+        valu = 64 * (f1 * cnt["filtered"] + f2 * cnt["pass1"] + f3 * cnt["pass2"]
+                     + f4 * cnt["kept"])
+        t = paths[name]["stages_ms"]["forward"] * 1e-3
+        src = KERNEL_SRC if name == "fp32" else MFMA_SRC
         traffic = None
-        if os.path.exists(TRAFFIC_FILE):
-            tr = json.load(open(TRAFFIC_FILE))
-            if tr.get("source_sha256_16") == source_hash(KERNEL_SRC) and \
-                    tr.get("workload") == w.name:
+        tf = TRAFFIC_FILES[name]
+        if os.path.exists(tf):
+            tr = json.load(open(tf))
+            if tr.get("source_sha256_16") == source_hash(src) and tr.get("workload") == w.name:
                 traffic = tr.get("hbm_bytes_per_launch")
-        roofline = dict(
-            bound="alu", kernel="forward: k_eval_items + k_eval_reduce (ngd_eval)",
-            achieved=achieved, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-            frac=achieved / FP32_VALU_PEAK_TFLOPS, traffic=traffic,
-            units=dict(group_candidate_pairs=cnt, flops_per_lane_per_stage=[f1, f2, f3, f4],
-                       lanes_per_pair=64, flops_per_launch=lane_flops,
-                       launch_ms=stage_ms["forward"]))
-        work = cnt
-        log(f"forward work: {cnt}; {achieved:.1f} TFLOP/s executed")
+        if name == "fp32":
+            a = valu / t / 1e12
+            return dict(bound="alu", kernel="forward: k_eval_items + k_eval_reduce (ngd_eval)",
+                        achieved=a, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                        frac=a / FP32_VALU_PEAK_TFLOPS, traffic=traffic,
+                        units=dict(group_candidate_pairs=cnt,
+                                   flops_per_lane_per_stage=[f1, f2, f3, f4],
+                                   lanes_per_pair=64, flops_per_launch=valu,
+                                   launch_ms=t * 1e3))
+        nf = 1 + w.n + w.n * (w.n + 1) // 2
+        ks = 1 + (w.n * (w.n + 1) // 2 + 15) // 16
+        alg = cnt["examined"] * 64 * nf * 2 * 3
+        a = alg / t / 1e12
+        return dict(bound="mfma", kernel="forward: k_eval_mfma + k_eval_reduce (ngd_eval, "
+                                         "NGD_BF16_MFMA)",
+                    achieved=a, peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=a / BF16_MFMA_PEAK_TFLOPS, traffic=traffic,
+                    units=dict(group_candidate_pairs=cnt, features=nf,
+                               mfma_flops_per_group_pair=64 * nf * 2 * 3,
+                               mfma_flops_per_launch=alg,
+                               mfma_flops_executed_padded=cnt["examined"] * 64 * ks * 16 * 2 * 3,
+                               fp32_survivor_flops=valu,
+                               fp32_survivor_tflops=valu / t / 1e12, launch_ms=t * 1e3))
+
+    roofline = None
+    rooflines = {}
+    if w.culled:
+        for name in paths:
+            rooflines[name] = forward_roofline(name)
+            log(f"{name} forward: {rooflines[name]['units']['group_candidate_pairs']}; "
+                f"{rooflines[name]['achieved']:.1f} {rooflines[name]['unit']} "
+                f"({rooflines[name]['bound']})")
+        roofline = rooflines[head]
     if args.profile:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -258,13 +303,15 @@ def main():
         metric="Gaussian-query evals/sec, culled fwd+bwd 10-D, + % HBM/MFMA roofline",
         value=value, unit="Gaussian-query evals/s (dense-equivalent Q*K per step time)",
         n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
-        higher_is_better=True, scaling="weak", vs_baseline=None, dtype="f32",
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32" if head == "fp32" else "bf16+f32",
         data="synthetic",
         config=dict(workload=w.name, description=w.description, n=w.n, k=w.k, q=w.q,
                     k_target=w.k_target, near_frac=w.near_frac, n_proj=params.n_proj,
                     tau=params.tau, tile=params.tile,
                     tiling="k-d" if params.tiling == 0 else "morton"),
-        stages_ms=stage_ms,
+        precision=head, stages_ms=stage_ms,
+        paths={k: dict(v, roofline=rooflines.get(k)) for k, v in paths.items()},
         cull=dict(candidates=st["total"], ntiles=st["ntiles"], max_per_tile=st["max_per_tile"],
                   candidate_pairs=cand_pairs,
                   survivor_fraction=st["total"] / max(st["ntiles"] * w.k, 1)),

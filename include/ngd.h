@@ -52,8 +52,21 @@ extern "C" {
 #define NGD_MAX_N 12        /* dimensions supported: 1 .. NGD_MAX_N */
 #define NGD_MAX_PROJ 32     /* projection vectors: 1 .. NGD_MAX_PROJ */
 
-/* Arithmetic of ngd_eval / ngd_eval_backward. */
-#define NGD_FP32 0          /* float32 direct evaluation */
+/* Arithmetic of ngd_eval / ngd_eval_backward (culled only for BF16_MFMA). */
+#define NGD_FP32 0          /* float32 direct evaluation, staged certified skip */
+#define NGD_BF16_MFMA 1     /* the (query group, candidate) skip decided by a
+                               BF16 matrix-core contraction of quadratic query
+                               features (1, x', x'_i x'_j; x' centred on the
+                               work item's query box) against per-Gaussian
+                               quadratic coefficients, each split into bf16
+                               hi + lo with the products hi*hi + hi*lo + lo*hi
+                               accumulated in float32 (Sec. 3.1, Eq. 1-2
+                               expanded).  A candidate is skipped for a group
+                               only when the contraction minus a certified
+                               error bound puts every query of the group past
+                               the skip threshold; every other candidate is
+                               evaluated exactly as with NGD_FP32, so colours
+                               keep float32 accuracy. */
 
 typedef struct ngd_mixture ngd_mixture;
 typedef struct ngd_cull ngd_cull;
@@ -176,19 +189,23 @@ int ngd_cull_destroy(ngd_cull *cull);
  *            certified below tau * 2^-20 are skipped without evaluation.
  *   queries  device, q x n
  *   out      device, q x 3, in the caller's query order
+ *   precision NGD_FP32, or NGD_BF16_MFMA (needs a cull; its first use on a
+ *            cull build derives the per-Gaussian coefficients, k x 260 bytes
+ *            at n = 10, in library memory)
  * Does not synchronise. */
 int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
              int64_t q, int precision, float *out, void *stream);
 
 /* Work counters of the culled forward, for measurement (synchronises).
- * Runs the forward kernel on the same cull in a counting mode (no colours
- * written) and returns in counts (host, 4 x int64): the (64-query group,
- * candidate) pairs examined, those that passed the first and the second
- * Mahalanobis-bound check (marginals over the first 3 and 6 coordinates),
- * and those kept (evaluated with exp and accumulated).  `cull` and
- * `queries`/q as for ngd_eval. */
+ * Runs the forward kernel of `precision` on the same cull in a counting mode
+ * (no colours written) and returns in counts (host, 5 x int64): the
+ * (64-query group, candidate) pairs examined, those not skipped by the
+ * matrix-core filter (all of them with NGD_FP32), those that then passed the
+ * first and the second Mahalanobis-bound check (marginals over the first 3
+ * and 6 coordinates), and those kept (evaluated with exp and accumulated).
+ * `cull` and `queries`/q as for ngd_eval. */
 int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
-                   int64_t q, int64_t *counts, void *stream);
+                   int64_t q, int precision, int64_t *counts, void *stream);
 
 /* Gradients of a loss l given grad_out = dl/df (device, q x 3), with respect
  * to every Gaussian's mean, factor, weight and colour (the analytic
@@ -200,7 +217,11 @@ int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *qu
  * Outputs (device, overwritten, caller's Gaussian order): g_mean k x n,
  * g_factor k x n(n+1)/2 (packed like the factor), g_weight k, g_colour k x 3.
  * Each Gaussian's sums are formed by one wave in a fixed order: no atomics,
- * bitwise reproducible.  `cull` may be NULL (dense).  Does not synchronise. */
+ * bitwise reproducible.  `cull` may be NULL (dense).  With a cull the sums
+ * run over the pairs the last ngd_eval on this cull and mixture version kept,
+ * whatever its precision; without one, the keep decisions are taken first
+ * with `precision`.  The gradient arithmetic is float32 in both cases.  Does
+ * not synchronise. */
 int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull,
                       const float *queries, int64_t q, const float *grad_out,
                       int precision, float *g_mean, float *g_factor, float *g_weight,

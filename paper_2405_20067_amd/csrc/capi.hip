@@ -222,7 +222,8 @@ static void cull_release(ngd_cull *c)
                       &c->kd_work.val[0], &c->kd_work.val[1], &c->kd_work.ext[0],
                       &c->kd_work.ext[1], &c->kd_work.hist, &c->kd_work.cnt,
                       &c->kd_work.dim,
-                      &c->kd_work.prefix, &c->kd_work.rank};
+                      &c->kd_work.prefix, &c->kd_work.rank, &c->mrec, &c->mrow, &c->tcen,
+                      &c->eb0, &c->ebnd};
     for (DevBuf *b : bufs) b->release();
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     c->stats_host = nullptr;
@@ -319,6 +320,7 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (!cull_reserve_lists(c))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: candidate list allocation failed"));
     c->act_version = -1;
+    ++c->build_seq;
     c->transposed = false;
     e = launch_cull_build_lists(c, s);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (lists)"));
@@ -389,6 +391,21 @@ static int check_cull(const char *fn, const ngd_mixture *mix, const ngd_cull *c,
     return NGD_OK;
 }
 
+// Coefficient records of the matrix-core forward: grown with the cull.
+static int reserve_mfma(const char *fn, ngd_cull *c)
+{
+    const size_t kk = size_t(c->k > 0 ? c->k : 1);
+    const size_t tt = size_t(c->ntiles > 0 ? c->ntiles : 1);
+    const size_t ee = size_t(c->total > 0 ? c->total : 1);
+    if (!c->mrec.ensure(kk * mfma_rec_bytes(c->n)) || !c->mrow.ensure(kk * sizeof(float)) ||
+        !c->tcen.ensure(tt * c->n * sizeof(float)) || !c->eb0.ensure(ee * 4 * 16) ||
+        !c->ebnd.ensure(ee * 16)) {
+        c->mrec_seq = -1;
+        return fail(NGD_E_NOMEM, "%s: coefficient records: allocation failed", fn);
+    }
+    return NGD_OK;
+}
+
 int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries, int64_t q,
              int precision, float *out, void *stream)
 {
@@ -398,8 +415,10 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
     if (q > 0 && (!queries || !out)) return fail(NGD_E_INVAL, "ngd_eval: NULL array");
     if (!aligned4(queries) || !aligned4(out))
         return fail(NGD_E_INVAL, "ngd_eval: arrays must be 4-byte aligned");
-    if (precision != NGD_FP32)
+    if (precision != NGD_FP32 && precision != NGD_BF16_MFMA)
         return fail(NGD_E_INVAL, "ngd_eval: unknown precision %d", precision);
+    if (precision == NGD_BF16_MFMA && !cull)
+        return fail(NGD_E_INVAL, "ngd_eval: NGD_BF16_MFMA needs a cull");
     if (mix->version == 0) return fail(NGD_E_STALE, "ngd_eval: mixture has no parameters yet");
     if (cull) {
         const int rc = check_cull("ngd_eval", mix, cull, queries, q);
@@ -410,7 +429,15 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
     if (mix->k == 0 || (cull && cull->nitems == 0)) {
         e = launch_zero_f32(out, 3 * q, S(stream));
     } else if (cull) {
-        e = launch_eval_culled(mix, cull, out, S(stream));
+        if (precision == NGD_BF16_MFMA) {
+            // the coefficient records are a cache of the cull (grown on use)
+            ngd_cull *mc = const_cast<ngd_cull *>(cull);
+            const int rc = reserve_mfma("ngd_eval", mc);
+            if (rc) return rc;
+            e = launch_eval_mfma(mix, mc, out, nullptr, S(stream));
+        } else {
+            e = launch_eval_culled(mix, cull, out, S(stream));
+        }
         if (e == hipSuccess) cull->act_version = mix->version;
     } else {
         e = launch_eval_dense(mix, queries, q, out, S(stream));
@@ -420,14 +447,16 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
 }
 
 int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
-                   int64_t q, int64_t *counts, void *stream)
+                   int64_t q, int precision, int64_t *counts, void *stream)
 {
     if (!mix || !cull || !counts) return fail(NGD_E_INVAL, "ngd_eval_stats: NULL argument");
     if (q < 0 || q >= (int64_t(1) << 31))
         return fail(NGD_E_INVAL, "ngd_eval_stats: q=%lld outside [0, 2^31)", (long long)q);
+    if (precision != NGD_FP32 && precision != NGD_BF16_MFMA)
+        return fail(NGD_E_INVAL, "ngd_eval_stats: unknown precision %d", precision);
     const int rc = check_cull("ngd_eval_stats", mix, cull, queries, q);
     if (rc) return rc;
-    for (int i = 0; i < 4; ++i) counts[i] = 0;
+    for (int i = 0; i < 5; ++i) counts[i] = 0;
     if (q == 0 || mix->k == 0 || cull->nitems == 0) return NGD_OK;
     static std::mutex mu;
     static DevBuf buf[64];
@@ -436,18 +465,27 @@ int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *qu
     if (e != hipSuccess) return hip_fail(e, "ngd_eval_stats");
     if (dev < 0 || dev >= 64) return fail(NGD_E_INVAL, "ngd_eval_stats: device %d", dev);
     std::lock_guard<std::mutex> lk(mu);
-    if (!buf[dev].ensure(4 * sizeof(unsigned long long)))
+    if (!buf[dev].ensure(5 * sizeof(unsigned long long)))
         return fail(NGD_E_NOMEM, "ngd_eval_stats: workspace allocation failed");
-    unsigned long long host[4] = {0, 0, 0, 0};
+    if (precision == NGD_BF16_MFMA) {
+        const int rm = reserve_mfma("ngd_eval_stats", const_cast<ngd_cull *>(cull));
+        if (rm) return rm;
+    }
+    unsigned long long host[5] = {0, 0, 0, 0, 0};
     e = hipMemcpyAsync(buf[dev].p, host, sizeof(host), hipMemcpyHostToDevice, S(stream));
-    if (e == hipSuccess)
-        e = launch_eval_stats(mix, cull, buf[dev].as<unsigned long long>(), S(stream));
+    if (e == hipSuccess) {
+        if (precision == NGD_BF16_MFMA)
+            e = launch_eval_mfma(mix, const_cast<ngd_cull *>(cull), nullptr,
+                                 buf[dev].as<unsigned long long>(), S(stream));
+        else
+            e = launch_eval_stats(mix, cull, buf[dev].as<unsigned long long>(), S(stream));
+    }
     if (e == hipSuccess)
         e = hipMemcpyAsync(host, buf[dev].p, sizeof(host), hipMemcpyDeviceToHost, S(stream));
     if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
     if (e != hipSuccess) return hip_fail(e, "ngd_eval_stats");
     cull->act_version = mix->version;
-    for (int i = 0; i < 4; ++i) counts[i] = int64_t(host[i]);
+    for (int i = 0; i < 5; ++i) counts[i] = int64_t(host[i]);
     return NGD_OK;
 }
 
@@ -465,8 +503,10 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull, const float 
     if (!aligned4(queries) || !aligned4(grad_out) || !aligned4(g_mean) || !aligned4(g_factor) ||
         !aligned4(g_weight) || !aligned4(g_colour))
         return fail(NGD_E_INVAL, "ngd_eval_backward: arrays must be 4-byte aligned");
-    if (precision != NGD_FP32)
+    if (precision != NGD_FP32 && precision != NGD_BF16_MFMA)
         return fail(NGD_E_INVAL, "ngd_eval_backward: unknown precision %d", precision);
+    if (precision == NGD_BF16_MFMA && !cull)
+        return fail(NGD_E_INVAL, "ngd_eval_backward: NGD_BF16_MFMA needs a cull");
     if (mix->version == 0)
         return fail(NGD_E_STALE, "ngd_eval_backward: mixture has no parameters yet");
     if (cull) {
@@ -480,7 +520,14 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull, const float 
         // without a forward on this cull and mixture version, decide them now
         e = hipSuccess;
         if (cull->act_version != mix->version && cull->nitems > 0) {
-            e = launch_eval_culled(mix, cull, nullptr, S(stream));
+            if (precision == NGD_BF16_MFMA) {
+                const int rm = reserve_mfma("ngd_eval_backward", const_cast<ngd_cull *>(cull));
+                if (rm) return rm;
+                e = launch_eval_mfma(mix, const_cast<ngd_cull *>(cull), nullptr, nullptr,
+                                     S(stream));
+            } else {
+                e = launch_eval_culled(mix, cull, nullptr, S(stream));
+            }
             if (e == hipSuccess) cull->act_version = mix->version;
         }
         if (e == hipSuccess)

@@ -21,8 +21,7 @@
 // times alpha |c|.  The same test is applied once more before the exp.
 //
 // Dense kernel: the plain direct sum over all Gaussians, no skipping.
-#include <utility>
-
+#include "eval_common.hpp"
 #include "ngd_internal.hpp"
 #include "wave.hpp"
 
@@ -30,95 +29,6 @@ namespace ngd {
 namespace {
 
 constexpr int kEvalThreads = 256;
-// s_waitcnt immediate that waits for all scalar-memory (and LDS) loads only:
-// vmcnt and expcnt at their maxima, lgkmcnt 0.
-constexpr int kWaitScalar = 0xC07F;
-
-template <int N> struct RecLayout {
-    static constexpr int T = N * (N + 1) / 2;
-    static constexpr int R = (N + T + 7 + 3) / 4 * 4;
-    static constexpr int AC = N + T;
-    static constexpr int PF = R < 32 ? R : 32;   // floats loaded ahead
-    static constexpr int K1 = N < 3 ? N : 3;      // stage boundaries
-    static constexpr int K2 = N < 6 ? N : 6;
-};
-
-// Record field e: from the prefetched block when e < PF, else from memory.
-template <int N, int E>
-__device__ __forceinline__ float field(const float (&blk)[RecLayout<N>::PF],
-                                       const float *__restrict__ r)
-{
-    if constexpr (E < RecLayout<N>::PF)
-        return blk[E];
-    else
-        return r[E];
-}
-
-// Rows [R0, R1) of y = S'(x - m), accumulated into msq; d holds x - m.
-template <int N, int R0, int R1>
-__device__ __forceinline__ void rows(const float (&blk)[RecLayout<N>::PF],
-                                     const float *__restrict__ r, const float (&x)[N],
-                                     float (&d)[N], float (&y)[N], float &msq)
-{
-    if constexpr (R0 < R1) {
-        d[R0] = x[R0] - field<N, R0>(blk, r);
-        constexpr int base = N + R0 * (R0 + 1) / 2;
-        float acc = field<N, base>(blk, r) * d[0];
-        [&]<int... J>(std::integer_sequence<int, J...>) {
-            ((acc = fmaf(field<N, base + 1 + J>(blk, r), d[1 + J], acc)), ...);
-        }(std::make_integer_sequence<int, R0>{});
-        y[R0] = acc;
-        msq = fmaf(acc, acc, msq);
-        rows<N, R0 + 1, R1>(blk, r, x, d, y, msq);
-    }
-}
-
-// Accumulates one Gaussian into f for this lane's query x.  With SKIP,
-// returns early when the whole wave can drop the pair.
-// Returns whether the wave kept the pair (the same for every lane).  With
-// COUNT, st[0..2] count the pairs that passed the first and second checks
-// and were kept (wave-uniform counters).
-template <int N, bool SKIP, bool ACC = true, bool COUNT = false>
-__device__ __forceinline__ bool eval_pair(const float (&blk)[RecLayout<N>::PF],
-                                          const float *__restrict__ r, const float (&x)[N],
-                                          bool valid, float skip, float &f0, float &f1,
-                                          float &f2, uint32_t *st = nullptr)
-{
-    using Lay = RecLayout<N>;
-    float d[N], y[N];
-    float msq = 0.0f;
-    rows<N, 0, Lay::K1>(blk, r, x, d, y, msq);
-    if constexpr (SKIP && Lay::K1 < N) {
-        if (ballot(valid && msq <= skip) == 0) return false;
-    }
-    if constexpr (COUNT) ++st[0];
-    rows<N, Lay::K1, Lay::K2>(blk, r, x, d, y, msq);
-    if constexpr (SKIP && Lay::K2 < N && Lay::K1 < Lay::K2) {
-        if (ballot(valid && msq <= skip) == 0) return false;
-    }
-    if constexpr (COUNT) ++st[1];
-    rows<N, Lay::K2, N>(blk, r, x, d, y, msq);
-    if constexpr (SKIP) {
-        if (ballot(valid && msq <= skip) == 0) return false;
-    }
-    if constexpr (COUNT) ++st[2];
-    if constexpr (ACC) {
-        const float g = __builtin_amdgcn_exp2f(-msq);
-        f0 = fmaf(g, field<N, Lay::AC + 0>(blk, r), f0);
-        f1 = fmaf(g, field<N, Lay::AC + 1>(blk, r), f1);
-        f2 = fmaf(g, field<N, Lay::AC + 2>(blk, r), f2);
-    }
-    return true;
-}
-
-template <int N>
-__device__ __forceinline__ void load_block(float (&blk)[RecLayout<N>::PF],
-                                           const float *__restrict__ r)
-{
-#pragma unroll
-    for (int e = 0; e < RecLayout<N>::PF; ++e) blk[e] = r[e];
-}
-
 template <int N>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t q,
                                                              const float *__restrict__ rec,
@@ -150,8 +60,13 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t 
 // OUT = false: only the keep/skip flags are written (the backward pass needs
 // them when no forward ran on this cull).  COUNT (with OUT = false): the
 // flags are written and the stage counters of every wave are added to
-// stats[0..3] = (pairs examined, passed check 1, passed check 2, kept).
-template <int N, bool OUT, bool COUNT = false>
+// stats[0..4] = (pairs examined, examined again (no matrix filter here),
+// passed check 1, passed check 2, kept).
+// PRE: the (entry, group) flags already hold a filter's decision (1: the
+// pair may contribute); only flagged pairs are evaluated, and the flags are
+// overwritten with the kept decision.  With COUNT it adds the stage counters
+// to stats[2..4] only (the filter counted stats[0..1]).
+template <int N, bool OUT, bool COUNT = false, bool PRE = false>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     int64_t q, int tile, const float *__restrict__ grec, const float *__restrict__ qs,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ cand,
@@ -192,36 +107,68 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
         const int lane = lane_id();
         const int vidx = (lane < n) ? cand[ch + lane] : 0;
         uint32_t kept = 0;
-        int64_t ia = __builtin_amdgcn_readlane(vidx, 0);
-        load_block<N>(bufA, grec + ia * Lay::R);
-        for (int j = 0; j < n; j += 2) {
-            __builtin_amdgcn_s_waitcnt(kWaitScalar);
-            int64_t ib = 0;
-            if (j + 1 < n) {
-                ib = __builtin_amdgcn_readlane(vidx, j + 1);
-                load_block<N>(bufB, grec + ib * Lay::R);
+        if constexpr (!PRE) {
+            int64_t ia = __builtin_amdgcn_readlane(vidx, 0);
+            load_block<N>(bufA, grec + ia * Lay::R);
+            for (int j = 0; j < n; j += 2) {
+                __builtin_amdgcn_s_waitcnt(kWaitScalar);
+                int64_t ib = 0;
+                if (j + 1 < n) {
+                    ib = __builtin_amdgcn_readlane(vidx, j + 1);
+                    load_block<N>(bufB, grec + ib * Lay::R);
+                }
+                if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
+                                                   f1, f2, st))
+                    kept = (lane == j) ? 1u : kept;
+                if (j + 1 >= n) break;
+                __builtin_amdgcn_s_waitcnt(kWaitScalar);
+                if (j + 2 < n) {
+                    ia = __builtin_amdgcn_readlane(vidx, j + 2);
+                    load_block<N>(bufA, grec + ia * Lay::R);
+                }
+                if (eval_pair<N, true, OUT, COUNT>(bufB, grec + ib * Lay::R, x, valid, skip, f0,
+                                                   f1, f2, st))
+                    kept = (lane == j + 1) ? 1u : kept;
             }
-            if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0, f1,
-                                               f2, st))
-                kept = (lane == j) ? 1u : kept;
-            if (j + 1 >= n) break;
-            __builtin_amdgcn_s_waitcnt(kWaitScalar);
-            if (j + 2 < n) {
-                ia = __builtin_amdgcn_readlane(vidx, j + 2);
-                load_block<N>(bufA, grec + ia * Lay::R);
+        } else {
+            // the flagged candidates in ascending order, one record ahead
+            uint64_t todo =
+                ballot(lane < n && grp < ngroups && act[(ch + lane) * ngroups + grp] != 0);
+            int ja = todo ? __builtin_ctzll(todo) : -1;
+            if (ja >= 0) {
+                todo &= todo - 1;
+                load_block<N>(bufA, grec + int64_t(__builtin_amdgcn_readlane(vidx, ja)) * Lay::R);
             }
-            if (eval_pair<N, true, OUT, COUNT>(bufB, grec + ib * Lay::R, x, valid, skip, f0, f1,
-                                               f2, st))
-                kept = (lane == j + 1) ? 1u : kept;
+            while (ja >= 0) {
+                const int64_t ia = __builtin_amdgcn_readlane(vidx, ja);
+                const int jb = todo ? __builtin_ctzll(todo) : -1;
+                __builtin_amdgcn_s_waitcnt(kWaitScalar);
+                if (jb >= 0) {
+                    todo &= todo - 1;
+                    load_block<N>(bufB,
+                                  grec + int64_t(__builtin_amdgcn_readlane(vidx, jb)) * Lay::R);
+                }
+                if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
+                                                   f1, f2, st))
+                    kept = (lane == ja) ? 1u : kept;
+#pragma unroll
+                for (int e = 0; e < Lay::PF; ++e) bufA[e] = bufB[e];
+                ja = jb;
+            }
         }
         if (lane < n && grp < ngroups) act[(ch + lane) * ngroups + grp] = uint8_t(kept);
     }
     if constexpr (COUNT) {
         if (lane_id() == 0 && grp < ngroups) {
-            atomicAdd(&stats[0], static_cast<unsigned long long>(e1 - e0));
-            atomicAdd(&stats[1], static_cast<unsigned long long>(st[0]));
-            atomicAdd(&stats[2], static_cast<unsigned long long>(st[1]));
-            atomicAdd(&stats[3], static_cast<unsigned long long>(st[2]));
+            // (examined, not skipped by a matrix filter -- there is none here,
+            // passed check 1, passed check 2, kept)
+            if constexpr (!PRE) {
+                atomicAdd(&stats[0], static_cast<unsigned long long>(e1 - e0));
+                atomicAdd(&stats[1], static_cast<unsigned long long>(e1 - e0));
+            }
+            atomicAdd(&stats[2], static_cast<unsigned long long>(st[0]));
+            atomicAdd(&stats[3], static_cast<unsigned long long>(st[1]));
+            atomicAdd(&stats[4], static_cast<unsigned long long>(st[2]));
         }
     }
     if constexpr (!OUT) return;
@@ -295,11 +242,9 @@ hipError_t culled_n(const ngd_mixture *mix, const ngd_cull *c, float *out, hipSt
                 c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
                 c->item_off.as<int64_t>(), skip, nullptr, c->fpart.as<float>(), act);
     }
-    if (out)
-        k_eval_reduce<<<dim3(unsigned(c->ntiles), gy), per, 0, s>>>(
-            c->q, tile, c->perm.as<int32_t>(), c->item_off.as<int64_t>(), c->fpart.as<float>(),
-            out);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !out) return e;
+    return launch_eval_reduce(c, out, s);
 }
 
 template <int N>
@@ -318,7 +263,56 @@ hipError_t stats_n(const ngd_cull *c, unsigned long long *stats, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int N>
+hipError_t flagged_n(const ngd_cull *c, float *out, unsigned long long *stats, hipStream_t s)
+{
+    const int tile = c->params.tile;
+    const int per = tile < kEvalThreads ? (tile + 63) / 64 * 64 : kEvalThreads;
+    const unsigned gy = unsigned((tile + kEvalThreads - 1) / kEvalThreads);
+    const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
+    if (c->nitems == 0) return hipSuccess;
+    const dim3 grid(unsigned(c->nitems), gy);
+    auto go = [&](auto kern, float *o, unsigned long long *st) {
+        kern<<<grid, per, 0, s>>>(c->q, tile, c->grec.as<float>(), c->qs.as<float>(),
+                                  c->tile_off.as<int64_t>(), c->cand.as<int32_t>(),
+                                  c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
+                                  c->item_off.as<int64_t>(), skip, o, c->fpart.as<float>(),
+                                  c->act.as<uint8_t>(), st);
+    };
+    if (stats)
+        go(k_eval_items<N, false, true, true>, nullptr, stats);
+    else if (out)
+        go(k_eval_items<N, true, false, true>, out, nullptr);
+    else
+        go(k_eval_items<N, false, false, true>, nullptr, nullptr);
+    return hipGetLastError();
+}
+
 }  // namespace
+
+hipError_t launch_eval_flagged(const ngd_mixture *mix, const ngd_cull *c, float *out,
+                               unsigned long long *stats, hipStream_t s)
+{
+    if (c->q == 0 || c->ntiles == 0) return hipSuccess;
+    switch (mix->n) {
+#define NGD_CASE(NN) \
+    case NN: return flagged_n<NN>(c, out, stats, s);
+        NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
+        NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
+#undef NGD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_eval_reduce(const ngd_cull *c, float *out, hipStream_t s)
+{
+    const int tile = c->params.tile;
+    const int per = tile < kEvalThreads ? (tile + 63) / 64 * 64 : kEvalThreads;
+    const unsigned gy = unsigned((tile + kEvalThreads - 1) / kEvalThreads);
+    k_eval_reduce<<<dim3(unsigned(c->ntiles), gy), per, 0, s>>>(
+        c->q, tile, c->perm.as<int32_t>(), c->item_off.as<int64_t>(), c->fpart.as<float>(), out);
+    return hipGetLastError();
+}
 
 hipError_t launch_eval_stats(const ngd_mixture *mix, const ngd_cull *c,
                              unsigned long long *stats, hipStream_t s)

@@ -1,0 +1,587 @@
+// Culled forward with a matrix-core filter: the Mahalanobis distance of
+// every (query, candidate) pair of a work item as one BF16 MFMA contraction
+// of quadratic query features against per-Gaussian quadratic coefficients.
+//
+// The quadratic form (Sec. 3.1, Eq. 1-2, in exp2 units, S' = sqrt(log2(e)/2)
+// L^-1, P' = S'^T S'):
+//   M'(x) = |S'(x - m)|^2
+//         = sum_{i<=j} C_ij x'_i x'_j + sum_i b'_i x'_i + a',
+//   x' = x - c, m' = m - c, C_ii = P'_ii, C_ij = 2 P'_ij (i < j),
+//   b' = -2 S'^T (S' m'),  a' = |S' m'|^2,
+// with c the centre of the tile's query box, so that the features stay
+// small and the expanded form does not cancel away its own accuracy.  The
+// feature vector (1, x', x'_i x'_j) has 1 + N + N(N+1)/2 entries (66 at
+// N = 10), laid out as one k-step of 16 for the constant and linear terms
+// and ceil(N(N+1)/2 / 16) k-steps for the quadratic ones.
+//
+// Precision: features and coefficients are split into bf16 pairs
+// v = hi + lo + r, |r| <= 2^-16 |v|, and the contraction takes the three
+// products hi*hi + hi*lo + lo*hi with fp32 accumulation
+// (v_mfma_f32_32x32x16_bf16).  Its error against the exact form is below
+// 2^-13 * sum_k |F_k| |C_k| (a generous bound: split and omitted lo*lo terms
+// give about 3 * 2^-16, accumulation of at most 3 * 96 exact products about
+// 2^-16).  Over a 64-query group with h_i = max |x'_i| that sum is at most
+//   R' |h|^2 + |b'|_1 max h + |a'|,   R' = max row sum of |S'|^T |S'|,
+// and the fp32 rounding of b' adds at most 2^-18 R' |m'|_1 max h.  A
+// candidate is skipped for the whole group only when the smallest M' of the
+// group minus that bound exceeds the skip threshold log2(1/tau) + 20, the
+// same certificate the fp32 kernel applies (G < tau 2^-20).  Every
+// candidate that is not skipped is evaluated exactly as in the fp32 kernel
+// (the same staged code, lane = query), so the colours carry fp32 accuracy;
+// they differ from the fp32 kernel's only by pairs below the certificate.
+//
+// Once per cull build: the quadratic coefficients of every ordered Gaussian
+// (float64 P', then bf16 hi / lo), the centre of every tile's query box, and
+// for every candidate entry (tile, Gaussian) the centred constant and linear
+// coefficients and bound terms -- one thread per entry.
+// Filter kernel, one workgroup per work item (up to 256 queries in 4 waves):
+// per wave the query features as MFMA A fragments (rows = queries, 2 blocks
+// of 32); the entries' B fragments staged in LDS in double-buffered chunks of
+// 64 (the next chunk loaded while the current one is computed); per block of
+// 32 entries 3 x KS x 2 MFMAs and the certified group test; the (entry,
+// group) flag records whether the pair may contribute.  The
+// float32 items kernel then evaluates only the flagged pairs (eval.hip).
+#include <cmath>
+
+#include "eval_common.hpp"
+#include "ngd_internal.hpp"
+#include "wave.hpp"
+
+namespace ngd {
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kMThreads = 256;
+constexpr int kCh = 64;       // entries staged in LDS at a time (one per lane)
+static_assert(kCh == kWave, "a wave loads the indices of one chunk");
+constexpr float kGammaQ = 1.0f / 8192.0f;     // 2^-13
+constexpr float kGammaB = 1.0f / 262144.0f;   // 2^-18
+
+template <int N> struct Feat {
+    static constexpr int T = N * (N + 1) / 2;
+    static constexpr int KQ = (T + 15) / 16;   // quadratic k-steps
+    static constexpr int KS = 1 + KQ;          // plus constant and linear
+    static_assert(N + 1 <= 16, "constant and linear terms fill one k-step");
+};
+
+// Quadratic slot q -> (i, j), i <= j, the upper triangle by rows.
+template <int N> struct QuadTable {
+    int i[Feat<N>::KQ * 16];
+    int j[Feat<N>::KQ * 16];
+    constexpr QuadTable() : i(), j()
+    {
+        int q = 0;
+        for (int a = 0; a < N; ++a)
+            for (int b = a; b < N; ++b) {
+                i[q] = a;
+                j[q] = b;
+                ++q;
+            }
+        for (; q < Feat<N>::KQ * 16; ++q) {
+            i[q] = -1;
+            j[q] = -1;
+        }
+    }
+};
+template <int N> inline constexpr QuadTable<N> kQuad{};
+
+__device__ __forceinline__ void split_bf16(float v, __bf16 &hi, __bf16 &lo)
+{
+    hi = __bf16(v);
+    lo = __bf16(v - float(hi));
+}
+
+// Per ordered Gaussian: the quadratic coefficients as bf16 hi / lo pairs in
+// B-fragment order -- for quadratic k-step ks and half h, 8 hi then 8 lo --
+// and R' = max row sum of |S'|^T |S'|.  P' is formed in float64.
+template <int N>
+__global__ __launch_bounds__(256) void k_mfma_coef(int64_t k, const float *__restrict__ grec,
+                                                   __bf16 *__restrict__ mrec,
+                                                   float *__restrict__ rrow)
+{
+    using Fe = Feat<N>;
+    constexpr int R = RecLayout<N>::R;
+    const int64_t s = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (s >= k) return;
+    const float *r = grec + s * R + N;   // S' packed lower by rows
+    double S[Fe::T];
+#pragma unroll
+    for (int e = 0; e < Fe::T; ++e) S[e] = double(r[e]);
+    auto sidx = [](int row, int col) { return row * (row + 1) / 2 + col; };
+    __bf16 *o = mrec + s * (Fe::KQ * 32);
+#pragma unroll
+    for (int q = 0; q < Fe::KQ * 16; ++q) {
+        float cf = 0.0f;
+        if (kQuad<N>.i[q] >= 0) {
+            const int a = kQuad<N>.i[q], b = kQuad<N>.j[q];   // a <= b
+            double p = 0.0;
+#pragma unroll
+            for (int row = 0; row < N; ++row)
+                if (row >= b) p += S[sidx(row, a)] * S[sidx(row, b)];
+            cf = float(a == b ? p : 2.0 * p);
+        }
+        __bf16 hi, lo;
+        split_bf16(cf, hi, lo);
+        const int ks = q / 16, h = (q % 16) / 8, e = q % 8;
+        o[(ks * 2 + h) * 16 + e] = hi;
+        o[(ks * 2 + h) * 16 + 8 + e] = lo;
+    }
+    double best = 0.0;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        double rs = 0.0;
+#pragma unroll
+        for (int b = 0; b < N; ++b) {
+#pragma unroll
+            for (int row = 0; row < N; ++row) {
+                if (row >= a && row >= b) rs += fabs(S[sidx(row, a)]) * fabs(S[sidx(row, b)]);
+            }
+        }
+        best = rs > best ? rs : best;
+    }
+    rrow[s] = float(best) * (1.0f + 1.0f / 1048576.0f);
+}
+
+// Centre of each tile's query box (x-space, the sorted queries).
+template <int N>
+__global__ __launch_bounds__(256) void k_tile_centre(int64_t q, int tile,
+                                                     const float *__restrict__ qs,
+                                                     float *__restrict__ tcen)
+{
+    __shared__ float slo[256 / kWave][N], shi[256 / kWave][N];
+    const int64_t t = blockIdx.x;
+    float lo[N], hi[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        lo[a] = INFINITY;
+        hi[a] = -INFINITY;
+    }
+    for (int i = int(threadIdx.x); i < tile; i += 256) {
+        const int64_t p = t * tile + i;
+        if (p >= q) break;
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const float v = qs[a * q + p];
+            lo[a] = fminf(lo[a], v);
+            hi[a] = fmaxf(hi[a], v);
+        }
+    }
+    const int w = int(threadIdx.x) / kWave;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        const float mn = wave_min(lo[a]), mx = wave_max(hi[a]);
+        if (lane_id() == 0) {
+            slo[w][a] = mn;
+            shi[w][a] = mx;
+        }
+    }
+    __syncthreads();
+    if (int(threadIdx.x) < N) {
+        const int a = int(threadIdx.x);
+        float mn = INFINITY, mx = -INFINITY;
+        for (int v = 0; v < 256 / kWave; ++v) {
+            mn = fminf(mn, slo[v][a]);
+            mx = fmaxf(mx, shi[v][a]);
+        }
+        tcen[t * N + a] = (mn <= mx) ? 0.5f * mn + 0.5f * mx : 0.0f;
+    }
+}
+
+// Per candidate entry (tile, Gaussian): the centred constant and linear
+// coefficients a' = |S'm'|^2, b' = -2 S'^T (S'm'), m' = m - c_tile, as the
+// k-step-0 B fragments (per half: 8 bf16 hi, 8 bf16 lo), and the bound terms
+// (|a'|, |b'|_1, |m'|_1, R').
+template <int N>
+__global__ __launch_bounds__(256) void k_mfma_entry(int64_t total,
+                                                    const int32_t *__restrict__ cand,
+                                                    const int32_t *__restrict__ ent_tile,
+                                                    const float *__restrict__ grec,
+                                                    const float *__restrict__ rrow,
+                                                    const float *__restrict__ tcen,
+                                                    bf16x8 *__restrict__ eb0,
+                                                    float4 *__restrict__ ebnd)
+{
+    constexpr int R = RecLayout<N>::R;
+    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
+    if (e >= total) return;
+    const int sp = cand[e];
+    // the record's mean and factor with 16-byte loads (records are 16-byte
+    // aligned; R is a multiple of 4)
+    constexpr int NV = (N + RecLayout<N>::T + 3) / 4;
+    float r[NV * 4];
+    const float4 *r4 = reinterpret_cast<const float4 *>(grec + int64_t(sp) * R);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        const float4 u = r4[v];
+        r[4 * v + 0] = u.x;
+        r[4 * v + 1] = u.y;
+        r[4 * v + 2] = u.z;
+        r[4 * v + 3] = u.w;
+    }
+    const float *c = tcen + int64_t(ent_tile[e]) * N;
+    float mp[N], y[N], b[N];
+    float m1 = 0.0f;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        mp[a] = r[a] - c[a];
+        m1 += fabsf(mp[a]);
+    }
+    float a0 = 0.0f;
+#pragma unroll
+    for (int row = 0; row < N; ++row) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int col = 0; col <= row; ++col)
+            acc = fmaf(r[N + row * (row + 1) / 2 + col], mp[col], acc);
+        y[row] = acc;
+        a0 = fmaf(acc, acc, a0);
+    }
+    float b1 = 0.0f;
+#pragma unroll
+    for (int col = 0; col < N; ++col) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int row = col; row < N; ++row)
+            acc = fmaf(r[N + row * (row + 1) / 2 + col], y[row], acc);
+        b[col] = -2.0f * acc;
+        b1 += fabsf(b[col]);
+    }
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        bf16x8 vhi, vlo;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const int slot = 8 * hh + k;
+            const float v = slot == 0 ? a0 : (slot <= N ? b[slot - 1] : 0.0f);
+            __bf16 hi, lo;
+            split_bf16(v, hi, lo);
+            vhi[k] = hi;
+            vlo[k] = lo;
+        }
+        eb0[e * 4 + hh * 2 + 0] = vhi;
+        eb0[e * 4 + hh * 2 + 1] = vlo;
+    }
+    ebnd[e] = make_float4(fabsf(a0), b1, m1, rrow[sp]);
+}
+
+template <int N, bool COUNT>
+__global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
+    int64_t q, int tile, const bf16x8 *__restrict__ mrec, const bf16x8 *__restrict__ eb0,
+    const float4 *__restrict__ ebnd, const float *__restrict__ tcen,
+    const float *__restrict__ qs, const int64_t *__restrict__ tile_off,
+    const int32_t *__restrict__ cand, const int32_t *__restrict__ item_tile,
+    const int64_t *__restrict__ item_off, float skip, uint8_t *__restrict__ act,
+    unsigned long long *__restrict__ stats)
+{
+    using Fe = Feat<N>;
+    constexpr int KS = Fe::KS, KQ = Fe::KQ;
+    __shared__ bf16x8 s_b[2][kCh][KS][2][2];   // buffer, entry, k-step, half, {hi, lo}
+    __shared__ float4 s_bd[2][kCh];           // |a'|, |b'|_1, |m'|_1, R'
+
+    const int64_t it = blockIdx.x;
+    const int64_t t = uniform(item_tile[it]);
+    const int64_t i0 = uniform64(item_off[t]);
+    const int64_t c0 = uniform64(tile_off[t]), c1 = uniform64(tile_off[t + 1]);
+    const int64_t e0 = c0 + (it - i0) * kItemCands;
+    const int64_t e1 = (e0 + kItemCands < c1) ? e0 + kItemCands : c1;
+
+    const int lane = lane_id(), w = int(threadIdx.x) / kWave, h = lane / 32;
+    const int s = int(blockIdx.y) * kMThreads + int(threadIdx.x);
+    const int64_t p = t * tile + s;
+    const bool valid = (s < tile) && (p < q);
+    float cen[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) cen[a] = tcen[t * N + a];
+
+    // this wave's half-widths about the centre
+    float h2 = 0.0f, hm = 0.0f;
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        const float xa = valid ? qs[a * q + p] : 0.0f;
+        const float ha = wave_max(valid ? fabsf(xa - cen[a]) : 0.0f);
+        h2 = fmaf(ha, ha, h2);
+        hm = fmaxf(hm, ha);
+    }
+    h2 *= 1.0f + 1.0f / 1048576.0f;
+
+    // A fragments: rows are the wave's queries (two blocks of 32).  Every
+    // lane forms all 16 features of each k-step for its row (indices known
+    // at compile time), then keeps the half h = lane / 32 it holds.
+    bf16x8 ahi[2][KS], alo[2][KS];
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+        const int sr = w * kWave + int(blockIdx.y) * kMThreads + rb * 32 + (lane % 32);
+        const int64_t pr = t * tile + sr;
+        const bool vr = (sr < tile) && (pr < q);
+        float xr[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) xr[a] = vr ? qs[a * q + pr] - cen[a] : 0.0f;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            float f[16];
+#pragma unroll
+            for (int slot = 0; slot < 16; ++slot) {
+                f[slot] = 0.0f;
+                if (ks == 0) {
+                    if (slot == 0)
+                        f[slot] = vr ? 1.0f : 0.0f;
+                    else if (slot <= N)
+                        f[slot] = xr[slot - 1];
+                } else {
+                    const int qq = (ks - 1) * 16 + slot;
+                    if (kQuad<N>.i[qq] >= 0) f[slot] = xr[kQuad<N>.i[qq]] * xr[kQuad<N>.j[qq]];
+                }
+            }
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const float v = h ? f[8 + e] : f[e];
+                __bf16 hi, lo;
+                split_bf16(v, hi, lo);
+                ahi[rb][ks][e] = hi;
+                alo[rb][ks][e] = lo;
+            }
+        }
+    }
+    // all 64 queries of the group valid: no row masking in the group test
+    const bool full = ballot(valid) == ~uint64_t(0);
+    uint32_t rowvalid = 0;   // bit rb * 16 + r: accumulator element r of row block rb
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int row = 8 * (r / 4) + 4 * h + (r % 4);
+            const int sq = w * kWave + int(blockIdx.y) * kMThreads + rb * 32 + row;
+            if (sq < tile && t * tile + sq < q) rowvalid |= 1u << (rb * 16 + r);
+        }
+    }
+
+    const int ngroups = (tile + kWave - 1) / kWave;
+    const int grp = s / kWave;
+    unsigned long long n_exam = 0, n_pass = 0;
+
+    // Chunks of kCh entries staged in LDS, double-buffered: the workgroup
+    // loads chunk c + 1 (each thread a few 16-byte units, every unit once)
+    // while it computes chunk c, then stores it and meets at one barrier.
+    constexpr int kUnits = kCh * KS * 4;   // 16-byte B-fragment units per chunk
+    constexpr int kStage = (kUnits + kCh + kMThreads - 1) / kMThreads;
+    const int nthr = int(blockDim.x);
+    bf16x8 stage[kStage];
+    auto load_chunk = [&](int64_t ch) {
+        // the chunk's Gaussian positions: one coalesced load per wave, then
+        // handed to the lanes that need them by lane permutes (so the record
+        // loads below do not each wait for a load of their own index)
+        const int cv = (ch + lane < e1) ? cand[ch + lane] : 0;
+        int spk[kStage];
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const int u = int(threadIdx.x) + k * nthr;
+            const int j = u < kUnits ? u / (KS * 4) : u - kUnits;
+            spk[k] = __shfl(cv, j & (kWave - 1), kWave);
+        }
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const int u = int(threadIdx.x) + k * nthr;
+            if (k * nthr >= kUnits + kCh) break;
+            int j, r;
+            if (u < kUnits) {
+                j = u / (KS * 4);
+                r = u % (KS * 4);
+            } else {
+                j = u - kUnits;
+                r = -1;
+            }
+            const int64_t e = ch + j;
+            if (u < kUnits + kCh && e < e1) {
+                if (r < 0)
+                    stage[k] = *reinterpret_cast<const bf16x8 *>(ebnd + e);
+                else if (r < 4)
+                    stage[k] = eb0[e * 4 + r];
+                else
+                    stage[k] = mrec[int64_t(spk[k]) * (KQ * 4) + (r - 4)];
+            }
+        }
+    };
+    auto store_chunk = [&](int buf, int64_t ch) {
+#pragma unroll
+        for (int k = 0; k < kStage; ++k) {
+            const int u = int(threadIdx.x) + k * nthr;
+            if (k * nthr >= kUnits + kCh) break;
+            if (u >= kUnits + kCh) continue;
+            const int j = u < kUnits ? u / (KS * 4) : u - kUnits;
+            if (ch + j >= e1) continue;
+            if (u < kUnits)
+                (&s_b[buf][0][0][0][0])[u] = stage[k];
+            else
+                s_bd[buf][j] = *reinterpret_cast<const float4 *>(&stage[k]);
+        }
+    };
+    // smaller workgroups (tiles of fewer than 256 queries) stage each chunk
+    // synchronously, every thread copying as many units as it takes
+    const bool piped = nthr == kMThreads;
+    auto copy_chunk = [&](int buf, int64_t ch) {
+        for (int u = int(threadIdx.x); u < kUnits + kCh; u += nthr) {
+            const int j = u < kUnits ? u / (KS * 4) : u - kUnits;
+            const int r = u < kUnits ? u % (KS * 4) : -1;
+            const int64_t e = ch + j;
+            if (e >= e1) continue;
+            if (r < 0)
+                s_bd[buf][j] = ebnd[e];
+            else if (r < 4)
+                (&s_b[buf][0][0][0][0])[u] = eb0[e * 4 + r];
+            else
+                (&s_b[buf][0][0][0][0])[u] = mrec[int64_t(cand[e]) * (KQ * 4) + (r - 4)];
+        }
+    };
+    if (e0 < e1) {
+        if (piped) {
+            load_chunk(e0);
+            store_chunk(0, e0);
+        } else {
+            copy_chunk(0, e0);
+        }
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t ch = e0; ch < e1; ch += kCh) {
+        const bool more = ch + kCh < e1;
+        if (more && piped) load_chunk(ch + kCh);
+        const int n = int((e1 - ch < kCh) ? e1 - ch : kCh);
+        for (int cb = 0; cb < n; cb += 32) {
+            const int jl = cb + (lane % 32);
+            const bool jv = jl < n;
+            const int jc = jv ? jl : cb;   // idle lanes: a valid row, column ignored
+            bf16x8 bhi[KS], blo[KS];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                bhi[ks] = s_b[buf][jc][ks][h][0];
+                blo[ks] = s_b[buf][jc][ks][h][1];
+            }
+            const float4 bd = s_bd[buf][jc];
+            f32x16 acc0 = {}, acc1 = {};
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[0][ks], bhi[ks], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(alo[1][ks], bhi[ks], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][ks], blo[ks], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][ks], blo[ks], acc1, 0, 0, 0);
+                acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[0][ks], bhi[ks], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ahi[1][ks], bhi[ks], acc1, 0, 0, 0);
+            }
+            // certified group test of the entry in this lane's column: the
+            // smallest M' over the group's rows, as a signed-integer minimum
+            // of the float bits -- exact among non-negative values, and any
+            // negative value (rounding below 0) stays negative, which keeps
+            // the candidate, as it must
+            int mi = 0x7f800000;   // +inf
+            if (full) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    mi = min(mi, min(__float_as_int(acc0[r]), __float_as_int(acc1[r])));
+            } else {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    if (rowvalid & (1u << r)) mi = min(mi, __float_as_int(acc0[r]));
+                    if (rowvalid & (1u << (16 + r))) mi = min(mi, __float_as_int(acc1[r]));
+                }
+            }
+            const float mn = __int_as_float(mi);
+            const float bound =
+                kGammaQ * (bd.w * h2 + bd.y * hm + bd.x) + kGammaB * bd.w * bd.z * hm;
+            const bool pass = jv && !(mn - bound > skip);
+            const uint64_t bal = ballot(pass);
+            if constexpr (COUNT) {
+                n_exam += uint64_t(n - cb < 32 ? n - cb : 32);
+                n_pass += uint64_t(__popc(uint32_t(bal) | uint32_t(bal >> 32)));
+            }
+            if (lane < 32 && jv && grp < ngroups)
+                act[(ch + jl) * ngroups + grp] =
+                    uint8_t(((bal >> lane) | (bal >> (lane + 32))) & 1u);
+        }
+        if (more) {
+            if (piped)
+                store_chunk(buf ^ 1, ch + kCh);
+            else
+                copy_chunk(buf ^ 1, ch + kCh);
+        }
+        __syncthreads();
+        buf ^= 1;
+    }
+    if constexpr (COUNT) {
+        if (lane == 0 && grp < ngroups) {
+            atomicAdd(&stats[0], n_exam);
+            atomicAdd(&stats[1], n_pass);
+        }
+    }
+}
+
+template <int N>
+hipError_t mfma_n(const ngd_mixture *mix, ngd_cull *c, float *out, unsigned long long *stats,
+                  hipStream_t s)
+{
+    const int tile = c->params.tile;
+    const int per = tile < kMThreads ? (tile + 63) / 64 * 64 : kMThreads;
+    const unsigned gy = unsigned((tile + kMThreads - 1) / kMThreads);
+    const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
+    hipError_t e;
+    if (c->mrec_seq != c->build_seq) {
+        // once per cull build: per-Gaussian quadratic coefficients, tile
+        // centres, per-entry centred coefficients
+        k_mfma_coef<N><<<unsigned((c->k + 255) / 256), 256, 0, s>>>(
+            c->k, c->grec.as<float>(), c->mrec.as<__bf16>(), c->mrow.as<float>());
+        k_tile_centre<N><<<unsigned(c->ntiles), 256, 0, s>>>(c->q, tile, c->qs.as<float>(),
+                                                            c->tcen.as<float>());
+        if (c->total > 0)
+            k_mfma_entry<N><<<unsigned((c->total + 255) / 256), 256, 0, s>>>(
+                c->total, c->cand.as<int32_t>(), c->ent_tile.as<int32_t>(), c->grec.as<float>(),
+                c->mrow.as<float>(), c->tcen.as<float>(), c->eb0.as<bf16x8>(),
+                c->ebnd.as<float4>());
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        c->mrec_seq = c->build_seq;
+    }
+    if (c->nitems > 0) {
+        const dim3 grid(unsigned(c->nitems), gy);
+        auto go = [&](auto kern, unsigned long long *st) {
+            kern<<<grid, per, 0, s>>>(c->q, tile, c->mrec.as<bf16x8>(), c->eb0.as<bf16x8>(),
+                                      c->ebnd.as<float4>(), c->tcen.as<float>(),
+                                      c->qs.as<float>(), c->tile_off.as<int64_t>(),
+                                      c->cand.as<int32_t>(), c->item_tile.as<int32_t>(),
+                                      c->item_off.as<int64_t>(), skip, c->act.as<uint8_t>(), st);
+        };
+        if (stats)
+            go(k_mfma_filter<N, true>, stats);
+        else
+            go(k_mfma_filter<N, false>, nullptr);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if ((e = launch_eval_flagged(mix, c, out, stats, s)) != hipSuccess) return e;
+    }
+    if (!out) return hipSuccess;
+    return launch_eval_reduce(c, out, s);
+}
+
+}  // namespace
+
+size_t mfma_rec_bytes(int n)
+{
+    const int t = n * (n + 1) / 2;
+    return size_t((t + 15) / 16) * 32 * sizeof(uint16_t);
+}
+
+size_t mfma_entry_bytes() { return 4 * sizeof(bf16x8) + sizeof(float4); }
+
+hipError_t launch_eval_mfma(const ngd_mixture *mix, ngd_cull *c, float *out,
+                            unsigned long long *stats, hipStream_t s)
+{
+    if (c->q == 0 || c->ntiles == 0) return hipSuccess;
+    switch (mix->n) {
+#define NGD_CASE(NN) \
+    case NN: return mfma_n<NN>(mix, c, out, stats, s);
+        NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
+        NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
+#undef NGD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace ngd

@@ -161,6 +161,14 @@ struct ngd_cull {
     int64_t *stats_host = nullptr;  // pinned: total, max per tile, items
     ngd::KdPlan kd_q, kd_g;    // k-d tiling plans of the queries and the Gaussians
     ngd::KdWork kd_work;
+    // matrix-core forward: quadratic coefficients of the ordered Gaussians
+    ngd::DevBuf mrec;          // k x mfma_rec_bytes(n): bf16 hi / lo pairs
+    ngd::DevBuf mrow;          // k float: bound factor R'
+    ngd::DevBuf tcen;          // ntiles x n float: centre of each tile's query box
+    ngd::DevBuf eb0;           // total x 64 B: centred constant / linear terms, bf16
+    ngd::DevBuf ebnd;          // total x 4 float: bound terms of each entry
+    int64_t build_seq = 0;     // builds of this handle
+    int64_t mrec_seq = -1;     // build the coefficients belong to
 };
 
 namespace ngd {
@@ -184,6 +192,21 @@ hipError_t launch_eval_dense(const ngd_mixture *mix, const float *queries, int64
 hipError_t launch_eval_stats(const ngd_mixture *mix, const ngd_cull *c,
                              unsigned long long *stats, hipStream_t s);
 // Culled forward; with out == nullptr only the keep/skip flags are written.
+hipError_t launch_eval_reduce(const ngd_cull *c, float *out, hipStream_t s);
+// The float32 forward over the (entry, group) pairs a filter flagged in
+// c->act (1: evaluate); rewrites the flags with the kept decision.  out,
+// stats as for launch_eval_mfma (stats[2..4] only).
+hipError_t launch_eval_flagged(const ngd_mixture *mix, const ngd_cull *c, float *out,
+                               unsigned long long *stats, hipStream_t s);
+// Culled forward with the BF16 MFMA filter (eval_mfma.hip).  out: colours;
+// out == nullptr: keep/skip flags only; stats != nullptr: counting mode,
+// stats[0..4] = (group-candidate pairs examined, not skipped by the matrix
+// filter, passed check 1, passed check 2, kept).  Builds the coefficient
+// records (c->mrec, c->mrow, reserved by the caller) once per cull build.
+hipError_t launch_eval_mfma(const ngd_mixture *mix, ngd_cull *c, float *out,
+                            unsigned long long *stats, hipStream_t s);
+size_t mfma_rec_bytes(int n);
+size_t mfma_entry_bytes();
 hipError_t launch_eval_culled(const ngd_mixture *mix, const ngd_cull *c, float *out,
                               hipStream_t s);
 hipError_t launch_backward_dense(const ngd_mixture *mix, const float *queries, int64_t q,

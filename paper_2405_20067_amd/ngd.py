@@ -15,12 +15,13 @@ import numpy as np
 
 __all__ = [
     "NgdError", "CullParams", "Mixture", "Cull", "lib", "LIB_PATH",
-    "eval_mixture", "eval_backward", "eval_stats", "l2_loss", "FP32",
+    "eval_mixture", "eval_backward", "eval_stats", "l2_loss", "FP32", "BF16_MFMA",
     "E_INVAL", "E_SINGULAR", "E_HIP", "E_NOMEM", "E_STALE",
 ]
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libngd.so")
 FP32 = 0
+BF16_MFMA = 1
 E_INVAL, E_SINGULAR, E_HIP, E_NOMEM, E_STALE = -1, -2, -3, -4, -5
 
 _lib = None
@@ -70,7 +71,7 @@ _SIGS = [
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
       ctypes.c_void_p, ctypes.c_void_p]),
     ("ngd_eval_stats", ctypes.c_int,
-     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
       ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
     ("ngd_eval_backward", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
@@ -256,14 +257,17 @@ def eval_mixture(mix: Mixture, cull: Cull | None, queries, out=None, precision=F
     return out
 
 
-def eval_stats(mix: Mixture, cull: Cull, queries, stream=None):
-    """Work counters of the culled forward: dict(examined, pass1, pass2, kept),
-    counted in (64-query group, candidate) pairs."""
+def eval_stats(mix: Mixture, cull: Cull, queries, precision=FP32, stream=None):
+    """Work counters of the culled forward of `precision`: dict(examined,
+    filtered, pass1, pass2, kept), counted in (64-query group, candidate)
+    pairs; `filtered` are those the matrix-core filter did not skip (all
+    examined ones with FP32)."""
     q = queries.numel() // mix.n
-    counts = (ctypes.c_int64 * 4)()
+    counts = (ctypes.c_int64 * 5)()
     _check(lib().ngd_eval_stats(mix.handle, cull.handle, _ptr(queries, "queries", q * mix.n),
-                                q, counts, _stream(stream)))
-    return dict(examined=counts[0], pass1=counts[1], pass2=counts[2], kept=counts[3])
+                                q, int(precision), counts, _stream(stream)))
+    return dict(examined=counts[0], filtered=counts[1], pass1=counts[2], pass2=counts[3],
+                kept=counts[4])
 
 
 def eval_backward(mix: Mixture, cull: Cull | None, queries, grad_out, grads=None,

@@ -1,0 +1,161 @@
+"""Parity of the BF16 matrix-core forward (precision NGD_BF16_MFMA) against
+the float64 oracle, through the C-ABI.
+
+The matrix cores only decide which (64-query group, candidate) pairs are
+skipped, with a certified bound; every pair they do not skip is evaluated by
+the float32 code.  So the colours meet the float32 bar (1e-4 normwise) and
+differ from the float32 forward only by pairs below the skip certificate
+(G < tau 2^-20).  The bar the method sets for a BF16 path, 2e-3, is checked
+as well.  The backward sums over the pairs the forward kept.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_helpers import case, dev, host, normwise, per_gaussian_csr, per_query_csr
+from paper_2405_20067_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL_FP32 = 1e-4
+TOL_BF16 = 2e-3
+
+CASES = [
+    dict(n=4, k=300, q=3000, tile=256),
+    dict(n=6, k=777, q=5000, tile=100),
+    dict(n=10, k=1500, q=4100, tile=256),
+    dict(n=10, k=65, q=257, tile=64),
+    dict(n=3, k=64, q=70, tile=1),
+    dict(n=2, k=130, q=1000, tile=1024),
+    dict(n=12, k=400, q=2000, tile=256),
+    dict(n=6, k=5000, q=70000, tile=256),
+    dict(n=10, k=3000, q=9000, tile=256, sdiag=(3.0, 30.0)),
+]
+
+
+def _ids(c):
+    fmt = lambda v: "-".join(f"{x:g}" for x in v) if isinstance(v, tuple) else v
+    return "-".join(f"{k}{fmt(v)}" for k, v in c.items())
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _setup(cfg):
+    from paper_2405_20067_amd import ngd
+    n, k, q = cfg["n"], cfg["k"], cfg["q"]
+    mix, x, proj = case(n, k, q, seed=n * 7 + k, sdiag=cfg.get("sdiag"))
+    m = ngd.Mixture(n, k)
+    m.update(dev(mix["mean"]), dev(mix["factor"]), dev(mix["weight"]), dev(mix["colour"]))
+    xd = dev(x)
+    p = ngd.default_params()
+    p.tile = cfg["tile"]
+    c = ngd.Cull().build(m, xd, proj, p)
+    return mix, x, m, xd, c
+
+
+@pytest.mark.parametrize("cfg", CASES, ids=_ids)
+def test_mfma_forward_matches_oracle(torch_cuda, cfg):
+    from paper_2405_20067_amd import ngd
+    mix, x, m, xd, c = _setup(cfg)
+    fm = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    ff = host(ngd.eval_mixture(m, c, xd, precision=ngd.FP32))
+    full = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x)
+    assert normwise(fm, full) <= TOL_FP32
+    assert normwise(fm, full) <= TOL_BF16
+    exp = c.export()
+    qoff, gidx = per_query_csr(exp, cfg["q"], cfg["tile"])
+    restricted = oracle.eval_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x,
+                                   qoff, gidx)
+    assert normwise(fm, restricted) <= TOL_FP32
+    # the two forwards differ only by pairs under the skip certificate
+    ac = mix["weight"].astype(np.float64)[:, None] * np.abs(mix["colour"])
+    slack = 1e-4 * 2.0 ** -20 * ac.sum(0)
+    assert np.all(np.abs(fm.astype(np.float64) - ff) <= slack + 1e-6 * np.abs(ff).max())
+
+
+@pytest.mark.parametrize("cfg", [c for c in CASES if c["tile"] > 1 and c["n"] > 2], ids=_ids)
+def test_mfma_backward_matches_oracle(torch_cuda, cfg):
+    from paper_2405_20067_amd import ngd
+    mix, x, m, xd, c = _setup(cfg)
+    q = cfg["q"]
+    g = inputs.gen_grad_out(q, seed=cfg["k"])
+    ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA)
+    got = [host(t) for t in ngd.eval_backward(m, c, xd, dev(g), precision=ngd.BF16_MFMA)]
+    exp = c.export()
+    sel, qoff, qidx = per_gaussian_csr(exp, q, cfg["tile"])
+    part = oracle.grad_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g,
+                             sel, qoff, qidx)
+    full = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g)
+    for name, a, b, f in zip(("mean", "factor", "weight", "colour"), got, part, full):
+        want = np.zeros_like(f)
+        want[sel] = b
+        assert normwise(a, want) <= TOL_FP32, name
+        assert normwise(a, f) <= TOL_BF16, name
+
+
+def test_mfma_flags_without_forward(torch_cuda):
+    """A backward with no forward on the cull decides the kept pairs itself,
+    with the matrix-core filter; the result is the one after a forward."""
+    from paper_2405_20067_amd import ngd
+    cfg = dict(n=10, k=1500, q=4100, tile=256)
+    mix, x, m, xd, c = _setup(cfg)
+    g = dev(inputs.gen_grad_out(cfg["q"], seed=5))
+    a = [host(t) for t in ngd.eval_backward(m, c, xd, g, precision=ngd.BF16_MFMA)]
+    ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA)
+    b = [host(t) for t in ngd.eval_backward(m, c, xd, g, precision=ngd.BF16_MFMA)]
+    for u, v in zip(a, b):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_mfma_filter_work_and_kept_pairs(torch_cuda):
+    """The matrix filter leaves far fewer pairs for the float32 code than the
+    float32 kernel examines, and keeps (almost exactly) the same pairs."""
+    from paper_2405_20067_amd import ngd
+    cfg = dict(n=10, k=3000, q=20000, tile=256)
+    mix, x, m, xd, c = _setup(cfg)
+    sf = ngd.eval_stats(m, c, xd, precision=ngd.FP32)
+    sm = ngd.eval_stats(m, c, xd, precision=ngd.BF16_MFMA)
+    assert sf["examined"] == sm["examined"] and sf["filtered"] == sf["examined"]
+    assert sm["filtered"] <= 0.5 * sm["examined"], sm
+    assert sm["kept"] <= sm["filtered"]
+    assert abs(sm["kept"] - sf["kept"]) <= 1e-3 * sf["kept"] + 2, (sm, sf)
+
+
+def test_mfma_needs_a_cull(torch_cuda):
+    from paper_2405_20067_amd import ngd
+    mix, x, m, xd, c = _setup(dict(n=4, k=50, q=300, tile=256))
+    with pytest.raises(ngd.NgdError) as ei:
+        ngd.eval_mixture(m, None, xd, precision=ngd.BF16_MFMA)
+    assert ei.value.code == ngd.E_INVAL
+    with pytest.raises(ngd.NgdError):
+        ngd.eval_mixture(m, c, xd, precision=7)
+
+
+def test_mfma_repeat_and_rebuild(torch_cuda):
+    """Bitwise repeatable; the coefficient records follow a rebuild."""
+    from paper_2405_20067_amd import ngd
+    cfg = dict(n=6, k=777, q=5000, tile=256)
+    mix, x, m, xd, c = _setup(cfg)
+    a = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    b = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    np.testing.assert_array_equal(a, b)
+    mix2 = dict(mix)
+    mix2["mean"] = (mix["mean"] + np.float32(0.01)).astype(np.float32)
+    m.update(dev(mix2["mean"]), dev(mix2["factor"]), dev(mix2["weight"]), dev(mix2["colour"]))
+    p = ngd.default_params()
+    c.build(m, xd, _proj(cfg), p)
+    f2 = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    want = oracle.eval_mixture(mix2["mean"], mix2["factor"], mix2["weight"], mix2["colour"], x)
+    assert normwise(f2, want) <= TOL_FP32
+
+
+def _proj(cfg):
+    _, _, proj = case(cfg["n"], cfg["k"], cfg["q"], seed=cfg["n"] * 7 + cfg["k"])
+    return proj
