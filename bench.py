@@ -46,9 +46,12 @@ def stage_flops(n: int):
     return rows(0, k1), rows(k1, k2), rows(k2, n), 1 + 6
 
 
-def source_hash(path):
+def source_hash(*paths):
     import hashlib
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -247,12 +250,12 @@ def main():
         valu = 64 * (f1 * cnt["filtered"] + f2 * cnt["pass1"] + f3 * cnt["pass2"]
                      + f4 * cnt["kept"])
         t = paths[name]["stages_ms"]["forward"] * 1e-3
-        src = KERNEL_SRC if name == "fp32" else MFMA_SRC
+        src = (KERNEL_SRC,) if name == "fp32" else (MFMA_SRC, KERNEL_SRC)
         traffic = None
         tf = TRAFFIC_FILES[name]
         if os.path.exists(tf):
             tr = json.load(open(tf))
-            if tr.get("source_sha256_16") == source_hash(src) and tr.get("workload") == w.name:
+            if tr.get("source_sha256_16") == source_hash(*src) and tr.get("workload") == w.name:
                 traffic = tr.get("hbm_bytes_per_launch")
         if name == "fp32":
             a = valu / t / 1e12

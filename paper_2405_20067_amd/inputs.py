@@ -91,7 +91,8 @@ WORKLOADS = {
     "10d-4m": Workload(
         "10d-4m", 10, 262144, 1 << 22, "pos3+nrm3+view3+rough1",
         (10.0, 200.0), 5.0, 0.5, k_target=4096, backward=True,
-        description="10-D, K=262,144, 2^22 queries, culled forward + backward"),
+        description="10-D, K=262,144, 2^22 queries, culled forward + backward; BF16 MFMA "
+                    "filter against the float32 kernel"),
 }
 
 

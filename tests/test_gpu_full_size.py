@@ -64,13 +64,44 @@ def test_full_size_cull_forward_backward(torch_cuda, name):
     qs = rng.choice(w.q, 192, replace=False)
     fo = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x[qs])
     assert normwise(f[qs], fo) <= TOL_FP32
+    # the matrix-core forward on the same cull: the same sampled bar, and
+    # against the float32 forward within the skip certificate
+    fm = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    assert normwise(fm[qs], fo) <= TOL_FP32
+    ac = mix["weight"].astype(np.float64)[:, None] * np.abs(mix["colour"])
+    slack = 1e-4 * 2.0 ** -20 * ac.sum(0)
+    assert np.all(np.abs(fm.astype(np.float64) - f) <= slack + 1e-6 * np.abs(f).max())
+    gm = [host(t) for t in ngd.eval_backward(m, c, xd, dev(g), precision=ngd.BF16_MFMA)]
     # backward: sampled Gaussians (the ones with the largest gradients among a
     # random subset, so the comparison is not of zeros) over all queries
     pool = rng.choice(w.k, 4096, replace=False)
     mag = np.abs(grads[2][pool])
     sel = pool[np.argsort(-mag)[:24]]
     go = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g, sel=sel)
-    for name_o, a, b in zip(("mean", "factor", "weight", "colour"), grads, go):
+    for name_o, a, am, b in zip(("mean", "factor", "weight", "colour"), grads, gm, go):
         # the culled pairs' terms are in the oracle's sum but not in the GPU's;
         # their share is checked by the small cases; here the bar is 2e-3
         assert normwise(a[sel], b) <= 2e-3, name_o
+        assert normwise(am[sel], b) <= 2e-3, name_o
+
+
+def test_full_size_4m_queries_both_precisions(torch_cuda):
+    """2^22 queries (the matrix-core comparison workload): sampled colours
+    of both forwards against the float64 oracle over all K Gaussians."""
+    from paper_2405_20067_amd import ngd
+    w, mix, x, proj = _workload("10d-4m")
+    print(f"[10d-4m] n={w.n} k={w.k} q={w.q}", flush=True)
+    m = ngd.Mixture(w.n, w.k)
+    m.update(dev(mix["mean"]), dev(mix["factor"]), dev(mix["weight"]), dev(mix["colour"]))
+    xd = dev(x)
+    c = ngd.Cull().build(m, xd, proj, ngd.default_params())
+    ff = host(ngd.eval_mixture(m, c, xd, precision=ngd.FP32))
+    fm = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    rng = np.random.default_rng(11)
+    qs = rng.choice(w.q, 128, replace=False)
+    fo = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x[qs])
+    assert normwise(ff[qs], fo) <= TOL_FP32
+    assert normwise(fm[qs], fo) <= TOL_FP32
+    ac = mix["weight"].astype(np.float64)[:, None] * np.abs(mix["colour"])
+    slack = 1e-4 * 2.0 ** -20 * ac.sum(0)
+    assert np.all(np.abs(fm.astype(np.float64) - ff) <= slack + 1e-6 * np.abs(ff).max())
