@@ -149,13 +149,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward(
         return;
     }
 #pragma unroll
-    for (int a = 0; a < N; ++a) b1[a] = wave_sum(b1[a]);
+    for (int a = 0; a < N; ++a) b1[a] = wave_sum_last(b1[a]);
 #pragma unroll
-    for (int e = 0; e < T; ++e) b2[e] = wave_sum(b2[e]);
-    h0 = wave_sum(h0);
-    h1 = wave_sum(h1);
-    h2 = wave_sum(h2);
-    if (lane != 0) return;
+    for (int e = 0; e < T; ++e) b2[e] = wave_sum_last(b2[e]);
+    h0 = wave_sum_last(h0);
+    h1 = wave_sum_last(h1);
+    h2 = wave_sum_last(h2);
+    if (lane != kWave - 1) return;
     // S = S' / sqrt(c), y = y' / sqrt(c), c = log2(e)/2:
     //   S^T B1 = S'^T B1' / c,  S^T B2 = S'^T B2' / c^1.5
     const float inv_c = float(1.0 / kHalfLog2e);
@@ -292,13 +292,13 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
         return;
     }
 #pragma unroll
-    for (int a = 0; a < N; ++a) b1[a] = wave_sum(b1[a]);
+    for (int a = 0; a < N; ++a) b1[a] = wave_sum_last(b1[a]);
 #pragma unroll
-    for (int e = 0; e < T; ++e) b2[e] = wave_sum(b2[e]);
-    h0 = wave_sum(h0);
-    h1 = wave_sum(h1);
-    h2 = wave_sum(h2);
-    if (lane != 0) return;
+    for (int e = 0; e < T; ++e) b2[e] = wave_sum_last(b2[e]);
+    h0 = wave_sum_last(h0);
+    h1 = wave_sum_last(h1);
+    h2 = wave_sum_last(h2);
+    if (lane != kWave - 1) return;
     float *out = gpart + it * Lay::NM;
 #pragma unroll
     for (int a = 0; a < N; ++a) out[a] = b1[a];

@@ -225,6 +225,17 @@ static void cull_release(ngd_cull *c)
                       &c->kd_work.prefix, &c->kd_work.rank, &c->mrec, &c->mrow, &c->tcen,
                       &c->eb0, &c->ebnd};
     for (DevBuf *b : bufs) b->release();
+    KdWork *works[] = {&c->kd_work_g};
+    for (KdWork *w : works) {
+        DevBuf *wb[] = {&w->idx[0], &w->idx[1], &w->val[0], &w->val[1], &w->ext[0], &w->ext[1],
+                        &w->hist, &w->cnt, &w->dim, &w->prefix, &w->rank};
+        for (DevBuf *b : wb) b->release();
+    }
+    if (c->side) (void)hipStreamDestroy(c->side);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    c->side = nullptr;
+    c->ev_fork = c->ev_join = nullptr;
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     c->stats_host = nullptr;
 }

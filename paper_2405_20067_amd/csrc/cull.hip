@@ -520,26 +520,39 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     if (c->params.tiling == 0) {
         // k-d order of the query projections (runs of `tile`, and of 64
         // inside those) and of the projected means (runs of 64, the chunks
-        // of the interval test)
+        // of the interval test).  The two are independent: the Gaussians'
+        // order runs on a second stream, forked after their projections and
+        // joined before anything reads it.
+        bool forked = false;
+        if (k > kWave) {
+            if ((e = hipEventRecord(c->ev_fork, s)) != hipSuccess) return e;
+            if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
+            forked = true;
+            e = kd_order(c->kd_g, c->kd_work_g, P, c->g_mr.as<float>(), k,
+                         c->gperm.as<int32_t>(), c->g_mr_s.as<float>(), c->side);
+            const hipError_t ej = hipEventRecord(c->ev_join, c->side);
+            if (e == hipSuccess) e = ej;
+            if (e != hipSuccess) {
+                (void)hipStreamWaitEvent(s, c->ev_join, 0);
+                return e;
+            }
+            g_sorted = true;
+        } else if (k > 0) {
+            k_iota<<<nblk(k, kThreads), kThreads, 0, s>>>(c->gperm.as<int32_t>(), k);
+        }
         if (q > 0) {
             if (q <= std::min(c->params.tile, kWave))
                 k_iota<<<nblk(q, kThreads), kThreads, 0, s>>>(c->perm.as<int32_t>(), q);
             else if ((e = kd_order(c->kd_q, c->kd_work, P, c->qr.as<float>(), q,
-                                   c->perm.as<int32_t>(), c->qr_s.as<float>(), s)) != hipSuccess)
+                                   c->perm.as<int32_t>(), c->qr_s.as<float>(), s)) !=
+                     hipSuccess) {
+                if (forked) (void)hipStreamWaitEvent(s, c->ev_join, 0);
                 return e;
+            }
             else
                 qr_s = c->qr_s.as<float>();
         }
-        if (k > 0) {
-            if (k <= kWave)
-                k_iota<<<nblk(k, kThreads), kThreads, 0, s>>>(c->gperm.as<int32_t>(), k);
-            else if ((e = kd_order(c->kd_g, c->kd_work, P, c->g_mr.as<float>(), k,
-                                   c->gperm.as<int32_t>(), c->g_mr_s.as<float>(), s)) !=
-                     hipSuccess)
-                return e;
-            else
-                g_sorted = true;
-        }
+        if (forked && (e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess) return e;
     }
     // Morton: queries: keys, sort -> perm
     if (c->params.tiling == 1 && q > 0) {
@@ -845,7 +858,12 @@ bool cull_reserve_front(ngd_cull *c)
     if (c->params.tiling == 0) {
         ok &= kd_plan(c->kd_q, q, c->params.tile, std::min(c->params.tile, kWave)) &&
               kd_plan(c->kd_g, k, kWave, kWave);
-        ok = ok && kd_reserve(c->kd_work, c->kd_q, q, P) && kd_reserve(c->kd_work, c->kd_g, k, P);
+        ok = ok && kd_reserve(c->kd_work, c->kd_q, q, P) && kd_reserve(c->kd_work_g, c->kd_g, k, P);
+        if (ok && !c->side) ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+        if (ok && !c->ev_fork)
+            ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+        if (ok && !c->ev_join)
+            ok = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
     }
     return ok;
 }

@@ -160,7 +160,10 @@ struct ngd_cull {
     ngd::DevBuf stats;         // 2 int64: total, max per tile
     int64_t *stats_host = nullptr;  // pinned: total, max per tile, items
     ngd::KdPlan kd_q, kd_g;    // k-d tiling plans of the queries and the Gaussians
-    ngd::KdWork kd_work;
+    ngd::KdWork kd_work;       // query k-d work
+    ngd::KdWork kd_work_g;     // Gaussian k-d work (runs concurrently, on `side`)
+    hipStream_t side = nullptr;          // default-priority, non-blocking
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // matrix-core forward: quadratic coefficients of the ordered Gaussians
     ngd::DevBuf mrec;          // k x mfma_rec_bytes(n): bf16 hi / lo pairs
     ngd::DevBuf mrow;          // k float: bound factor R'

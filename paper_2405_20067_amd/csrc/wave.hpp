@@ -62,6 +62,26 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// Sum over the wave by DPP (no LDS traffic), valid in lane 63 only: the
+// inclusive-scan steps of wave_inclusive_scan on floats.  A fixed order, so
+// bitwise reproducible.
+template <int CTRL, int ROWS> __device__ __forceinline__ float dpp_add(float x)
+{
+    const int y = __builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROWS, 0xf, false);
+    return x + __int_as_float(y);
+}
+
+__device__ __forceinline__ float wave_sum_last(float v)
+{
+    v = dpp_add<kDppRowShr1, 0xf>(v);
+    v = dpp_add<kDppRowShr2, 0xf>(v);
+    v = dpp_add<kDppRowShr4, 0xf>(v);
+    v = dpp_add<kDppRowShr8, 0xf>(v);
+    v = dpp_add<kDppRowBcast15, 0xa>(v);
+    v = dpp_add<kDppRowBcast31, 0xc>(v);
+    return v;
+}
+
 __device__ __forceinline__ float wave_min(float v)
 {
 #pragma unroll
