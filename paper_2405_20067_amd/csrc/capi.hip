@@ -211,8 +211,8 @@ static void cull_release(ngd_cull *c)
     DevBuf *bufs[] = {&c->proj,    &c->qr,       &c->range_part, &c->qrange,  &c->g_mr,
                       &c->g_thr,   &c->keys0,    &c->keys1,      &c->vals0,   &c->vals1,
                       &c->radix_hist, &c->radix_off, &c->perm,   &c->gperm,   &c->qs,
-                      &c->gs,      &c->tile_lo,  &c->tile_hi, &c->sup_lo, &c->sup_hi, &c->qr_s,    &c->grec,    &c->g_mr_s,
-                      &c->g_thr_s, &c->masks,    &c->seg_cnt,    &c->tile_cnt, &c->tile_off,
+                      &c->gs,      &c->tile_lo,  &c->tile_hi, &c->tbnd,   &c->sbnd,   &c->qr_s,    &c->grec,    &c->g_mr_s,
+                      &c->g_ub, &c->g_lb, &c->masks,    &c->seg_cnt,    &c->tile_cnt, &c->tile_off,
                       &c->cand,    &c->g_cnt,    &c->g_off,      &c->g_tiles, &c->scan_tmp,
                       &c->stats,   &c->item_cnt, &c->item_off,   &c->item_tile, &c->fpart,
                       &c->gitem_cnt, &c->gitem_off, &c->gitem_g, &c->gpart,   &c->gflag,

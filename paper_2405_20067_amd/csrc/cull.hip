@@ -177,14 +177,15 @@ __global__ __launch_bounds__(kThreads) void k_keys(int64_t n, int P,
 
 // ---- tiles ---------------------------------------------------------------
 template <int N, int PMAX>
-__global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P,
+__global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P, int PP,
                                                       const int32_t *__restrict__ perm,
                                                       const float *__restrict__ qr,
                                                       const float *__restrict__ qr_s,
                                                       const float *__restrict__ queries,
                                                       float *__restrict__ qs,
                                                       float *__restrict__ tlo,
-                                                      float *__restrict__ thi)
+                                                      float *__restrict__ thi,
+                                                      float *__restrict__ tbnd)
 {
     __shared__ float smin[1024 / kWave][PMAX], smax[1024 / kWave][PMAX];
     const int64_t t = blockIdx.x;
@@ -222,92 +223,173 @@ __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P
         }
     }
     __syncthreads();
-    if (threadIdx.x < P) {
+    if (int(threadIdx.x) < PP) {
         const int j = threadIdx.x;
-        float a = INFINITY, b = -INFINITY;
-        for (int i = 0; i < nw; ++i) {
-            a = fminf(a, smin[i][j]);
-            b = fmaxf(b, smax[i][j]);
+        // the padding projections pass every test
+        float a = -INFINITY, b = INFINITY;
+        if (j < P) {
+            a = INFINITY;
+            b = -INFINITY;
+            for (int i = 0; i < nw; ++i) {
+                a = fminf(a, smin[i][j]);
+                b = fmaxf(b, smax[i][j]);
+            }
+            tlo[t * P + j] = a;
+            thi[t * P + j] = b;
         }
-        tlo[t * P + j] = a;
-        thi[t * P + j] = b;
+        tbnd[t * 2 * PP + j] = a;
+        tbnd[t * 2 * PP + PP + j] = b;
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_gauss_gather(
-    int64_t k, int R, int P, const int32_t *__restrict__ gperm, const float *__restrict__ rec,
-    const float *__restrict__ g_mr, const float *__restrict__ g_thr, float *__restrict__ grec,
-    float *__restrict__ g_mr_s, float *__restrict__ g_thr_s)
+// Records of the Gaussians in their tile order: a block moves 64 records of
+// R floats as float4s, consecutive threads on consecutive float4s.
+__global__ __launch_bounds__(kThreads) void k_rec_gather(int64_t k, int R,
+                                                         const int32_t *__restrict__ gperm,
+                                                         const float *__restrict__ rec,
+                                                         float *__restrict__ grec)
+{
+    const int R4 = R / 4;
+    const int64_t s0 = int64_t(blockIdx.x) * kWave;
+    const int cnt = int(k - s0 < kWave ? k - s0 : kWave);
+    const float4 *src = reinterpret_cast<const float4 *>(rec);
+    float4 *dst = reinterpret_cast<float4 *>(grec) + s0 * R4;
+    for (int e = threadIdx.x; e < cnt * R4; e += kThreads) {
+        const int sl = e / R4;
+        const int f = e - sl * R4;
+        dst[e] = src[int64_t(gperm[s0 + sl]) * R4 + f];
+    }
+}
+
+// ---- the interval test restated as two comparisons ------------------------
+// For a Gaussian with projected mean m and threshold thr = fl(kappa^2 sigma^2)
+// on projection j, Eq. 5 keeps a box [lo, hi] iff
+//     fl(d * d) <= thr,   d = max(fl(lo - m), fl(m - hi), 0).
+// x -> fl(x * x) is monotone on x >= 0, so fl(d * d) <= thr iff d <= s, the
+// largest float whose rounded square is <= thr.  d <= s iff fl(lo - m) <= s
+// and fl(m - hi) <= s; x -> fl(x - m) and x -> fl(m - x) are monotone too, so
+// these hold iff lo <= U and hi >= L, with U the largest float x such that
+// fl(x - m) <= s and L the smallest float x such that fl(m - x) <= s.  The
+// test per (lane, box, projection) is then two comparisons, with exactly the
+// outcome of the formula (finite bounds and means; thr < 0 keeps nothing,
+// U = L = NaN).  Each limit is found by bisection over the ordered bit
+// patterns of the floats, which needs only the monotonicity; it starts from a
+// bracket of 8 units in the last place about the arithmetic guess and falls
+// back to the whole range when that bracket does not hold the change.
+
+// ordered image of a non-NaN float: keys compare as the floats do
+__device__ __forceinline__ int32_t fkey(float x)
+{
+    const int32_t b = __float_as_int(x);
+    return b >= 0 ? b : (b ^ 0x7fffffff);
+}
+
+__device__ __forceinline__ float fkey_inv(int32_t key)
+{
+    return __int_as_float(key >= 0 ? key : (key ^ 0x7fffffff));
+}
+
+constexpr int32_t kKeyNegInf = int32_t(0xff800000u ^ 0x7fffffffu);
+constexpr int32_t kKeyPosInf = 0x7f800000;
+
+// The largest key in [lo, hi] whose float satisfies pred, for pred true at
+// lo and monotone (true, then false) on the range.
+template <class Pred>
+__device__ int32_t last_true(const Pred &pred, float guess, int32_t lo, int32_t hi)
+{
+    if (pred(fkey_inv(hi))) return hi;
+    // invariant: pred(lo) true, pred(hi) false
+    if (guess == guess) {
+        const int64_t g = fkey(guess);
+        const int32_t a = int32_t(g - 8 > lo ? g - 8 : lo);
+        const int32_t b = int32_t(g + 8 < hi ? g + 8 : hi);
+        if (pred(fkey_inv(a))) lo = a;
+        if (!pred(fkey_inv(b))) hi = b;
+    }
+    while (int64_t(hi) - lo > 1) {
+        const int32_t mid = int32_t((int64_t(lo) + hi) >> 1);
+        if (pred(fkey_inv(mid)))
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_gauss_limits(
+    int64_t k, const int32_t *__restrict__ gperm, const float *__restrict__ g_mr,
+    const float *__restrict__ g_mr_s, const float *__restrict__ g_thr, float *__restrict__ g_ub,
+    float *__restrict__ g_lb)
 {
     const int64_t s = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (s >= k) return;
+    const int64_t j = blockIdx.y;
     const int64_t i = gperm[s];
-    for (int e = 0; e < R; e += 4)
-        *reinterpret_cast<float4 *>(grec + s * R + e) =
-            *reinterpret_cast<const float4 *>(rec + i * R + e);
-    for (int j = 0; j < P; ++j) {
-        if (g_mr) g_mr_s[j * k + s] = g_mr[j * k + i];   // null: already in order
-        g_thr_s[j * k + s] = g_thr[j * k + i];
+    // null g_mr_s: the means are not in order yet
+    const float m = g_mr_s ? g_mr_s[j * k + s] : g_mr[j * k + i];
+    const float thr = g_thr[j * k + i];
+    float ub = __int_as_float(0x7fc00000), lb = ub;   // NaN: nothing passes
+    if (thr >= 0.0f && m - m == 0.0f) {
+        const float r = fkey_inv(last_true([thr](float x) { return x * x <= thr; }, sqrtf(thr),
+                                           fkey(0.0f), kKeyPosInf));
+        ub = fkey_inv(last_true([m, r](float x) { return x - m <= r; }, m + r, kKeyNegInf,
+                                kKeyPosInf));
+        // the smallest x with fl(m - x) <= r: one key above the largest
+        // with fl(m - x) > r (none: -inf itself passes)
+        const auto fails = [m, r](float x) { return !(m - x <= r); };
+        lb = fails(-INFINITY)
+                 ? fkey_inv(last_true(fails, m - r, kKeyNegInf, kKeyPosInf) + 1)
+                 : -INFINITY;
     }
+    g_ub[j * k + s] = ub;
+    g_lb[j * k + s] = lb;
 }
 
-// Bounds of every super-tile: the union of its tiles' bounds.
-__global__ __launch_bounds__(kThreads) void k_super_bounds(int64_t ntiles, int P,
-                                                           const float *__restrict__ tlo,
-                                                           const float *__restrict__ thi,
-                                                           float *__restrict__ slo,
-                                                           float *__restrict__ shi)
+// Bounds of every super-tile: the union of its tiles' boxes.
+__global__ __launch_bounds__(kThreads) void k_super_bounds(int64_t ntiles, int PP,
+                                                           const float *__restrict__ tbnd,
+                                                           float *__restrict__ sbnd)
 {
     const int64_t nsup = (ntiles + kSuperTiles - 1) / kSuperTiles;
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (i >= nsup * P) return;
-    const int64_t sp = i / P;
-    const int j = int(i - sp * P);
+    if (i >= nsup * 2 * PP) return;
+    const int64_t sp = i / (2 * PP);
+    const int e = int(i - sp * 2 * PP);
     const int64_t t1 = (sp + 1) * kSuperTiles < ntiles ? (sp + 1) * kSuperTiles : ntiles;
-    float a = INFINITY, b = -INFINITY;
-    for (int64_t t = sp * kSuperTiles; t < t1; ++t) {
-        a = fminf(a, tlo[t * P + j]);
-        b = fmaxf(b, thi[t * P + j]);
-    }
-    slo[i] = a;
-    shi[i] = b;
+    float v = e < PP ? INFINITY : -INFINITY;
+    for (int64_t t = sp * kSuperTiles; t < t1; ++t)
+        v = e < PP ? fminf(v, tbnd[t * 2 * PP + e]) : fmaxf(v, tbnd[t * 2 * PP + e]);
+    sbnd[i] = v;
 }
 
 // ---- the interval test (Eq. 5 per tile) -----------------------------------
-// One wave per chunk of 64 ordered Gaussians (lane = Gaussian, its projected
-// means and thresholds in registers) walks a range of tiles with the bounds
-// wave-uniform, first per super-tile of kSuperTiles tiles, then per tile for
-// the lanes still alive; every test stops as soon as no lane survives.  A
-// super-tile's interval contains each of its tiles' intervals, so its
-// distance is never larger (rounding is monotone): a lane culled for the
-// super-tile is culled for each tile, and the masks are those of the plain
-// per-tile test bit for bit.
-template <int PMAX>
-__device__ __forceinline__ bool interval_test(bool alive, int P, const float (&mr)[PMAX],
-                                              const float (&thr)[PMAX],
-                                              const float *__restrict__ lo,
-                                              const float *__restrict__ hi)
+// One wave per chunk of 64 ordered Gaussians (lane = Gaussian, its limits
+// U, L in registers) walks a range of tiles with the boxes wave-uniform,
+// first per super-tile of kSuperTiles tiles, then per tile for the lanes
+// still alive; a test stops once no lane survives (checked every 4
+// projections).  A super-tile's box contains each of its tiles' boxes, so a
+// lane it culls is culled for each tile, and the masks are those of the
+// plain per-tile test bit for bit.
+template <int PP>
+__device__ __forceinline__ uint64_t box_test(uint64_t alive, const float (&ub)[PP],
+                                             const float (&lb)[PP],
+                                             const float *__restrict__ box)
 {
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) {
-        if (j < P) {
-            const float a = lo[j] - mr[j];
-            const float b = mr[j] - hi[j];
-            const float dist = fmaxf(fmaxf(a, b), 0.0f);
-            const float d2 = dist * dist;
-            alive = alive && (d2 <= thr[j]);
-            if (ballot(alive) == 0) break;
-        }
+    for (int g = 0; g < PP; g += 4) {
+#pragma unroll
+        for (int j = g; j < g + 4; ++j)
+            alive &= ballot(box[j] <= ub[j]) & ballot(box[PP + j] >= lb[j]);
+        if (alive == 0) break;
     }
     return alive;
 }
 
-template <int PMAX>
+template <int PP>
 __global__ __launch_bounds__(kThreads) void k_cull_test(
     int64_t k, int64_t ntiles, int64_t tpad, int P, int tiles_per_wave,
-    const float *__restrict__ g_mr_s, const float *__restrict__ g_thr_s,
-    const float *__restrict__ tlo, const float *__restrict__ thi,
-    const float *__restrict__ slo, const float *__restrict__ shi, uint64_t *__restrict__ masks)
+    const float *__restrict__ g_ub, const float *__restrict__ g_lb,
+    const float *__restrict__ tbnd, const float *__restrict__ sbnd, uint64_t *__restrict__ masks)
 {
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t nchunks = (k + kWave - 1) / kWave;
@@ -315,12 +397,14 @@ __global__ __launch_bounds__(kThreads) void k_cull_test(
     if (c >= nchunks) return;
     const int64_t s = c * kWave + lane;
     const bool valid = s < k;
-    float mr[PMAX], thr[PMAX];
+    float ub[PP], lb[PP];
 #pragma unroll
-    for (int j = 0; j < PMAX; ++j) {
-        mr[j] = (valid && j < P) ? g_mr_s[j * k + s] : 0.0f;
-        thr[j] = (valid && j < P) ? g_thr_s[j * k + s] : -1.0f;
+    for (int j = 0; j < PP; ++j) {
+        // padding projections: the boxes span everything and so does this
+        ub[j] = (valid && j < P) ? g_ub[j * k + s] : INFINITY;
+        lb[j] = (valid && j < P) ? g_lb[j * k + s] : -INFINITY;
     }
+    const uint64_t alive0 = ballot(valid);
     // tiles_per_wave is a multiple of 64 (and so of kSuperTiles)
     const int64_t t0 = int64_t(blockIdx.y) * tiles_per_wave;
     const int64_t t1 = (t0 + tiles_per_wave < ntiles) ? t0 + tiles_per_wave : ntiles;
@@ -328,13 +412,12 @@ __global__ __launch_bounds__(kThreads) void k_cull_test(
         const int64_t te = (tb + kWave < t1) ? tb + kWave : t1;
         uint64_t mine = 0;   // lane l: mask of tile tb + l
         for (int64_t sb = tb; sb < te; sb += kSuperTiles) {
-            const int64_t sp = sb / kSuperTiles;
-            const bool sup = interval_test<PMAX>(valid, P, mr, thr, slo + sp * P, shi + sp * P);
-            if (ballot(sup) == 0) continue;
+            const uint64_t sup =
+                box_test<PP>(alive0, ub, lb, sbnd + (sb / kSuperTiles) * 2 * PP);
+            if (sup == 0) continue;
             const int64_t se = (sb + kSuperTiles < te) ? sb + kSuperTiles : te;
             for (int64_t t = sb; t < se; ++t) {
-                const bool alive = interval_test<PMAX>(sup, P, mr, thr, tlo + t * P, thi + t * P);
-                const uint64_t m = ballot(alive);
+                const uint64_t m = box_test<PP>(sup, ub, lb, tbnd + t * 2 * PP);
                 if (lane == int(t - tb)) mine = m;
             }
         }
@@ -581,26 +664,31 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         if (e != hipSuccess) return e;
     }
     // tiles
+    const int PP = pad_proj(P);
     if (c->ntiles > 0) {
         const int bt = int(std::min<int64_t>(1024, (int64_t(c->params.tile) + 63) / 64 * 64));
         if (P <= 16)
             k_tile_bounds<N, 16><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
-                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s, queries,
-                c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>());
+                q, c->params.tile, P, PP, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s,
+                queries, c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>(),
+                c->tbnd.as<float>());
         else
             k_tile_bounds<N, 32><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
-                q, c->params.tile, P, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s, queries,
-                c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>());
+                q, c->params.tile, P, PP, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s,
+                queries, c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>(),
+                c->tbnd.as<float>());
         const int64_t nsup = (c->ntiles + kSuperTiles - 1) / kSuperTiles;
-        k_super_bounds<<<nblk(nsup * P, kThreads), kThreads, 0, s>>>(
-            c->ntiles, P, c->tile_lo.as<float>(), c->tile_hi.as<float>(), c->sup_lo.as<float>(),
-            c->sup_hi.as<float>());
+        k_super_bounds<<<nblk(nsup * 2 * PP, kThreads), kThreads, 0, s>>>(
+            c->ntiles, PP, c->tbnd.as<float>(), c->sbnd.as<float>());
     }
     if (k > 0) {
-        k_gauss_gather<<<nblk(k, kThreads), kThreads, 0, s>>>(
-            k, R, P, c->gperm.as<int32_t>(), mix->rec.as<float>(),
-            g_sorted ? nullptr : c->g_mr.as<float>(), c->g_thr.as<float>(), c->grec.as<float>(),
-            c->g_mr_s.as<float>(), c->g_thr_s.as<float>());
+        k_rec_gather<<<nblk(k, kWave), kThreads, 0, s>>>(k, R, c->gperm.as<int32_t>(),
+                                                          mix->rec.as<float>(),
+                                                          c->grec.as<float>());
+        k_gauss_limits<<<dim3(nblk(k, kThreads), unsigned(P)), kThreads, 0, s>>>(
+            k, c->gperm.as<int32_t>(), c->g_mr.as<float>(),
+            g_sorted ? c->g_mr_s.as<float>() : nullptr, c->g_thr.as<float>(),
+            c->g_ub.as<float>(), c->g_lb.as<float>());
     }
     k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long *>(c->stats.p), 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -616,18 +704,20 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     // interval test
     const int tiles_per_wave = 512;
     dim3 grid(nblk(c->nchunks, kThreads / kWave), nblk(c->ntiles, tiles_per_wave));
-    if (P <= 16)
-        k_cull_test<16><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,
-                                                   c->g_mr_s.as<float>(), c->g_thr_s.as<float>(),
-                                                   c->tile_lo.as<float>(), c->tile_hi.as<float>(),
-                                                   c->sup_lo.as<float>(), c->sup_hi.as<float>(),
-                                                   c->masks.as<uint64_t>());
-    else
-        k_cull_test<32><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,
-                                                   c->g_mr_s.as<float>(), c->g_thr_s.as<float>(),
-                                                   c->tile_lo.as<float>(), c->tile_hi.as<float>(),
-                                                   c->sup_lo.as<float>(), c->sup_hi.as<float>(),
-                                                   c->masks.as<uint64_t>());
+#define NGD_CULL_TEST(PPV)                                                                   \
+    k_cull_test<PPV><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,      \
+                                               c->g_ub.as<float>(), c->g_lb.as<float>(),     \
+                                               c->tbnd.as<float>(), c->sbnd.as<float>(),     \
+                                               c->masks.as<uint64_t>())
+    switch (PP) {
+    case 4: NGD_CULL_TEST(4); break;
+    case 8: NGD_CULL_TEST(8); break;
+    case 12: NGD_CULL_TEST(12); break;
+    case 16: NGD_CULL_TEST(16); break;
+    case 24: NGD_CULL_TEST(24); break;
+    default: NGD_CULL_TEST(32); break;
+    }
+#undef NGD_CULL_TEST
     // per-tile counts -> offsets
     const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
     dim3 sgrid(nblk(c->ntiles, kThreads), unsigned(c->nseg));
@@ -836,12 +926,13 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->gs.ensure(sizeof(float) * 3 * qq);
     ok &= c->tile_lo.ensure(sizeof(float) * T * P);
     ok &= c->tile_hi.ensure(sizeof(float) * T * P);
-    ok &= c->sup_lo.ensure(sizeof(float) * ((T + kSuperTiles - 1) / kSuperTiles) * P);
-    ok &= c->sup_hi.ensure(sizeof(float) * ((T + kSuperTiles - 1) / kSuperTiles) * P);
+    ok &= c->tbnd.ensure(sizeof(float) * T * 2 * pad_proj(P));
+    ok &= c->sbnd.ensure(sizeof(float) * ((T + kSuperTiles - 1) / kSuperTiles) * 2 * pad_proj(P));
     if (c->params.tiling == 0) ok &= c->qr_s.ensure(sizeof(float) * P * qq);
     ok &= c->grec.ensure(sizeof(float) * kk * rec_stride(int(n)));
     ok &= c->g_mr_s.ensure(sizeof(float) * P * kk);
-    ok &= c->g_thr_s.ensure(sizeof(float) * P * kk);
+    ok &= c->g_ub.ensure(sizeof(float) * P * kk);
+    ok &= c->g_lb.ensure(sizeof(float) * P * kk);
     ok &= c->masks.ensure(sizeof(uint64_t) * std::max<int64_t>(c->nchunks, 1) *
                           std::max<int64_t>(c->tpad, 64));
     ok &= c->seg_cnt.ensure(sizeof(int32_t) * c->nseg * T);

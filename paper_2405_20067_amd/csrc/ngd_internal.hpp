@@ -124,10 +124,14 @@ struct ngd_cull {
     ngd::DevBuf qs;            // n x q float: sorted queries, by dimension
     ngd::DevBuf gs;            // 3 x q float: sorted upstream gradient
     ngd::DevBuf tile_lo, tile_hi;   // ntiles x n_proj float
-    ngd::DevBuf sup_lo, sup_hi;     // ceil(ntiles / kSuperTiles) x n_proj float
+    // per tile / super-tile box: pad_proj(n_proj) lows, then as many highs
+    // (padding -inf / +inf)
+    ngd::DevBuf tbnd;               // ntiles x 2 pad_proj(n_proj) float
+    ngd::DevBuf sbnd;               // ceil(ntiles / kSuperTiles) x 2 pad_proj(n_proj) float
     ngd::DevBuf qr_s;               // n_proj x q float, tile order (k-d tiling)
     ngd::DevBuf grec;          // k x rec_stride float, sorted Gaussians
-    ngd::DevBuf g_mr_s, g_thr_s;    // n_proj x k float, sorted Gaussians
+    ngd::DevBuf g_mr_s;             // n_proj x k float, sorted Gaussians
+    ngd::DevBuf g_ub, g_lb;         // n_proj x k float, sorted: the interval test's limits
     ngd::DevBuf masks;         // nchunks x tpad uint64
     ngd::DevBuf seg_cnt;       // nseg x ntiles int32 (counts, then prefixes)
     ngd::DevBuf tile_cnt;      // ntiles int32
@@ -235,6 +239,9 @@ constexpr int kRadixPerBlock = 4096;
 // chunk of Gaussians outside a super-tile's bounds is outside each of its
 // tiles' bounds.
 constexpr int kSuperTiles = 16;
+// Projections per box in the interval test: n_proj rounded up to 4 (to 8
+// above 16).
+inline int pad_proj(int p) { return p <= 16 ? (p + 3) & ~3 : (p + 7) & ~7; }
 // Every buffer's capacity is checked on the host first (hipErrorInvalidValue
 // when one is too small).
 hipError_t radix_sort(int64_t n, const int64_t *n_dev, int nbits, DevBuf &k0, DevBuf &k1,
