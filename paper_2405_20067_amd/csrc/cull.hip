@@ -605,36 +605,43 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         // inside those) and of the projected means (runs of 64, the chunks
         // of the interval test).  The two are independent: the Gaussians'
         // order runs on a second stream, forked after their projections and
-        // joined before anything reads it.
+        // joined before anything reads it.  Both are enqueued a phase (a
+        // level) at a time, alternately, so that each stream has work while
+        // the host enqueues the other's.
         bool forked = false;
+        KdRun rg, rq;
         if (k > kWave) {
             if ((e = hipEventRecord(c->ev_fork, s)) != hipSuccess) return e;
             if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
             forked = true;
-            e = kd_order(c->kd_g, c->kd_work_g, P, c->g_mr.as<float>(), k,
+            e = kd_start(rg, c->kd_g, c->kd_work_g, P, c->g_mr.as<float>(), k,
                          c->gperm.as<int32_t>(), c->g_mr_s.as<float>(), c->side);
+            g_sorted = true;
+        } else if (k > 0) {
+            k_iota<<<nblk(k, kThreads), kThreads, 0, s>>>(c->gperm.as<int32_t>(), k);
+        }
+        if (e == hipSuccess && q > 0) {
+            if (q <= std::min(c->params.tile, kWave)) {
+                k_iota<<<nblk(q, kThreads), kThreads, 0, s>>>(c->perm.as<int32_t>(), q);
+            } else {
+                e = kd_start(rq, c->kd_q, c->kd_work, P, c->qr.as<float>(), q,
+                             c->perm.as<int32_t>(), c->qr_s.as<float>(), s);
+                qr_s = c->qr_s.as<float>();
+            }
+        }
+        while (e == hipSuccess && !(rq.done && rg.done)) {
+            if (!rq.done) e = kd_step(rq);
+            if (e == hipSuccess && !rg.done) e = kd_step(rg);
+        }
+        if (forked) {
             const hipError_t ej = hipEventRecord(c->ev_join, c->side);
             if (e == hipSuccess) e = ej;
             if (e != hipSuccess) {
                 (void)hipStreamWaitEvent(s, c->ev_join, 0);
                 return e;
             }
-            g_sorted = true;
-        } else if (k > 0) {
-            k_iota<<<nblk(k, kThreads), kThreads, 0, s>>>(c->gperm.as<int32_t>(), k);
         }
-        if (q > 0) {
-            if (q <= std::min(c->params.tile, kWave))
-                k_iota<<<nblk(q, kThreads), kThreads, 0, s>>>(c->perm.as<int32_t>(), q);
-            else if ((e = kd_order(c->kd_q, c->kd_work, P, c->qr.as<float>(), q,
-                                   c->perm.as<int32_t>(), c->qr_s.as<float>(), s)) !=
-                     hipSuccess) {
-                if (forked) (void)hipStreamWaitEvent(s, c->ev_join, 0);
-                return e;
-            }
-            else
-                qr_s = c->qr_s.as<float>();
-        }
+        if (e != hipSuccess) return e;
         if (forked && (e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess) return e;
     }
     // Morton: queries: keys, sort -> perm

@@ -13,22 +13,26 @@
 // (n, leaf, sub), and the host lays them out level by level.
 //
 // Upper levels (nodes of more than kLocalMax points) run one level at a
-// time over all of the level's nodes, each node cut into slices of kSlice
-// points (one workgroup each):
-//   split    per node: the projection of largest extent, from the node's
-//            min / max (accumulated by the previous level's scatter; for
-//            the root by a pass over its slices)
-//   hist     per slice of kHistSlice points: histogram of one radix digit
-//            (11, 11, 10 bits of the order-preserving key) among the points
-//            that match the digits found so far, added into the node's
-//            histogram
-//   select   per node: the bin that holds the rank n_left; three rounds
-//            give the pivot key (the first point that goes right)
-//   count    per slice: points below / equal to the pivot
+// time over all of the level's nodes, each node cut into slices (one
+// workgroup each), in five launches:
+//   hist 0   per slice of kHistSlice points: the node's split projection
+//            (largest extent, from the node's min / max accumulated by the
+//            previous level's scatter; for the root by a pass over its
+//            slices), then the histogram of the first radix digit (11, 11,
+//            10 bits of the order-preserving key), added into the node's
+//            round-0 histogram
+//   hist 1,2 per slice: the bin of the previous round's histogram that holds
+//            the rank n_left (every workgroup of the node finds the same; the
+//            node's first records it), then the histogram of the next digit
+//            among the points that match the digits found so far
+//   count    per slice of kSlice points: the last digit's bin, which
+//            completes the pivot key (the first point that goes right); the
+//            points below / equal to it
 //   scatter  per slice: offsets from the node's earlier slices' counts,
 //            stable ranks by workgroup prefix sums in position order; index
-//            and projection values move to the next buffer, and the
-//            children's min / max are accumulated for the next split
+//            and projection values move to the next buffer, the children's
+//            min / max are accumulated for the next split, and the node's
+//            histograms are cleared for the next level
 // Nodes of at most kLocalMax points finish their whole subtree in one
 // workgroup each (k_kd_local): the order and the sort keys stay in LDS, and
 // every level of the subtree is one bitonic sort of (run, key, position)
@@ -117,18 +121,14 @@ __device__ __forceinline__ uint32_t wave_umax_dpp(uint32_t v)
     return v;
 }
 
-__global__ __launch_bounds__(kThreads) void k_kd_zero(int32_t *__restrict__ p, int64_t n)
+// Clears the histograms; resets the root's min / max key slots (P
+// projections) to their identities.
+__global__ __launch_bounds__(kThreads) void k_kd_zero(int32_t *__restrict__ p, int64_t n,
+                                                      uint32_t *__restrict__ ext, int P)
 {
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i < n) p[i] = 0;
-}
-
-// min / max key slots of `count` (node, projection) pairs to their identities
-__global__ __launch_bounds__(kThreads) void k_kd_ext_reset(uint32_t *__restrict__ ext,
-                                                           int64_t count)
-{
-    const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (i < count) {
+    if (i < P) {
         ext[2 * i + 0] = 0xffffffffu;
         ext[2 * i + 1] = 0u;
     }
@@ -195,47 +195,6 @@ __global__ __launch_bounds__(kThreads) void k_kd_root_ext(const int64_t *__restr
     block_merge_ext<PMAX>(kmin, kmax, P, ext, 0);
 }
 
-// One thread per node: the split projection; resets the children's min /
-// max slots (filled by this level's scatter) when the next level has them.
-__global__ __launch_bounds__(kThreads) void k_kd_split(const int64_t *__restrict__ nodes,
-                                                       int64_t nnodes, int P,
-                                                       const uint32_t *__restrict__ ext,
-                                                       uint32_t *__restrict__ ext_next,
-                                                       int32_t *__restrict__ dim,
-                                                       uint32_t *__restrict__ prefix,
-                                                       int64_t *__restrict__ rank)
-{
-    const int64_t nd = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (nd >= nnodes) return;
-    const int64_t *row = nodes + nd * kNodeCols;
-    const int64_t nleft = row[2];
-    if (nleft < 0) {
-        dim[nd] = -1;
-        return;
-    }
-    int best = 0;
-    float best_ext = 0.0f;
-    for (int j = 0; j < P; ++j) {
-        const float mn = from_orderable(ext[(nd * P + j) * 2 + 0]);
-        const float mx = from_orderable(ext[(nd * P + j) * 2 + 1]);
-        const float e = mx - mn;
-        if (j == 0 || e > best_ext) {
-            best = j;
-            best_ext = e;
-        }
-    }
-    dim[nd] = best;
-    prefix[nd] = 0u;
-    rank[nd] = nleft;
-    const int64_t ch = row[5];
-    if (ext_next && ch >= 0) {
-        for (int j = 0; j < 2 * P; ++j) {   // both children's P slots
-            ext_next[(ch * P + j) * 2 + 0] = 0xffffffffu;
-            ext_next[(ch * P + j) * 2 + 1] = 0u;
-        }
-    }
-}
-
 // Block exclusive scan of one int64 per thread (THREADS threads).
 template <int THREADS = kThreads>
 __device__ int64_t block_exscan(int64_t v, int64_t *total)
@@ -261,24 +220,108 @@ __device__ int64_t block_exscan(int64_t v, int64_t *total)
     return before + inc - v;
 }
 
-// Per slice of kHistSlice points: histogram of one digit among the points
-// that match the digits found so far, added into the node's histogram
-// (integer atomics: the sum does not depend on their order).
+// One round of the radix selection, by a whole workgroup: the bin of the
+// node's histogram h (2^width bins, of the points matching `pre`) that holds
+// rank r; returns the extended prefix and the rank inside that bin.
+template <int THREADS>
+__device__ void block_select(const int32_t *__restrict__ h, int width, uint32_t pre, int64_t r,
+                             uint32_t *out_pre, int64_t *out_rank)
+{
+    __shared__ uint32_t s_pre;
+    __shared__ int64_t s_rank;
+    constexpr int kMaxPer = kBins / THREADS;
+    const int per = (1 << width) / THREADS;
+    int32_t cnt[kMaxPer];
+    int64_t mine = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
+        cnt[i] = i < per ? h[threadIdx.x * per + i] : 0;
+        mine += cnt[i];
+    }
+    int64_t tot;
+    int64_t cum = block_exscan<THREADS>(mine, &tot);
+#pragma unroll
+    for (int i = 0; i < kMaxPer; ++i) {
+        if (i < per && r >= cum && r < cum + cnt[i]) {
+            s_pre = (pre << width) | uint32_t(threadIdx.x * per + i);
+            s_rank = r - cum;
+        }
+        cum += cnt[i];
+    }
+    __syncthreads();
+    *out_pre = s_pre;
+    *out_rank = s_rank;
+}
+
+// Per slice of kHistSlice points, one round of the radix selection of the
+// node's pivot.  Round 0 first picks the node's split projection (its
+// first slice records it and resets the children's min / max slots);
+// rounds 1 and 2 first finish the previous round (its first slice records
+// the prefix and rank).  The histogram of the round's digit among the
+// points that match the prefix is added into the node's histogram of the
+// round (integer atomics: the sum does not depend on their order).
+// sel_pre / sel_rank: 3 x max_nodes, the state after rounds 0, 1, 2.
 __global__ __launch_bounds__(kHistThreads) void k_kd_hist(
-    const int64_t *__restrict__ slices, int64_t node0, int64_t n, int round,
-    const float *__restrict__ vin, const int32_t *__restrict__ dim,
-    const uint32_t *__restrict__ prefix, int32_t *__restrict__ node_hist)
+    const int64_t *__restrict__ nodes, const int64_t *__restrict__ slices, int64_t node0,
+    int64_t hslice0, int64_t max_nodes, int64_t n, int P, int round,
+    const float *__restrict__ vin, const uint32_t *__restrict__ ext,
+    uint32_t *__restrict__ ext_next, int32_t *__restrict__ dim, uint32_t *__restrict__ sel_pre,
+    int64_t *__restrict__ sel_rank, int32_t *__restrict__ hist)
 {
     __shared__ int h[kBins];
+    __shared__ float s_ext[32];
+    __shared__ int s_dim;
     const int64_t sl = blockIdx.x;
     const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
     const int64_t nd = slices[sl * kSliceCols + 2] - node0;
-    const int d = dim[nd];
-    if (d < 0) return;   // uniform over the workgroup
+    const int64_t *row = nodes + nd * kNodeCols;
+    const int64_t nleft = row[2];
+    const bool first = sl + hslice0 == row[6];
+    if (nleft < 0) {   // a leaf (uniform over the workgroup)
+        if (round == 0 && first && threadIdx.x == 0) dim[nd] = -1;
+        return;
+    }
+    uint32_t pre = 0u;
+    int d;
+    if (round == 0) {
+        // the projection of largest extent, the first on ties
+        if (int(threadIdx.x) < P) {
+            const int j = threadIdx.x;
+            s_ext[j] = from_orderable(ext[(nd * P + j) * 2 + 1]) -
+                       from_orderable(ext[(nd * P + j) * 2 + 0]);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int best = 0;
+            for (int j = 1; j < P; ++j)
+                if (s_ext[j] > s_ext[best]) best = j;
+            s_dim = best;
+        }
+        __syncthreads();
+        d = s_dim;
+        if (first) {
+            if (threadIdx.x == 0) dim[nd] = d;
+            const int64_t ch = row[5];
+            if (ext_next && ch >= 0 && int(threadIdx.x) < 2 * P) {   // both children's slots
+                ext_next[(ch * P + threadIdx.x) * 2 + 0] = 0xffffffffu;
+                ext_next[(ch * P + threadIdx.x) * 2 + 1] = 0u;
+            }
+        }
+    } else {
+        d = dim[nd];
+        const uint32_t p0 = round == 1 ? 0u : sel_pre[nd];
+        const int64_t r0 = round == 1 ? nleft : sel_rank[nd];
+        int64_t r1;
+        block_select<kHistThreads>(hist + ((round - 1) * max_nodes + nd) * kBins,
+                                   kWidth[round - 1], p0, r0, &pre, &r1);
+        if (first && threadIdx.x == 0) {
+            sel_pre[(round - 1) * max_nodes + nd] = pre;
+            sel_rank[(round - 1) * max_nodes + nd] = r1;
+        }
+    }
     for (int b = threadIdx.x; b < kBins; b += kHistThreads) h[b] = 0;
     __syncthreads();
     const int shift = kShift[round], width = kWidth[round];
-    const uint32_t pre = prefix[nd];
     const uint32_t mask = (1u << width) - 1u;
 #pragma unroll 8
     for (int64_t i = threadIdx.x; i < len; i += kHistThreads) {
@@ -287,59 +330,34 @@ __global__ __launch_bounds__(kHistThreads) void k_kd_hist(
         if (match) atomicAdd(&h[(key >> shift) & mask], 1);
     }
     __syncthreads();
-    int32_t *nh = node_hist + nd * kBins;
+    int32_t *nh = hist + (round * max_nodes + nd) * kBins;
     for (int b = threadIdx.x; b < kBins; b += kHistThreads)
         if (h[b]) atomicAdd(&nh[b], h[b]);
 }
 
-// One workgroup per node: the bin of the node's histogram that holds the
-// rank; clears the bins it read for the next round.
-__global__ __launch_bounds__(kThreads) void k_kd_select(int round,
-                                                        int32_t *__restrict__ node_hist,
-                                                        const int32_t *__restrict__ dim,
-                                                        uint32_t *__restrict__ prefix,
-                                                        int64_t *__restrict__ rank)
-{
-    const int64_t nd = blockIdx.x;
-    if (dim[nd] < 0) return;   // uniform: the whole block returns
-    // read before the scan's barriers: one thread rewrites them below
-    const int64_t r = rank[nd];
-    const uint32_t pre = prefix[nd];
-    const int width = kWidth[round];
-    const int per = (1 << width) / kThreads;   // 8 or 4
-    int32_t *h = node_hist + nd * kBins + threadIdx.x * per;
-    int64_t cnt[kBins / kThreads];
-    int64_t mine = 0;
-    for (int i = 0; i < per; ++i) {
-        cnt[i] = h[i];
-        h[i] = 0;
-        mine += cnt[i];
-    }
-    int64_t tot;
-    int64_t cum = block_exscan(mine, &tot);
-    for (int i = 0; i < per; ++i) {
-        if (r >= cum && r < cum + cnt[i]) {
-            prefix[nd] = (pre << width) | uint32_t(threadIdx.x * per + i);
-            rank[nd] = r - cum;
-        }
-        cum += cnt[i];
-    }
-}
-
-__global__ __launch_bounds__(kThreads) void k_kd_count(const int64_t *__restrict__ slices,
-                                                       int64_t node0, int64_t n,
-                                                       const float *__restrict__ vin,
-                                                       const int32_t *__restrict__ dim,
-                                                       const uint32_t *__restrict__ prefix,
-                                                       int64_t *__restrict__ cnt)
+// Per slice of kSlice points: the last round of the selection (the node's
+// first slice records the pivot key and the number of pivot-equal points
+// that go left), then the slice's points below and equal to the pivot.
+__global__ __launch_bounds__(kThreads) void k_kd_count(
+    const int64_t *__restrict__ nodes, const int64_t *__restrict__ slices, int64_t node0,
+    int64_t slice0, int64_t max_nodes, int64_t n, const float *__restrict__ vin,
+    const int32_t *__restrict__ dim, uint32_t *__restrict__ sel_pre,
+    int64_t *__restrict__ sel_rank, const int32_t *__restrict__ hist, int64_t *__restrict__ cnt)
 {
     const int64_t sl = blockIdx.x;
     const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
     const int64_t nd = slices[sl * kSliceCols + 2] - node0;
     const int d = dim[nd];
     int64_t less = 0, eq = 0;
-    if (d >= 0) {
-        const uint32_t pivot = prefix[nd];
+    if (d >= 0) {   // uniform
+        uint32_t pivot;
+        int64_t r;
+        block_select<kThreads>(hist + (2 * max_nodes + nd) * kBins, kWidth[2],
+                               sel_pre[max_nodes + nd], sel_rank[max_nodes + nd], &pivot, &r);
+        if (sl + slice0 == nodes[nd * kNodeCols + 3] && threadIdx.x == 0) {
+            sel_pre[2 * max_nodes + nd] = pivot;
+            sel_rank[2 * max_nodes + nd] = r;
+        }
         for (int64_t i = threadIdx.x; i < len; i += kThreads) {
             const uint32_t key = orderable(vin[int64_t(d) * n + s0 + i]);
             less += key < pivot;
@@ -382,7 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_kd_scatter(
     const float *__restrict__ vin, const int32_t *__restrict__ dim,
     const uint32_t *__restrict__ prefix, const int64_t *__restrict__ rank,
     const int64_t *__restrict__ cnt, int32_t *__restrict__ idx_out, float *__restrict__ vout,
-    uint32_t *__restrict__ ext_next)
+    uint32_t *__restrict__ ext_next, int32_t *__restrict__ hist, int64_t max_nodes)
 {
     const int64_t sl = blockIdx.x;
     const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
@@ -402,6 +420,11 @@ __global__ __launch_bounds__(kThreads) void k_kd_scatter(
     }
     // points below the pivot, and equal to it, in the node's earlier slices
     const int64_t sb = row[3] - slice0;
+    if (sl == sb) {   // the node's histograms, clean for the next level
+        for (int r = 0; r < 3; ++r)
+            for (int b = threadIdx.x; b < kBins; b += kThreads)
+                hist[(r * max_nodes + nd) * kBins + b] = 0;
+    }
     int64_t l_mine = 0, e_mine = 0;
     for (int64_t s = sb + threadIdx.x; s < sl; s += kThreads) {
         l_mine += cnt[s * 2 + 0];
@@ -864,17 +887,28 @@ bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P)
     ok &= w.val[1].ensure(sizeof(float) * P * nn);
     ok &= w.ext[0].ensure(sizeof(uint32_t) * 2 * P * mn);
     ok &= w.ext[1].ensure(sizeof(uint32_t) * 2 * P * mn);
-    ok &= w.hist.ensure(sizeof(int32_t) * kBins * mn);
+    ok &= w.hist.ensure(sizeof(int32_t) * 3 * kBins * mn);
     ok &= w.cnt.ensure(sizeof(int64_t) * 2 * ms);
     ok &= w.dim.ensure(sizeof(int32_t) * mn);
-    ok &= w.prefix.ensure(sizeof(uint32_t) * mn);
-    ok &= w.rank.ensure(sizeof(int64_t) * mn);
+    ok &= w.prefix.ensure(sizeof(uint32_t) * 3 * mn);
+    ok &= w.rank.ensure(sizeof(int64_t) * 3 * mn);
     return ok;
 }
 
-hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
+hipError_t kd_start(KdRun &r, const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
                     int32_t *perm, float *vals_sorted, hipStream_t s)
 {
+    r = KdRun{};
+    r.pl = &pl;
+    r.w = &w;
+    r.P = P;
+    r.vals = vals;
+    r.n = n;
+    r.perm = perm;
+    r.vals_sorted = vals_sorted;
+    r.s = s;
+    r.vin = vals;
+    r.done = n == 0;
     if (n == 0) return hipSuccess;
     const int64_t mn = std::max<int64_t>(pl.max_nodes, 1), ms = std::max<int64_t>(pl.max_slices, 1);
     if (pl.n != n || (pl.levels.empty() && !pl.has_local) || P < 1 || P > 32 ||
@@ -883,13 +917,25 @@ hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64
         w.val[1].cap < sizeof(float) * P * size_t(n) ||
         w.ext[0].cap < sizeof(uint32_t) * 2 * P * size_t(mn) ||
         w.ext[1].cap < sizeof(uint32_t) * 2 * P * size_t(mn) ||
-        w.hist.cap < sizeof(int32_t) * kBins * size_t(mn) ||
+        w.hist.cap < sizeof(int32_t) * 3 * kBins * size_t(mn) ||
         w.cnt.cap < sizeof(int64_t) * 2 * size_t(ms) || w.dim.cap < sizeof(int32_t) * size_t(mn) ||
-        w.prefix.cap < sizeof(uint32_t) * size_t(mn) || w.rank.cap < sizeof(int64_t) * size_t(mn))
+        w.prefix.cap < sizeof(uint32_t) * 3 * size_t(mn) ||
+        w.rank.cap < sizeof(int64_t) * 3 * size_t(mn)) {
+        r.done = true;
         return hipErrorInvalidValue;
-    const int32_t *idx_in = nullptr;   // level 0 reads the identity order
-    const float *vin = vals;
-    int cur = 0;
+    }
+    return hipSuccess;
+}
+
+hipError_t kd_step(KdRun &r)
+{
+    if (r.done) return hipSuccess;
+    const KdPlan &pl = *r.pl;
+    KdWork &w = *r.w;
+    const int P = r.P;
+    const int64_t n = r.n;
+    const hipStream_t s = r.s;
+    const int64_t mn = std::max<int64_t>(pl.max_nodes, 1);
     const int64_t *nodes = pl.node_tab.as<int64_t>();
     const int64_t *slices = pl.slice_tab.as<int64_t>();
     int32_t *hist = w.hist.as<int32_t>();
@@ -897,65 +943,79 @@ hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64
     uint32_t *prefix = w.prefix.as<uint32_t>();
     int64_t *rank = w.rank.as<int64_t>();
     int64_t *cnt = w.cnt.as<int64_t>();
-    if (!pl.levels.empty()) {
-        k_kd_zero<<<nb(kBins * mn, kThreads), kThreads, 0, s>>>(hist, kBins * mn);
-        k_kd_ext_reset<<<nb(P, kThreads), kThreads, 0, s>>>(w.ext[0].as<uint32_t>(), P);
+    const size_t nlev = pl.levels.size();
+    const size_t phase = r.phase++;
+    if (phase == 0) {   // the root's extents
+        if (nlev == 0) return hipSuccess;
+        k_kd_zero<<<nb(3 * kBins * mn, kThreads), kThreads, 0, s>>>(hist, 3 * kBins * mn,
+                                                                    w.ext[0].as<uint32_t>(), P);
         const KdLevel &lv = pl.levels[0];
         const int64_t *st = slices + lv.slice0 * kSliceCols;
         if (P <= 16)
             k_kd_root_ext<16><<<unsigned(lv.slice1 - lv.slice0), kThreads, 0, s>>>(
-                st, n, P, vals, w.ext[0].as<uint32_t>());
+                st, n, P, r.vals, w.ext[0].as<uint32_t>());
         else
             k_kd_root_ext<32><<<unsigned(lv.slice1 - lv.slice0), kThreads, 0, s>>>(
-                st, n, P, vals, w.ext[0].as<uint32_t>());
+                st, n, P, r.vals, w.ext[0].as<uint32_t>());
+        return hipGetLastError();
     }
-    for (size_t li = 0; li < pl.levels.size(); ++li) {
+    if (phase <= nlev) {   // upper level phase - 1
+        const size_t li = phase - 1;
         const KdLevel &lv = pl.levels[li];
-        const int64_t nn = lv.node1 - lv.node0, ns = lv.slice1 - lv.slice0;
+        const int64_t ns = lv.slice1 - lv.slice0;
         const int64_t *nt = nodes + lv.node0 * kNodeCols;
         const int64_t *st = slices + lv.slice0 * kSliceCols;
         uint32_t *ext = w.ext[li & 1].as<uint32_t>();
-        uint32_t *ext_next = (li + 1 < pl.levels.size()) ? w.ext[(li + 1) & 1].as<uint32_t>()
-                                                          : nullptr;
-        k_kd_split<<<nb(nn, kThreads), kThreads, 0, s>>>(nt, nn, P, ext, ext_next, dim, prefix,
-                                                          rank);
+        uint32_t *ext_next = (li + 1 < nlev) ? w.ext[(li + 1) & 1].as<uint32_t>() : nullptr;
         const int64_t *hst = slices + lv.hslice0 * kSliceCols;
         const unsigned nhs = unsigned(lv.hslice1 - lv.hslice0);
-        for (int r = 0; r < 3; ++r) {
-            k_kd_hist<<<nhs, kHistThreads, 0, s>>>(hst, lv.node0, n, r, vin, dim, prefix, hist);
-            k_kd_select<<<unsigned(nn), kThreads, 0, s>>>(r, hist, dim, prefix, rank);
-        }
-        k_kd_count<<<unsigned(ns), kThreads, 0, s>>>(st, lv.node0, n, vin, dim, prefix, cnt);
-        int32_t *idx_out = w.idx[cur].as<int32_t>();
-        float *vout = w.val[cur].as<float>();
+        for (int rd = 0; rd < 3; ++rd)
+            k_kd_hist<<<nhs, kHistThreads, 0, s>>>(nt, hst, lv.node0, lv.hslice0, mn, n, P, rd,
+                                                   r.vin, ext, ext_next, dim, prefix, rank, hist);
+        k_kd_count<<<unsigned(ns), kThreads, 0, s>>>(nt, st, lv.node0, lv.slice0, mn, n, r.vin,
+                                                     dim, prefix, rank, hist, cnt);
+        int32_t *idx_out = w.idx[r.cur].as<int32_t>();
+        float *vout = w.val[r.cur].as<float>();
         if (P <= 16)
-            k_kd_scatter<16><<<unsigned(ns), kThreads, 0, s>>>(nt, st, lv.node0, lv.slice0, n, P,
-                                                               idx_in, vin, dim, prefix, rank,
-                                                               cnt, idx_out, vout, ext_next);
+            k_kd_scatter<16><<<unsigned(ns), kThreads, 0, s>>>(
+                nt, st, lv.node0, lv.slice0, n, P, r.idx_in, r.vin, dim, prefix + 2 * mn,
+                rank + 2 * mn, cnt, idx_out, vout, ext_next, hist, mn);
         else
-            k_kd_scatter<32><<<unsigned(ns), kThreads, 0, s>>>(nt, st, lv.node0, lv.slice0, n, P,
-                                                               idx_in, vin, dim, prefix, rank,
-                                                               cnt, idx_out, vout, ext_next);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        idx_in = idx_out;
-        vin = vout;
-        cur ^= 1;
+            k_kd_scatter<32><<<unsigned(ns), kThreads, 0, s>>>(
+                nt, st, lv.node0, lv.slice0, n, P, r.idx_in, r.vin, dim, prefix + 2 * mn,
+                rank + 2 * mn, cnt, idx_out, vout, ext_next, hist, mn);
+        r.idx_in = idx_out;
+        r.vin = vout;
+        r.cur ^= 1;
+        return hipGetLastError();
     }
+    // the subtrees, or the order out as it stands
+    r.done = true;
     if (pl.has_local) {
         const int64_t *nt = nodes + pl.local.node0 * kNodeCols;
         const unsigned nl = unsigned(pl.local.node1 - pl.local.node0);
         if (P <= 16)
-            k_kd_local<16><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, idx_in, vin,
-                                                        perm, vals_sorted);
+            k_kd_local<16><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, r.idx_in,
+                                                        r.vin, r.perm, r.vals_sorted);
         else
-            k_kd_local<32><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, idx_in, vin,
-                                                        perm, vals_sorted);
+            k_kd_local<32><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, r.idx_in,
+                                                        r.vin, r.perm, r.vals_sorted);
         return hipGetLastError();
     }
-    hipError_t e = hipMemcpyAsync(perm, idx_in, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
-    if (e == hipSuccess && vals_sorted)
-        e = hipMemcpyAsync(vals_sorted, vin, sizeof(float) * P * n, hipMemcpyDeviceToDevice, s);
+    hipError_t e =
+        hipMemcpyAsync(r.perm, r.idx_in, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess && r.vals_sorted)
+        e = hipMemcpyAsync(r.vals_sorted, r.vin, sizeof(float) * P * n, hipMemcpyDeviceToDevice,
+                           s);
+    return e;
+}
+
+hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
+                    int32_t *perm, float *vals_sorted, hipStream_t s)
+{
+    KdRun r;
+    hipError_t e = kd_start(r, pl, w, P, vals, n, perm, vals_sorted, s);
+    while (e == hipSuccess && !r.done) e = kd_step(r);
     return e;
 }
 

@@ -79,6 +79,27 @@ bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P);
 // one split (n > sub).
 hipError_t kd_order(const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
                     int32_t *perm, float *vals_sorted, hipStream_t s);
+// The same, enqueued phase by phase (the root, each upper level, the
+// subtrees), so that two orders on two streams can be enqueued alternately:
+// kd_start checks the buffers, each kd_step enqueues one phase until done.
+struct KdRun {
+    const KdPlan *pl = nullptr;
+    KdWork *w = nullptr;
+    int P = 0;
+    const float *vals = nullptr;
+    int64_t n = 0;
+    int32_t *perm = nullptr;
+    float *vals_sorted = nullptr;
+    hipStream_t s = nullptr;
+    size_t phase = 0;
+    const int32_t *idx_in = nullptr;   // null: the identity order
+    const float *vin = nullptr;
+    int cur = 0;
+    bool done = true;
+};
+hipError_t kd_start(KdRun &r, const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
+                    int32_t *perm, float *vals_sorted, hipStream_t s);
+hipError_t kd_step(KdRun &r);
 
 }  // namespace ngd
 
