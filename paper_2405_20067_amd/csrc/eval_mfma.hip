@@ -1,5 +1,5 @@
 // Culled forward with a matrix-core filter: the Mahalanobis distance of
-// every (query, candidate) pair of a work item as one BF16 MFMA contraction
+// every (query, candidate) pair of a tile as one BF16 MFMA contraction
 // of quadratic query features against per-Gaussian quadratic coefficients.
 //
 // The quadratic form (Sec. 3.1, Eq. 1-2, in exp2 units, S' = sqrt(log2(e)/2)
@@ -34,10 +34,11 @@
 // (float64 P', then bf16 hi / lo), the centre of every tile's query box, and
 // for every candidate entry (tile, Gaussian) the centred constant and linear
 // coefficients and bound terms -- one thread per entry.
-// Filter kernel, one workgroup per work item (up to 256 queries in 4 waves):
+// Filter kernel, one workgroup per tile (up to 256 queries in 4 waves):
 // per wave the query features as MFMA A fragments (rows = queries, 2 blocks
 // of 32); the entries' B fragments staged in LDS in double-buffered chunks of
-// 64 (the next chunk loaded while the current one is computed); per block of
+// 64 (the next chunk loaded straight into LDS while the current one is
+// computed); per block of
 // 32 entries 3 x KS x 2 MFMAs and the certified group test; the (entry,
 // group) flag records whether the pair may contribute.  The
 // float32 items kernel then evaluates only the flagged pairs (eval.hip).
@@ -271,21 +272,23 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
     int64_t q, int tile, const bf16x8 *__restrict__ mrec, const bf16x8 *__restrict__ eb0,
     const float4 *__restrict__ ebnd, const float *__restrict__ tcen,
     const float *__restrict__ qs, const int64_t *__restrict__ tile_off,
-    const int32_t *__restrict__ cand, const int32_t *__restrict__ item_tile,
-    const int64_t *__restrict__ item_off, float skip, uint8_t *__restrict__ act,
+    const int32_t *__restrict__ cand, float skip, uint8_t *__restrict__ act,
     unsigned long long *__restrict__ stats)
 {
     using Fe = Feat<N>;
     constexpr int KS = Fe::KS, KQ = Fe::KQ;
-    __shared__ bf16x8 s_b[2][kCh][KS][2][2];   // buffer, entry, k-step, half, {hi, lo}
-    __shared__ float4 s_bd[2][kCh];           // |a'|, |b'|_1, |m'|_1, R'
+    // per buffer: kCh entries of kSlots 16-byte slots (unit r = (k-step * 2
+    // + half) * 2 + {hi, lo}, then one slot of padding, so that 8 and 16
+    // consecutive entries fall on distinct bank groups), then the entries'
+    // bound terms |a'|, |b'|_1, |m'|_1, R'
+    constexpr int kSlots = KS * 4 + 1;
+    constexpr int kBufSlots = kCh * kSlots + kCh;
+    __shared__ bf16x8 s_lds[2][kBufSlots];
 
-    const int64_t it = blockIdx.x;
-    const int64_t t = uniform(item_tile[it]);
-    const int64_t i0 = uniform64(item_off[t]);
-    const int64_t c0 = uniform64(tile_off[t]), c1 = uniform64(tile_off[t + 1]);
-    const int64_t e0 = c0 + (it - i0) * kItemCands;
-    const int64_t e1 = (e0 + kItemCands < c1) ? e0 + kItemCands : c1;
+    // one workgroup per tile (and part of a tile of more than 256 queries):
+    // the query features are formed once for all of the tile's candidates
+    const int64_t t = blockIdx.x;
+    const int64_t e0 = uniform64(tile_off[t]), e1 = uniform64(tile_off[t + 1]);
 
     const int lane = lane_id(), w = int(threadIdx.x) / kWave, h = lane / 32;
     const int s = int(blockIdx.y) * kMThreads + int(threadIdx.x);
@@ -295,12 +298,31 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
 #pragma unroll
     for (int a = 0; a < N; ++a) cen[a] = tcen[t * N + a];
 
+    // The coordinates this lane needs, loaded first and all together (from
+    // a valid row, the tile's first, where a row is past the tile's end):
+    // its own query's (the wave's half-widths) and its row of each of the
+    // two A row blocks.
+    float xo[N], xb[2][N];
+    bool vrow[2];
+    {
+        const int64_t pc = valid ? p : t * tile;
+#pragma unroll
+        for (int a = 0; a < N; ++a) xo[a] = qs[a * q + pc];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            const int sr = w * kWave + int(blockIdx.y) * kMThreads + rb * 32 + (lane % 32);
+            const int64_t pr = t * tile + sr;
+            vrow[rb] = (sr < tile) && (pr < q);
+            const int64_t prc = vrow[rb] ? pr : t * tile;
+#pragma unroll
+            for (int a = 0; a < N; ++a) xb[rb][a] = qs[a * q + prc];
+        }
+    }
     // this wave's half-widths about the centre
     float h2 = 0.0f, hm = 0.0f;
 #pragma unroll
     for (int a = 0; a < N; ++a) {
-        const float xa = valid ? qs[a * q + p] : 0.0f;
-        const float ha = wave_max(valid ? fabsf(xa - cen[a]) : 0.0f);
+        const float ha = wave_max_nonneg(valid ? fabsf(xo[a] - cen[a]) : 0.0f);
         h2 = fmaf(ha, ha, h2);
         hm = fmaxf(hm, ha);
     }
@@ -312,12 +334,10 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
     bf16x8 ahi[2][KS], alo[2][KS];
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
-        const int sr = w * kWave + int(blockIdx.y) * kMThreads + rb * 32 + (lane % 32);
-        const int64_t pr = t * tile + sr;
-        const bool vr = (sr < tile) && (pr < q);
+        const bool vr = vrow[rb];
         float xr[N];
 #pragma unroll
-        for (int a = 0; a < N; ++a) xr[a] = vr ? qs[a * q + pr] - cen[a] : 0.0f;
+        for (int a = 0; a < N; ++a) xr[a] = vr ? xb[rb][a] - cen[a] : 0.0f;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             float f[16];
@@ -362,91 +382,51 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
     unsigned long long n_exam = 0, n_pass = 0;
 
     // Chunks of kCh entries staged in LDS, double-buffered: the workgroup
-    // loads chunk c + 1 (each thread a few 16-byte units, every unit once)
-    // while it computes chunk c, then stores it and meets at one barrier.
-    constexpr int kUnits = kCh * KS * 4;   // 16-byte B-fragment units per chunk
-    constexpr int kStage = (kUnits + kCh + kMThreads - 1) / kMThreads;
+    // issues the loads of chunk c + 1 straight into LDS (global_load_lds,
+    // 16 bytes per lane, lane l of a wave to slot M0 + l) while it computes
+    // chunk c, then waits for them and meets at one barrier.
     const int nthr = int(blockDim.x);
-    bf16x8 stage[kStage];
-    auto load_chunk = [&](int64_t ch) {
-        // the chunk's Gaussian positions: one coalesced load per wave, then
-        // handed to the lanes that need them by lane permutes (so the record
-        // loads below do not each wait for a load of their own index)
-        const int cv = (ch + lane < e1) ? cand[ch + lane] : 0;
-        int spk[kStage];
-#pragma unroll
-        for (int k = 0; k < kStage; ++k) {
-            const int u = int(threadIdx.x) + k * nthr;
-            const int j = u < kUnits ? u / (KS * 4) : u - kUnits;
-            spk[k] = __shfl(cv, j & (kWave - 1), kWave);
-        }
-#pragma unroll
-        for (int k = 0; k < kStage; ++k) {
-            const int u = int(threadIdx.x) + k * nthr;
-            if (k * nthr >= kUnits + kCh) break;
+    // cv: the chunk's Gaussian positions, one coalesced load per wave made a
+    // chunk ahead, handed to the lanes that need them by lane permutes
+    auto load_chunk = [&](int buf, int64_t ch, int cv) {
+        for (int base = 0; base < kBufSlots; base += nthr) {
+            const int wbase = base + w * kWave;   // this wave's first slot
+            if (wbase >= kBufSlots) break;        // uniform over the wave
+            const int sl = wbase + lane;
             int j, r;
-            if (u < kUnits) {
-                j = u / (KS * 4);
-                r = u % (KS * 4);
+            if (sl < kCh * kSlots) {
+                j = sl / kSlots;
+                r = sl - j * kSlots;
             } else {
-                j = u - kUnits;
+                j = sl - kCh * kSlots;
                 r = -1;
             }
+            const int sp = __shfl(cv, j & (kWave - 1), kWave);
             const int64_t e = ch + j;
-            if (u < kUnits + kCh && e < e1) {
+            if (sl < kBufSlots && r < kSlots - 1 && e < e1) {
+                const bf16x8 *src;
                 if (r < 0)
-                    stage[k] = *reinterpret_cast<const bf16x8 *>(ebnd + e);
+                    src = reinterpret_cast<const bf16x8 *>(ebnd + e);
                 else if (r < 4)
-                    stage[k] = eb0[e * 4 + r];
+                    src = eb0 + e * 4 + r;
                 else
-                    stage[k] = mrec[int64_t(spk[k]) * (KQ * 4) + (r - 4)];
+                    src = mrec + int64_t(sp) * (KQ * 4) + (r - 4);
+                __builtin_amdgcn_global_load_lds(
+                    (const __attribute__((address_space(1))) void *)(src),
+                    (__attribute__((address_space(3))) void *)(&s_lds[buf][wbase]), 16, 0, 0);
             }
         }
     };
-    auto store_chunk = [&](int buf, int64_t ch) {
-#pragma unroll
-        for (int k = 0; k < kStage; ++k) {
-            const int u = int(threadIdx.x) + k * nthr;
-            if (k * nthr >= kUnits + kCh) break;
-            if (u >= kUnits + kCh) continue;
-            const int j = u < kUnits ? u / (KS * 4) : u - kUnits;
-            if (ch + j >= e1) continue;
-            if (u < kUnits)
-                (&s_b[buf][0][0][0][0])[u] = stage[k];
-            else
-                s_bd[buf][j] = *reinterpret_cast<const float4 *>(&stage[k]);
-        }
-    };
-    // smaller workgroups (tiles of fewer than 256 queries) stage each chunk
-    // synchronously, every thread copying as many units as it takes
-    const bool piped = nthr == kMThreads;
-    auto copy_chunk = [&](int buf, int64_t ch) {
-        for (int u = int(threadIdx.x); u < kUnits + kCh; u += nthr) {
-            const int j = u < kUnits ? u / (KS * 4) : u - kUnits;
-            const int r = u < kUnits ? u % (KS * 4) : -1;
-            const int64_t e = ch + j;
-            if (e >= e1) continue;
-            if (r < 0)
-                s_bd[buf][j] = ebnd[e];
-            else if (r < 4)
-                (&s_b[buf][0][0][0][0])[u] = eb0[e * 4 + r];
-            else
-                (&s_b[buf][0][0][0][0])[u] = mrec[int64_t(cand[e]) * (KQ * 4) + (r - 4)];
-        }
-    };
-    if (e0 < e1) {
-        if (piped) {
-            load_chunk(e0);
-            store_chunk(0, e0);
-        } else {
-            copy_chunk(0, e0);
-        }
-    }
+    auto cand_of = [&](int64_t ch) { return (ch + lane < e1) ? cand[ch + lane] : 0; };
+    if (e0 < e1) load_chunk(0, e0, cand_of(e0));
+    int cv_next = cand_of(e0 + kCh);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     int buf = 0;
     for (int64_t ch = e0; ch < e1; ch += kCh) {
         const bool more = ch + kCh < e1;
-        if (more && piped) load_chunk(ch + kCh);
+        if (more) load_chunk(buf ^ 1, ch + kCh, cv_next);
+        cv_next = cand_of(ch + 2 * kCh);
         const int n = int((e1 - ch < kCh) ? e1 - ch : kCh);
         for (int cb = 0; cb < n; cb += 32) {
             const int jl = cb + (lane % 32);
@@ -455,10 +435,11 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
             bf16x8 bhi[KS], blo[KS];
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                bhi[ks] = s_b[buf][jc][ks][h][0];
-                blo[ks] = s_b[buf][jc][ks][h][1];
+                bhi[ks] = s_lds[buf][jc * kSlots + (ks * 2 + h) * 2 + 0];
+                blo[ks] = s_lds[buf][jc * kSlots + (ks * 2 + h) * 2 + 1];
             }
-            const float4 bd = s_bd[buf][jc];
+            const bf16x8 bdv = s_lds[buf][kCh * kSlots + jc];
+            const float4 bd = *reinterpret_cast<const float4 *>(&bdv);
             f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
@@ -499,12 +480,8 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
                 act[(ch + jl) * ngroups + grp] =
                     uint8_t(((bal >> lane) | (bal >> (lane + 32))) & 1u);
         }
-        if (more) {
-            if (piped)
-                store_chunk(buf ^ 1, ch + kCh);
-            else
-                copy_chunk(buf ^ 1, ch + kCh);
-        }
+        // the next chunk in LDS, and every wave done with this one
+        __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         buf ^= 1;
     }
@@ -541,13 +518,12 @@ hipError_t mfma_n(const ngd_mixture *mix, ngd_cull *c, float *out, unsigned long
         c->mrec_seq = c->build_seq;
     }
     if (c->nitems > 0) {
-        const dim3 grid(unsigned(c->nitems), gy);
+        const dim3 grid(unsigned(c->ntiles), gy);
         auto go = [&](auto kern, unsigned long long *st) {
             kern<<<grid, per, 0, s>>>(c->q, tile, c->mrec.as<bf16x8>(), c->eb0.as<bf16x8>(),
                                       c->ebnd.as<float4>(), c->tcen.as<float>(),
                                       c->qs.as<float>(), c->tile_off.as<int64_t>(),
-                                      c->cand.as<int32_t>(), c->item_tile.as<int32_t>(),
-                                      c->item_off.as<int64_t>(), skip, c->act.as<uint8_t>(), st);
+                                      c->cand.as<int32_t>(), skip, c->act.as<uint8_t>(), st);
         };
         if (stats)
             go(k_mfma_filter<N, true>, stats);

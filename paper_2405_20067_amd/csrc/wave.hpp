@@ -62,6 +62,28 @@ __device__ __forceinline__ float wave_sum(float v)
     return v;
 }
 
+// Maximum over the wave of non-negative floats by DPP, the same in every
+// lane: the bit patterns of non-negative floats order as unsigned integers
+// as the floats do; a running max over row_shr 1, 2, 4, 8 and row_bcast 15,
+// 31 (lanes shifted in read 0, the identity) leaves the total in lane 63.
+template <int CTRL, int ROWS> __device__ __forceinline__ uint32_t dpp_umax(uint32_t x)
+{
+    const uint32_t y = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), CTRL, ROWS, 0xf, false));
+    return x > y ? x : y;
+}
+
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    uint32_t x = __float_as_uint(v);
+    x = dpp_umax<kDppRowShr1, 0xf>(x);
+    x = dpp_umax<kDppRowShr2, 0xf>(x);
+    x = dpp_umax<kDppRowShr4, 0xf>(x);
+    x = dpp_umax<kDppRowShr8, 0xf>(x);
+    x = dpp_umax<kDppRowBcast15, 0xa>(x);
+    x = dpp_umax<kDppRowBcast31, 0xc>(x);
+    return __uint_as_float(uint32_t(__builtin_amdgcn_readlane(int(x), 63)));
+}
+
 // Sum over the wave by DPP (no LDS traffic), valid in lane 63 only: the
 // inclusive-scan steps of wave_inclusive_scan on floats.  A fixed order, so
 // bitwise reproducible.
