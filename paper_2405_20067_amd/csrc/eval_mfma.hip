@@ -43,6 +43,7 @@
 // group) flag records whether the pair may contribute.  The
 // float32 items kernel then evaluates only the flagged pairs (eval.hip).
 #include <cmath>
+#include <type_traits>
 
 #include "eval_common.hpp"
 #include "ngd_internal.hpp"
@@ -277,12 +278,15 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
 {
     using Fe = Feat<N>;
     constexpr int KS = Fe::KS, KQ = Fe::KQ;
-    // per buffer: kCh entries of kSlots 16-byte slots (unit r = (k-step * 2
-    // + half) * 2 + {hi, lo}, then one slot of padding, so that 8 and 16
-    // consecutive entries fall on distinct bank groups), then the entries'
-    // bound terms |a'|, |b'|_1, |m'|_1, R'
-    constexpr int kSlots = KS * 4 + 1;
-    constexpr int kBufSlots = kCh * kSlots + kCh;
+    // Per buffer, three regions of 16-byte slots, each entry's units padded
+    // to an odd stride so that 8 and 16 consecutive entries fall on distinct
+    // bank groups: the k-step-0 units (half * 2 + {hi, lo}) of the entries,
+    // their quadratic units ((k-step - 1) * 2 + half) * 2 + {hi, lo}, and
+    // their bound terms |a'|, |b'|_1, |m'|_1, R' (consecutive).
+    constexpr int kMU = KQ * 4;                  // quadratic units per entry
+    constexpr int kStA = 5, kStB = kMU + 1;      // entry strides
+    constexpr int kOffB = kCh * kStA, kOffC = kOffB + kCh * kStB;
+    constexpr int kBufSlots = kOffC + kCh;
     __shared__ bf16x8 s_lds[2][kBufSlots];
 
     // one workgroup per tile (and part of a tile of more than 256 queries):
@@ -364,8 +368,10 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
             }
         }
     }
-    // all 64 queries of the group valid: no row masking in the group test
+    // all 64 queries of the group valid: no row masking in the group test;
+    // none valid (past the tile's end): the wave only loads and meets
     const bool full = ballot(valid) == ~uint64_t(0);
+    const bool live = ballot(valid) != 0;
     uint32_t rowvalid = 0;   // bit rb * 16 + r: accumulator element r of row block rb
 #pragma unroll
     for (int rb = 0; rb < 2; ++rb) {
@@ -385,37 +391,49 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
     // issues the loads of chunk c + 1 straight into LDS (global_load_lds,
     // 16 bytes per lane, lane l of a wave to slot M0 + l) while it computes
     // chunk c, then waits for them and meets at one barrier.
-    const int nthr = int(blockDim.x);
-    // cv: the chunk's Gaussian positions, one coalesced load per wave made a
-    // chunk ahead, handed to the lanes that need them by lane permutes
-    auto load_chunk = [&](int buf, int64_t ch, int cv) {
-        for (int base = 0; base < kBufSlots; base += nthr) {
-            const int wbase = base + w * kWave;   // this wave's first slot
-            if (wbase >= kBufSlots) break;        // uniform over the wave
+    // The workgroup is always kMThreads threads (waves whose rows are all
+    // past the tile's end only load and meet).  Each region is loaded in
+    // rounds of kMThreads slots, a wave's 64 lanes on 64 consecutive slots;
+    // a lane on a padding slot or an entry past the list's end loads
+    // nothing.
+    auto load_region = [&](auto region, int buf, int64_t ch, int nch, int cv) {
+        constexpr int R = decltype(region)::value;
+        constexpr int off = R == 0 ? 0 : (R == 1 ? kOffB : kOffC);
+        constexpr int len = R == 0 ? kCh * kStA : (R == 1 ? kCh * kStB : kCh);
+        constexpr int st = R == 0 ? kStA : (R == 1 ? kStB : 1);
+        constexpr int units = R == 0 ? 4 : (R == 1 ? kMU : 1);
+#pragma unroll
+        for (int k = 0; k < (len + kMThreads - 1) / kMThreads; ++k) {
+            const int wbase = k * kMThreads + w * kWave;   // this wave's first slot
+            if (wbase >= len) break;                       // uniform over the wave
             const int sl = wbase + lane;
-            int j, r;
-            if (sl < kCh * kSlots) {
-                j = sl / kSlots;
-                r = sl - j * kSlots;
+            const int j = sl / st, u = sl - j * st;
+            // a wave-uniform base and a 32-bit lane offset (in 16-byte units)
+            const bf16x8 *base;
+            uint32_t o;
+            if constexpr (R == 0) {
+                base = eb0 + ch * 4;
+                o = uint32_t(j * 4 + u);
+            } else if constexpr (R == 1) {
+                base = mrec;
+                o = uint32_t(__shfl(cv, j & (kWave - 1), kWave)) * kMU + uint32_t(u);
             } else {
-                j = sl - kCh * kSlots;
-                r = -1;
+                base = reinterpret_cast<const bf16x8 *>(ebnd + ch);
+                o = uint32_t(j);
             }
-            const int sp = __shfl(cv, j & (kWave - 1), kWave);
-            const int64_t e = ch + j;
-            if (sl < kBufSlots && r < kSlots - 1 && e < e1) {
-                const bf16x8 *src;
-                if (r < 0)
-                    src = reinterpret_cast<const bf16x8 *>(ebnd + e);
-                else if (r < 4)
-                    src = eb0 + e * 4 + r;
-                else
-                    src = mrec + int64_t(sp) * (KQ * 4) + (r - 4);
+            const bf16x8 *src = base + o;
+            if (sl < len && u < units && j < nch)
                 __builtin_amdgcn_global_load_lds(
                     (const __attribute__((address_space(1))) void *)(src),
-                    (__attribute__((address_space(3))) void *)(&s_lds[buf][wbase]), 16, 0, 0);
-            }
+                    (__attribute__((address_space(3))) void *)(&s_lds[buf][off + wbase]), 16, 0,
+                    0);
         }
+    };
+    auto load_chunk = [&](int buf, int64_t ch, int cv) {
+        const int nch = int((e1 - ch < kCh) ? e1 - ch : kCh);   // entries present
+        load_region(std::integral_constant<int, 0>{}, buf, ch, nch, cv);
+        load_region(std::integral_constant<int, 1>{}, buf, ch, nch, cv);
+        load_region(std::integral_constant<int, 2>{}, buf, ch, nch, cv);
     };
     auto cand_of = [&](int64_t ch) { return (ch + lane < e1) ? cand[ch + lane] : 0; };
     if (e0 < e1) load_chunk(0, e0, cand_of(e0));
@@ -428,17 +446,24 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
         if (more) load_chunk(buf ^ 1, ch + kCh, cv_next);
         cv_next = cand_of(ch + 2 * kCh);
         const int n = int((e1 - ch < kCh) ? e1 - ch : kCh);
-        for (int cb = 0; cb < n; cb += 32) {
+        if constexpr (COUNT) {
+            // a group past the tile's end counts its pairs as examined, as
+            // the float32 kernel does
+            if (!live) n_exam += uint64_t(n);
+        }
+        for (int cb = 0; live && cb < n; cb += 32) {
             const int jl = cb + (lane % 32);
             const bool jv = jl < n;
             const int jc = jv ? jl : cb;   // idle lanes: a valid row, column ignored
             bf16x8 bhi[KS], blo[KS];
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                bhi[ks] = s_lds[buf][jc * kSlots + (ks * 2 + h) * 2 + 0];
-                blo[ks] = s_lds[buf][jc * kSlots + (ks * 2 + h) * 2 + 1];
+                const int sl = ks == 0 ? jc * kStA + h * 2
+                                       : kOffB + jc * kStB + ((ks - 1) * 2 + h) * 2;
+                bhi[ks] = s_lds[buf][sl];
+                blo[ks] = s_lds[buf][sl + 1];
             }
-            const bf16x8 bdv = s_lds[buf][kCh * kSlots + jc];
+            const bf16x8 bdv = s_lds[buf][kOffC + jc];
             const float4 bd = *reinterpret_cast<const float4 *>(&bdv);
             f32x16 acc0 = {}, acc1 = {};
 #pragma unroll
@@ -498,7 +523,6 @@ hipError_t mfma_n(const ngd_mixture *mix, ngd_cull *c, float *out, unsigned long
                   hipStream_t s)
 {
     const int tile = c->params.tile;
-    const int per = tile < kMThreads ? (tile + 63) / 64 * 64 : kMThreads;
     const unsigned gy = unsigned((tile + kMThreads - 1) / kMThreads);
     const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
     hipError_t e;
@@ -520,7 +544,7 @@ hipError_t mfma_n(const ngd_mixture *mix, ngd_cull *c, float *out, unsigned long
     if (c->nitems > 0) {
         const dim3 grid(unsigned(c->ntiles), gy);
         auto go = [&](auto kern, unsigned long long *st) {
-            kern<<<grid, per, 0, s>>>(c->q, tile, c->mrec.as<bf16x8>(), c->eb0.as<bf16x8>(),
+            kern<<<grid, kMThreads, 0, s>>>(c->q, tile, c->mrec.as<bf16x8>(), c->eb0.as<bf16x8>(),
                                       c->ebnd.as<float4>(), c->tcen.as<float>(),
                                       c->qs.as<float>(), c->tile_off.as<int64_t>(),
                                       c->cand.as<int32_t>(), skip, c->act.as<uint8_t>(), st);
