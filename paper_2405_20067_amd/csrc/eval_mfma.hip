@@ -206,17 +206,37 @@ __global__ __launch_bounds__(256) void k_mfma_entry(int64_t total,
                                                     float4 *__restrict__ ebnd)
 {
     constexpr int R = RecLayout<N>::R;
-    const int64_t e = int64_t(blockIdx.x) * 256 + threadIdx.x;
-    if (e >= total) return;
-    const int sp = cand[e];
-    // the record's mean and factor with 16-byte loads (records are 16-byte
-    // aligned; R is a multiple of 4)
+    // the record's mean and factor: NV float4s, staged per wave in LDS by
+    // 16-byte global-to-LDS loads in rounds of 64 consecutive slots (each
+    // round reads whole stretches of records), at an odd stride per entry
+    // so that the lanes' reads meet no bank conflicts
     constexpr int NV = (N + RecLayout<N>::T + 3) / 4;
+    constexpr int kSt = NV | 1;
+    __shared__ float4 s_rec[256 / kWave][kWave * kSt];
+    const int w = int(threadIdx.x) / kWave, lane = lane_id();
+    const int64_t ew = int64_t(blockIdx.x) * 256 + w * kWave;   // the wave's first entry
+    if (ew >= total) return;                                    // uniform over the wave
+    const int nw = int(total - ew < kWave ? total - ew : kWave);
+    const int64_t e = ew + lane;
+    const int spl = lane < nw ? cand[e] : 0;
+#pragma unroll
+    for (int i = 0; i < kSt; ++i) {
+        const int sl = i * kWave + lane;
+        const int j = sl / kSt, v = sl - j * kSt;
+        const int spj = __shfl(spl, j, kWave);
+        if (v < NV && j < nw)
+            __builtin_amdgcn_global_load_lds(
+                (const __attribute__((address_space(1))) void *)(grec + int64_t(spj) * R + 4 * v),
+                (__attribute__((address_space(3))) void *)(&s_rec[w][i * kWave]), 16, 0, 0);
+    }
+    // the wave reads only what its own loads wrote
+    __builtin_amdgcn_s_waitcnt(0);
+    if (lane >= nw) return;
+    const int sp = spl;
     float r[NV * 4];
-    const float4 *r4 = reinterpret_cast<const float4 *>(grec + int64_t(sp) * R);
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        const float4 u = r4[v];
+        const float4 u = s_rec[w][lane * kSt + v];
         r[4 * v + 0] = u.x;
         r[4 * v + 1] = u.y;
         r[4 * v + 2] = u.z;
