@@ -62,11 +62,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t 
 // flags are written and the stage counters of every wave are added to
 // stats[0..4] = (pairs examined, examined again (no matrix filter here),
 // passed check 1, passed check 2, kept).
-// PRE: the (entry, group) flags already hold a filter's decision (1: the
-// pair may contribute); only flagged pairs are evaluated, and the flags are
-// overwritten with the kept decision.  With COUNT it adds the stage counters
-// to stats[2..4] only (the filter counted stats[0..1]).
-template <int N, bool OUT, bool COUNT = false, bool PRE = false>
+template <int N, bool OUT, bool COUNT = false>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     int64_t q, int tile, const float *__restrict__ grec, const float *__restrict__ qs,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ cand,
@@ -107,54 +103,27 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
         const int lane = lane_id();
         const int vidx = (lane < n) ? cand[ch + lane] : 0;
         uint32_t kept = 0;
-        if constexpr (!PRE) {
-            int64_t ia = __builtin_amdgcn_readlane(vidx, 0);
-            load_block<N>(bufA, grec + ia * Lay::R);
-            for (int j = 0; j < n; j += 2) {
-                __builtin_amdgcn_s_waitcnt(kWaitScalar);
-                int64_t ib = 0;
-                if (j + 1 < n) {
-                    ib = __builtin_amdgcn_readlane(vidx, j + 1);
-                    load_block<N>(bufB, grec + ib * Lay::R);
-                }
-                if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
-                                                   f1, f2, st))
-                    kept = (lane == j) ? 1u : kept;
-                if (j + 1 >= n) break;
-                __builtin_amdgcn_s_waitcnt(kWaitScalar);
-                if (j + 2 < n) {
-                    ia = __builtin_amdgcn_readlane(vidx, j + 2);
-                    load_block<N>(bufA, grec + ia * Lay::R);
-                }
-                if (eval_pair<N, true, OUT, COUNT>(bufB, grec + ib * Lay::R, x, valid, skip, f0,
-                                                   f1, f2, st))
-                    kept = (lane == j + 1) ? 1u : kept;
+        int64_t ia = __builtin_amdgcn_readlane(vidx, 0);
+        load_block<N>(bufA, grec + ia * Lay::R);
+        for (int j = 0; j < n; j += 2) {
+            __builtin_amdgcn_s_waitcnt(kWaitScalar);
+            int64_t ib = 0;
+            if (j + 1 < n) {
+                ib = __builtin_amdgcn_readlane(vidx, j + 1);
+                load_block<N>(bufB, grec + ib * Lay::R);
             }
-        } else {
-            // the flagged candidates in ascending order, one record ahead
-            uint64_t todo =
-                ballot(lane < n && grp < ngroups && act[(ch + lane) * ngroups + grp] != 0);
-            int ja = todo ? __builtin_ctzll(todo) : -1;
-            if (ja >= 0) {
-                todo &= todo - 1;
-                load_block<N>(bufA, grec + int64_t(__builtin_amdgcn_readlane(vidx, ja)) * Lay::R);
+            if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
+                                               f1, f2, st))
+                kept = (lane == j) ? 1u : kept;
+            if (j + 1 >= n) break;
+            __builtin_amdgcn_s_waitcnt(kWaitScalar);
+            if (j + 2 < n) {
+                ia = __builtin_amdgcn_readlane(vidx, j + 2);
+                load_block<N>(bufA, grec + ia * Lay::R);
             }
-            while (ja >= 0) {
-                const int64_t ia = __builtin_amdgcn_readlane(vidx, ja);
-                const int jb = todo ? __builtin_ctzll(todo) : -1;
-                __builtin_amdgcn_s_waitcnt(kWaitScalar);
-                if (jb >= 0) {
-                    todo &= todo - 1;
-                    load_block<N>(bufB,
-                                  grec + int64_t(__builtin_amdgcn_readlane(vidx, jb)) * Lay::R);
-                }
-                if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
-                                                   f1, f2, st))
-                    kept = (lane == ja) ? 1u : kept;
-#pragma unroll
-                for (int e = 0; e < Lay::PF; ++e) bufA[e] = bufB[e];
-                ja = jb;
-            }
+            if (eval_pair<N, true, OUT, COUNT>(bufB, grec + ib * Lay::R, x, valid, skip, f0,
+                                               f1, f2, st))
+                kept = (lane == j + 1) ? 1u : kept;
         }
         if (lane < n && grp < ngroups) act[(ch + lane) * ngroups + grp] = uint8_t(kept);
     }
@@ -162,10 +131,8 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
         if (lane_id() == 0 && grp < ngroups) {
             // (examined, not skipped by a matrix filter -- there is none here,
             // passed check 1, passed check 2, kept)
-            if constexpr (!PRE) {
-                atomicAdd(&stats[0], static_cast<unsigned long long>(e1 - e0));
-                atomicAdd(&stats[1], static_cast<unsigned long long>(e1 - e0));
-            }
+            atomicAdd(&stats[0], static_cast<unsigned long long>(e1 - e0));
+            atomicAdd(&stats[1], static_cast<unsigned long long>(e1 - e0));
             atomicAdd(&stats[2], static_cast<unsigned long long>(st[0]));
             atomicAdd(&stats[3], static_cast<unsigned long long>(st[1]));
             atomicAdd(&stats[4], static_cast<unsigned long long>(st[2]));
@@ -263,46 +230,7 @@ hipError_t stats_n(const ngd_cull *c, unsigned long long *stats, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int N>
-hipError_t flagged_n(const ngd_cull *c, float *out, unsigned long long *stats, hipStream_t s)
-{
-    const int tile = c->params.tile;
-    const int per = tile < kEvalThreads ? (tile + 63) / 64 * 64 : kEvalThreads;
-    const unsigned gy = unsigned((tile + kEvalThreads - 1) / kEvalThreads);
-    const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
-    if (c->nitems == 0) return hipSuccess;
-    const dim3 grid(unsigned(c->nitems), gy);
-    auto go = [&](auto kern, float *o, unsigned long long *st) {
-        kern<<<grid, per, 0, s>>>(c->q, tile, c->grec.as<float>(), c->qs.as<float>(),
-                                  c->tile_off.as<int64_t>(), c->cand.as<int32_t>(),
-                                  c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
-                                  c->item_off.as<int64_t>(), skip, o, c->fpart.as<float>(),
-                                  c->act.as<uint8_t>(), st);
-    };
-    if (stats)
-        go(k_eval_items<N, false, true, true>, nullptr, stats);
-    else if (out)
-        go(k_eval_items<N, true, false, true>, out, nullptr);
-    else
-        go(k_eval_items<N, false, false, true>, nullptr, nullptr);
-    return hipGetLastError();
-}
-
 }  // namespace
-
-hipError_t launch_eval_flagged(const ngd_mixture *mix, const ngd_cull *c, float *out,
-                               unsigned long long *stats, hipStream_t s)
-{
-    if (c->q == 0 || c->ntiles == 0) return hipSuccess;
-    switch (mix->n) {
-#define NGD_CASE(NN) \
-    case NN: return flagged_n<NN>(c, out, stats, s);
-        NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
-        NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
-#undef NGD_CASE
-    default: return hipErrorInvalidValue;
-    }
-}
 
 hipError_t launch_eval_reduce(const ngd_cull *c, float *out, hipStream_t s)
 {

@@ -288,15 +288,21 @@ __global__ __launch_bounds__(256) void k_mfma_entry(int64_t total,
     ebnd[e] = make_float4(fabsf(a0), b1, m1, rrow[sp]);
 }
 
-template <int N, bool COUNT>
-__global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
+// OUT: the colours are accumulated and written (caller order); otherwise
+// only the (entry, group) flags.  COUNT (with OUT = false): the counters
+// stats[0..4] = (examined, not skipped by the matrix filter, passed check 1,
+// passed check 2, kept) are added.
+template <int N, bool OUT, bool COUNT>
+__global__ __launch_bounds__(kMThreads, 3) void k_mfma_filter(
     int64_t q, int tile, const bf16x8 *__restrict__ mrec, const bf16x8 *__restrict__ eb0,
     const float4 *__restrict__ ebnd, const float *__restrict__ tcen,
-    const float *__restrict__ qs, const int64_t *__restrict__ tile_off,
-    const int32_t *__restrict__ cand, float skip, uint8_t *__restrict__ act,
-    unsigned long long *__restrict__ stats)
+    const float *__restrict__ qs, const float *__restrict__ grec,
+    const int64_t *__restrict__ tile_off, const int32_t *__restrict__ cand,
+    const int32_t *__restrict__ perm, float skip, uint8_t *__restrict__ act,
+    float *__restrict__ out, unsigned long long *__restrict__ stats)
 {
     using Fe = Feat<N>;
+    using Lay = RecLayout<N>;
     constexpr int KS = Fe::KS, KQ = Fe::KQ;
     // Per buffer, three regions of 16-byte slots, each entry's units padded
     // to an odd stride so that 8 and 16 consecutive entries fall on distinct
@@ -460,11 +466,13 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
     int cv_next = cand_of(e0 + kCh);
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+    uint32_t st[3] = {0u, 0u, 0u};
     int buf = 0;
     for (int64_t ch = e0; ch < e1; ch += kCh) {
         const bool more = ch + kCh < e1;
         if (more) load_chunk(buf ^ 1, ch + kCh, cv_next);
-        cv_next = cand_of(ch + 2 * kCh);
+        const int cv_after = cand_of(ch + 2 * kCh);
         const int n = int((e1 - ch < kCh) ? e1 - ch : kCh);
         if constexpr (COUNT) {
             // a group past the tile's end counts its pairs as examined, as
@@ -529,18 +537,75 @@ __global__ __launch_bounds__(kMThreads, 2) void k_mfma_filter(
         __builtin_amdgcn_s_waitcnt(0);
         __syncthreads();
         buf ^= 1;
+        cv_next = cv_after;
+    }
+    // The pairs the filter kept are evaluated in float32 by the staged code
+    // of the float32 kernel (lane = its own query), in ascending entry order
+    // per group, each record fetched with wave-uniform loads one pair ahead;
+    // the flag becomes the kept decision.  The flags read are this wave's
+    // own (written above, complete after the last wait).
+    if (live && grp < ngroups) {
+        float x[N];
+        {
+            // the row index made opaque here, so that the compiler does not
+            // keep its N addresses live through the loop above
+            int pc = int(valid ? s : 0);
+            asm volatile("" : "+v"(pc));
+            const float *qp = qs + t * tile + pc;
+#pragma unroll
+            for (int a = 0; a < N; ++a) x[a] = qp[a * q];
+        }
+        float bufA[Lay::PF], bufB[Lay::PF];
+        for (int64_t ch = e0; ch < e1; ch += kWave) {
+            const int n = int((e1 - ch < kWave) ? e1 - ch : kWave);
+            uint8_t *fl = act + (ch + lane) * ngroups + grp;
+            uint64_t todo = ballot(lane < n && *fl != 0);
+            if (todo == 0) continue;
+            const int vidx = (lane < n) ? cand[ch + lane] : 0;
+            uint32_t kept = 0;
+            int ja = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            load_block<N>(bufA, grec + int64_t(__builtin_amdgcn_readlane(vidx, ja)) * Lay::R);
+            while (ja >= 0) {
+                const int64_t ia = __builtin_amdgcn_readlane(vidx, ja);
+                const int jb = todo ? __builtin_ctzll(todo) : -1;
+                __builtin_amdgcn_s_waitcnt(kWaitScalar);
+                if (jb >= 0) {
+                    todo &= todo - 1;
+                    load_block<N>(bufB,
+                                  grec + int64_t(__builtin_amdgcn_readlane(vidx, jb)) * Lay::R);
+                }
+                if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
+                                                   f1, f2, st))
+                    kept = (lane == ja) ? 1u : kept;
+#pragma unroll
+                for (int e = 0; e < Lay::PF; ++e) bufA[e] = bufB[e];
+                ja = jb;
+            }
+            if (lane < n) *fl = uint8_t(kept);
+        }
     }
     if constexpr (COUNT) {
         if (lane == 0 && grp < ngroups) {
             atomicAdd(&stats[0], n_exam);
             atomicAdd(&stats[1], n_pass);
+            atomicAdd(&stats[2], static_cast<unsigned long long>(st[0]));
+            atomicAdd(&stats[3], static_cast<unsigned long long>(st[1]));
+            atomicAdd(&stats[4], static_cast<unsigned long long>(st[2]));
+        }
+    }
+    if constexpr (OUT) {
+        if (valid) {
+            const int64_t o = perm[p];
+            out[o * 3 + 0] = f0;
+            out[o * 3 + 1] = f1;
+            out[o * 3 + 2] = f2;
         }
     }
 }
 
 template <int N>
-hipError_t mfma_n(const ngd_mixture *mix, ngd_cull *c, float *out, unsigned long long *stats,
-                  hipStream_t s)
+hipError_t mfma_n(ngd_cull *c, float *out, unsigned long long *stats, hipStream_t s)
 {
     const int tile = c->params.tile;
     const unsigned gy = unsigned((tile + kMThreads - 1) / kMThreads);
@@ -561,23 +626,27 @@ hipError_t mfma_n(const ngd_mixture *mix, ngd_cull *c, float *out, unsigned long
         if ((e = hipGetLastError()) != hipSuccess) return e;
         c->mrec_seq = c->build_seq;
     }
-    if (c->nitems > 0) {
+    if (c->ntiles > 0) {
+        // every tile's workgroup writes its queries' colours (zeros for a
+        // tile with no candidates)
         const dim3 grid(unsigned(c->ntiles), gy);
-        auto go = [&](auto kern, unsigned long long *st) {
+        auto go = [&](auto kern, float *o, unsigned long long *st) {
             kern<<<grid, kMThreads, 0, s>>>(c->q, tile, c->mrec.as<bf16x8>(), c->eb0.as<bf16x8>(),
-                                      c->ebnd.as<float4>(), c->tcen.as<float>(),
-                                      c->qs.as<float>(), c->tile_off.as<int64_t>(),
-                                      c->cand.as<int32_t>(), skip, c->act.as<uint8_t>(), st);
+                                            c->ebnd.as<float4>(), c->tcen.as<float>(),
+                                            c->qs.as<float>(), c->grec.as<float>(),
+                                            c->tile_off.as<int64_t>(), c->cand.as<int32_t>(),
+                                            c->perm.as<int32_t>(), skip, c->act.as<uint8_t>(), o,
+                                            st);
         };
         if (stats)
-            go(k_mfma_filter<N, true>, stats);
+            go(k_mfma_filter<N, false, true>, nullptr, stats);
+        else if (out)
+            go(k_mfma_filter<N, true, false>, out, nullptr);
         else
-            go(k_mfma_filter<N, false>, nullptr);
+            go(k_mfma_filter<N, false, false>, nullptr, nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = launch_eval_flagged(mix, c, out, stats, s)) != hipSuccess) return e;
     }
-    if (!out) return hipSuccess;
-    return launch_eval_reduce(c, out, s);
+    return hipSuccess;
 }
 
 }  // namespace
@@ -596,7 +665,7 @@ hipError_t launch_eval_mfma(const ngd_mixture *mix, ngd_cull *c, float *out,
     if (c->q == 0 || c->ntiles == 0) return hipSuccess;
     switch (mix->n) {
 #define NGD_CASE(NN) \
-    case NN: return mfma_n<NN>(mix, c, out, stats, s);
+    case NN: return mfma_n<NN>(c, out, stats, s);
         NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
         NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
 #undef NGD_CASE

@@ -221,11 +221,6 @@ hipError_t launch_eval_stats(const ngd_mixture *mix, const ngd_cull *c,
                              unsigned long long *stats, hipStream_t s);
 // Culled forward; with out == nullptr only the keep/skip flags are written.
 hipError_t launch_eval_reduce(const ngd_cull *c, float *out, hipStream_t s);
-// The float32 forward over the (entry, group) pairs a filter flagged in
-// c->act (1: evaluate); rewrites the flags with the kept decision.  out,
-// stats as for launch_eval_mfma (stats[2..4] only).
-hipError_t launch_eval_flagged(const ngd_mixture *mix, const ngd_cull *c, float *out,
-                               unsigned long long *stats, hipStream_t s);
 // Culled forward with the BF16 MFMA filter (eval_mfma.hip).  out: colours;
 // out == nullptr: keep/skip flags only; stats != nullptr: counting mode,
 // stats[0..4] = (group-candidate pairs examined, not skipped by the matrix
