@@ -262,16 +262,19 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
             const int sidx = gq * kWave + lane;
             const int64_t p = tt * tile + sidx;
             const bool valid = (sidx < tile) && (p < q);
+            // every lane loads (a lane past the tile's end from the tile's
+            // first query) and the invalid ones are zeroed: no branches
+            const int64_t pc = valid ? p : tt * tile;
             float x[N], d[N], y[N];
 #pragma unroll
-            for (int a = 0; a < N; ++a) x[a] = valid ? qs[a * q + p] : 0.0f;
+            for (int a = 0; a < N; ++a) x[a] = qs[a * q + pc];
             float msq = 0.0f;
             brows<N, 0, N>(r, x, d, y, msq);
             any = true;
             const float G = valid ? __builtin_amdgcn_exp2f(-msq) : 0.0f;
-            const float g0v = valid ? gs[p] : 0.0f;
-            const float g1v = valid ? gs[q + p] : 0.0f;
-            const float g2v = valid ? gs[2 * q + p] : 0.0f;
+            const float g0v = valid ? gs[pc] : 0.0f;
+            const float g1v = valid ? gs[q + pc] : 0.0f;
+            const float g2v = valid ? gs[2 * q + pc] : 0.0f;
             const float sdot = fmaf(g2v, c2, fmaf(g1v, c1, g0v * c0));
             const float w = alpha * G * sdot;
             h0 = fmaf(G, g0v, h0);
@@ -291,23 +294,27 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
         if (lane == 0) gflag[it] = 0;
         return;
     }
+    // the moments (B1 | B2 | H, padded to a multiple of 4) summed over the
+    // wave; lane 16 r + 15 writes the totals of the r-th quarter
+    constexpr int VP = (Lay::NM + 3) & ~3, Q = VP / 4;
+    float mv[VP];
 #pragma unroll
-    for (int a = 0; a < N; ++a) b1[a] = wave_sum_last(b1[a]);
+    for (int a = 0; a < N; ++a) mv[a] = b1[a];
 #pragma unroll
-    for (int e = 0; e < T; ++e) b2[e] = wave_sum_last(b2[e]);
-    h0 = wave_sum_last(h0);
-    h1 = wave_sum_last(h1);
-    h2 = wave_sum_last(h2);
-    if (lane != kWave - 1) return;
+    for (int e = 0; e < T; ++e) mv[N + e] = b2[e];
+    mv[N + T + 0] = h0;
+    mv[N + T + 1] = h1;
+    mv[N + T + 2] = h2;
+#pragma unroll
+    for (int e = Lay::NM; e < VP; ++e) mv[e] = 0.0f;
+    wave_reduce_scatter<VP>(mv);
+    if ((lane & 15) != 15) return;
     float *out = gpart + it * Lay::NM;
+    const int r0 = (lane >> 4) * Q;
 #pragma unroll
-    for (int a = 0; a < N; ++a) out[a] = b1[a];
-#pragma unroll
-    for (int e = 0; e < T; ++e) out[N + e] = b2[e];
-    out[N + T + 0] = h0;
-    out[N + T + 1] = h1;
-    out[N + T + 2] = h2;
-    gflag[it] = 1;
+    for (int i = 0; i < Q; ++i)
+        if (r0 + i < Lay::NM) out[r0 + i] = mv[i];
+    if (lane == kWave - 1) gflag[it] = 1;
 }
 
 // Per sorted Gaussian: sum its items' moments in item order, then

@@ -104,6 +104,38 @@ __device__ __forceinline__ float wave_sum_last(float v)
     return v;
 }
 
+// Sums over the wave of V values per lane (V a multiple of 4), scattered:
+// a permlane swap across lane distance 32 halves the values each lane
+// holds (lanes 0-31 keep the first half, 32-63 the second, each adding its
+// partner's), one across distance 16 halves them again within each half,
+// and a DPP running sum within each row of 16 lanes completes them.  Lane
+// 16 r + 15 then holds the totals of values [r V/4, (r + 1) V/4) in
+// v[0 .. V/4).  A fixed order: bitwise reproducible.
+template <int V> __device__ __forceinline__ void wave_reduce_scatter(float (&v)[V])
+{
+    static_assert(V % 4 == 0, "values in four equal rows");
+    constexpr int H = V / 2, Q = V / 4;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[i]),
+                                                        __float_as_uint(v[i + H]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v[i]),
+                                                        __float_as_uint(v[i + Q]), false, false);
+        v[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        v[i] = dpp_add<kDppRowShr1, 0xf>(v[i]);
+        v[i] = dpp_add<kDppRowShr2, 0xf>(v[i]);
+        v[i] = dpp_add<kDppRowShr4, 0xf>(v[i]);
+        v[i] = dpp_add<kDppRowShr8, 0xf>(v[i]);
+    }
+}
+
 __device__ __forceinline__ float wave_min(float v)
 {
 #pragma unroll
