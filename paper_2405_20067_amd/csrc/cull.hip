@@ -569,6 +569,19 @@ hipError_t launch_items(int64_t n, const int64_t *off, int per, DevBuf &cnt, Dev
     return scan_counts(cnt, ioff, n, scan_tmp, s);
 }
 
+// The Gaussians in their tile order: records, and the interval test's
+// limits (g_sorted: the projected means are already in that order).
+hipError_t gauss_side(ngd_cull *c, const ngd_mixture *mix, int64_t k, int R, int P,
+                      bool g_sorted, hipStream_t s)
+{
+    k_rec_gather<<<nblk(k, kWave), kThreads, 0, s>>>(k, R, c->gperm.as<int32_t>(),
+                                                      mix->rec.as<float>(), c->grec.as<float>());
+    k_gauss_limits<<<dim3(nblk(k, kThreads), unsigned(P)), kThreads, 0, s>>>(
+        k, c->gperm.as<int32_t>(), c->g_mr.as<float>(), g_sorted ? c->g_mr_s.as<float>() : nullptr,
+        c->g_thr.as<float>(), c->g_ub.as<float>(), c->g_lb.as<float>());
+    return hipGetLastError();
+}
+
 template <int N>
 hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hipStream_t s)
 {
@@ -599,7 +612,7 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     // the k-d order leaves the projections in order: tile bounds and the
     // ordered means read them without a gather
     const float *qr_s = nullptr;
-    bool g_sorted = false;
+    bool g_sorted = false, gauss_done = false;
     if (c->params.tiling == 0) {
         // k-d order of the query projections (runs of `tile`, and of 64
         // inside those) and of the projected means (runs of 64, the chunks
@@ -632,6 +645,11 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         while (e == hipSuccess && !(rq.done && rg.done)) {
             if (!rq.done) e = kd_step(rq);
             if (e == hipSuccess && !rg.done) e = kd_step(rg);
+        }
+        // the Gaussians' side goes on while the queries' order finishes
+        if (forked && e == hipSuccess) {
+            e = gauss_side(c, mix, k, R, P, true, c->side);
+            gauss_done = true;
         }
         if (forked) {
             const hipError_t ej = hipEventRecord(c->ev_join, c->side);
@@ -688,15 +706,8 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         k_super_bounds<<<nblk(nsup * 2 * PP, kThreads), kThreads, 0, s>>>(
             c->ntiles, PP, c->tbnd.as<float>(), c->sbnd.as<float>());
     }
-    if (k > 0) {
-        k_rec_gather<<<nblk(k, kWave), kThreads, 0, s>>>(k, R, c->gperm.as<int32_t>(),
-                                                          mix->rec.as<float>(),
-                                                          c->grec.as<float>());
-        k_gauss_limits<<<dim3(nblk(k, kThreads), unsigned(P)), kThreads, 0, s>>>(
-            k, c->gperm.as<int32_t>(), c->g_mr.as<float>(),
-            g_sorted ? c->g_mr_s.as<float>() : nullptr, c->g_thr.as<float>(),
-            c->g_ub.as<float>(), c->g_lb.as<float>());
-    }
+    if (k > 0 && !gauss_done && (e = gauss_side(c, mix, k, R, P, g_sorted, s)) != hipSuccess)
+        return e;
     k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long *>(c->stats.p), 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (k == 0 || c->ntiles == 0) {
