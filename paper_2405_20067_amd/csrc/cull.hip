@@ -458,6 +458,14 @@ __global__ __launch_bounds__(kThreads) void k_seg_prefix(int64_t ntiles, int nse
     atomicMax(maxc, static_cast<unsigned long long>(run));
 }
 
+// Candidate lists from the masks: one workgroup per (64 tiles, chunk
+// segment).  Per round of 64 chunks the masks are read row by row
+// (coalesced) into LDS, transposed; each wave then takes 16 of the tiles,
+// lane = chunk: the popcounts' exclusive scan gives each chunk's first
+// position, every lane places its chunk's set bits (ascending) in the
+// wave's LDS staging row, and the row goes out with contiguous stores.
+constexpr int kFillTiles = 64;
+constexpr int kFillStage = 1024;   // staged candidates per wave and round
 __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t tpad,
                                                         int64_t nchunks, int64_t per_seg,
                                                         const uint64_t *__restrict__ masks,
@@ -466,23 +474,60 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
                                                         int32_t *__restrict__ cand,
                                                         int32_t *__restrict__ ent_tile)
 {
-    const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (t >= ntiles) return;
+    __shared__ uint64_t sm[kFillTiles][kWave + 1];   // [tile][chunk]
+    __shared__ int32_t stage[kThreads / kWave][kFillStage];
+    __shared__ int64_t run[kFillTiles];
+    const int64_t t0 = int64_t(blockIdx.x) * kFillTiles;
     const int64_t seg = blockIdx.y;
     const int64_t c0 = seg * per_seg;
     const int64_t c1 = (c0 + per_seg < nchunks) ? c0 + per_seg : nchunks;
-    int64_t pos = tile_off[t] + seg_cnt[seg * ntiles + t];
-    const int64_t end = tile_off[t + 1];
-    for (int64_t c = c0; c < c1; ++c) {
-        uint64_t m = masks[c * tpad + t];
-        while (m) {
-            const int b = __ffsll(static_cast<unsigned long long>(m)) - 1;
-            if (pos < end) {
-                cand[pos] = int32_t(c * kWave + b);
-                ent_tile[pos] = int32_t(t);
+    const int w = int(threadIdx.x) / kWave, lane = lane_id();
+    if (int(threadIdx.x) < kFillTiles) {
+        const int64_t t = t0 + threadIdx.x;
+        run[threadIdx.x] = t < ntiles ? tile_off[t] + seg_cnt[seg * ntiles + t] : 0;
+    }
+    int32_t *st = stage[w];
+    for (int64_t cb = c0; cb < c1; cb += kWave) {
+        __syncthreads();   // run[] set; the previous round's readers done
+        for (int r = w; r < kWave; r += kThreads / kWave) {
+            const int64_t c = cb + r, t = t0 + lane;
+            sm[lane][r] = (c < c1 && t < ntiles) ? masks[c * tpad + t] : 0ull;
+        }
+        __syncthreads();
+        for (int tl = w; tl < kFillTiles; tl += kThreads / kWave) {
+            const int64_t t = t0 + tl;
+            if (t >= ntiles) break;   // uniform
+            uint64_t m = sm[tl][lane];
+            const int cnt = __popcll(m);
+            const int incl = wave_inclusive_scan(cnt);
+            const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
+            if (total == 0) continue;   // uniform
+            const int32_t gbase = int32_t((cb + lane) * kWave);
+            const int64_t base = run[tl], end = tile_off[t + 1];
+            int k = incl - cnt;
+            if (total <= kFillStage) {   // uniform
+                while (m) {
+                    st[k++] = gbase + (__ffsll(static_cast<unsigned long long>(m)) - 1);
+                    m &= m - 1;
+                }
+                for (int i = lane; i < total; i += kWave) {
+                    const int64_t pos = base + i;
+                    if (pos < end) {
+                        cand[pos] = st[i];
+                        ent_tile[pos] = int32_t(t);
+                    }
+                }
+            } else {   // a dense round: every lane writes its own bits
+                while (m) {
+                    const int64_t pos = base + k++;
+                    if (pos < end) {
+                        cand[pos] = gbase + (__ffsll(static_cast<unsigned long long>(m)) - 1);
+                        ent_tile[pos] = int32_t(t);
+                    }
+                    m &= m - 1;
+                }
             }
-            ++pos;
-            m &= m - 1;
+            if (lane == 0) run[tl] = base + total;   // this wave's own tile
         }
     }
 }
@@ -772,7 +817,7 @@ hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s)
             c->ntiles, c->item_off.as<int64_t>(), c->nitems, c->item_tile.as<int32_t>());
     if (c->total == 0 || c->ntiles == 0 || c->k == 0) return hipGetLastError();
     const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
-    dim3 sgrid(nblk(c->ntiles, kThreads), unsigned(c->nseg));
+    dim3 sgrid(nblk(c->ntiles, kFillTiles), unsigned(c->nseg));
     k_fill_cand<<<sgrid, kThreads, 0, s>>>(c->ntiles, c->tpad, c->nchunks, per_seg,
                                            c->masks.as<uint64_t>(), c->seg_cnt.as<int32_t>(),
                                            c->tile_off.as<int64_t>(), c->cand.as<int32_t>(),

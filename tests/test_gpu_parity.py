@@ -57,6 +57,10 @@ CULL_CASES = [
     dict(n=4, k=3000, q=20000, tile=256, long=2),
     dict(n=6, k=2500, q=9000, tile=512, long=1),
     dict(n=10, k=3000, q=9000, tile=256, sdiag=(3.0, 30.0), long=2),
+    # few, large tiles: most pairs are candidates (over 3000 of the 4096
+    # Gaussians per tile), more in each 64-chunk round of the list build than
+    # a wave stages at once
+    dict(n=4, k=4096, q=1500, tile=256, sdiag=(8.0, 12.0)),
 ]
 
 
