@@ -370,6 +370,13 @@ __global__ __launch_bounds__(kThreads) void k_super_bounds(int64_t ntiles, int P
 // projections).  A super-tile's box contains each of its tiles' boxes, so a
 // lane it culls is culled for each tile, and the masks are those of the
 // plain per-tile test bit for bit.
+//
+// Each group of 4 projections narrows the execution mask directly: with
+// exec = alive, v_cmpx keeps a lane only where its comparison holds (8
+// vector compares and no scalar mask arithmetic per group); the surviving
+// mask is read back and exec restored within the same asm block, so the
+// compiler's view of exec is untouched.  NaN limits compare false, as
+// before.
 template <int PP>
 __device__ __forceinline__ uint64_t box_test(uint64_t alive, const float (&ub)[PP],
                                              const float (&lb)[PP],
@@ -377,9 +384,27 @@ __device__ __forceinline__ uint64_t box_test(uint64_t alive, const float (&ub)[P
 {
 #pragma unroll
     for (int g = 0; g < PP; g += 4) {
-#pragma unroll
-        for (int j = g; j < g + 4; ++j)
-            alive &= ballot(box[j] <= ub[j]) & ballot(box[PP + j] >= lb[j]);
+        uint64_t sv;
+        asm volatile("s_mov_b64 %[sv], exec\n\t"
+                     "s_mov_b64 exec, %[al]\n\t"
+                     "v_cmpx_le_f32_e32 vcc, %[l0], %[u0]\n\t"
+                     "v_cmpx_ge_f32_e32 vcc, %[h0], %[b0]\n\t"
+                     "v_cmpx_le_f32_e32 vcc, %[l1], %[u1]\n\t"
+                     "v_cmpx_ge_f32_e32 vcc, %[h1], %[b1]\n\t"
+                     "v_cmpx_le_f32_e32 vcc, %[l2], %[u2]\n\t"
+                     "v_cmpx_ge_f32_e32 vcc, %[h2], %[b2]\n\t"
+                     "v_cmpx_le_f32_e32 vcc, %[l3], %[u3]\n\t"
+                     "v_cmpx_ge_f32_e32 vcc, %[h3], %[b3]\n\t"
+                     "s_mov_b64 %[al], exec\n\t"
+                     "s_mov_b64 exec, %[sv]"
+                     : [al] "+s"(alive), [sv] "=&s"(sv)
+                     : [l0] "s"(box[g + 0]), [u0] "v"(ub[g + 0]), [h0] "s"(box[PP + g + 0]),
+                       [b0] "v"(lb[g + 0]), [l1] "s"(box[g + 1]), [u1] "v"(ub[g + 1]),
+                       [h1] "s"(box[PP + g + 1]), [b1] "v"(lb[g + 1]), [l2] "s"(box[g + 2]),
+                       [u2] "v"(ub[g + 2]), [h2] "s"(box[PP + g + 2]), [b2] "v"(lb[g + 2]),
+                       [l3] "s"(box[g + 3]), [u3] "v"(ub[g + 3]), [h3] "s"(box[PP + g + 3]),
+                       [b3] "v"(lb[g + 3])
+                     : "vcc");
         if (alive == 0) break;
     }
     return alive;
