@@ -270,7 +270,8 @@ def main():
         ks = 1 + (w.n * (w.n + 1) // 2 + 15) // 16
         alg = cnt["examined"] * 64 * nf * 2 * 3
         a = alg / t / 1e12
-        return dict(bound="mfma", kernel="forward: k_eval_mfma + k_eval_reduce (ngd_eval, "
+        return dict(bound="mfma", kernel="forward: k_mfma_coef, k_tile_centre, k_mfma_entry "
+                                         "(once per cull build), k_mfma_filter (ngd_eval, "
                                          "NGD_BF16_MFMA)",
                     achieved=a, peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
                     frac=a / BF16_MFMA_PEAK_TFLOPS, traffic=traffic,
