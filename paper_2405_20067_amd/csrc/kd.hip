@@ -49,12 +49,12 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kSlice = 1024;        // points per scatter / count workgroup
-constexpr int kHistSlice = 8192;    // points per histogram workgroup
+constexpr int kHistSlice = 4096;    // points per histogram workgroup
 constexpr int kBins = 2048;
 constexpr int kShift[3] = {21, 10, 0};
 constexpr int kWidth[3] = {11, 11, 10};
 
-constexpr int kHistThreads = 1024;
+constexpr int kHistThreads = 512;
 
 constexpr int kLocalThreads = 256;
 constexpr int kLocalMax = 1024;     // points per subtree workgroup (<= 4096: 12-bit positions)
