@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     unsigned long long *__restrict__ stats = nullptr)
 {
     using Lay = RecLayout<N>;
-    const int64_t it = blockIdx.x;
+    const int64_t it = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles share an L2
     const int64_t t = uniform(item_tile[it]);
     const int64_t i0 = uniform64(item_off[t]);
     const int64_t nit = uniform64(item_off[t + 1]) - i0;

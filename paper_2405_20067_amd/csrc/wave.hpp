@@ -23,6 +23,20 @@ __device__ __forceinline__ uint64_t lanemask_lt()
     return (uint64_t(1) << lane_id()) - 1;
 }
 
+// Workgroups are dispatched to the 8 XCDs of the chip in turn (workgroup b
+// to XCD b mod 8), and each XCD has its own L2.  xcd_block maps the
+// dispatch index b of a grid of nb workgroups to a logical index so that
+// every XCD takes one contiguous range of the logical order (neighbouring
+// tiles or entries, which share Gaussians, then share an L2).  A bijection
+// of [0, nb).
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nb)
+{
+    const int64_t q = nb / kXcds, r = nb % kXcds;
+    const int64_t x = b % kXcds, i = b / kXcds;
+    return x * q + (x < r ? x : r) + i;
+}
+
 // DPP controls (GFX9 encoding).
 constexpr int kDppRowShr1 = 0x111;
 constexpr int kDppRowShr2 = 0x112;
