@@ -56,8 +56,8 @@ constexpr int kWidth[3] = {11, 11, 10};
 
 constexpr int kHistThreads = 512;
 
-constexpr int kLocalThreads = 256;
-constexpr int kLocalMax = 1024;     // points per subtree workgroup (<= 4096: 12-bit positions)
+constexpr int kLocalMax = 1024;
+constexpr unsigned kWideLocalBlocks = 512;   // subtrees for the 512-thread variant     // points per subtree workgroup (<= 4096: 12-bit positions)
 constexpr int kLocalRuns = 128;     // runs per subtree (8-bit run ids)
 constexpr int kLocalSplit = 64;     // runs split at one level of a subtree
 
@@ -495,16 +495,17 @@ __global__ __launch_bounds__(kThreads) void k_kd_scatter(
 
 // ---- subtrees of at most kLocalMax points, one workgroup each -------------
 
+template <int THREADS>
 __device__ int local_exscan(int v, int *total)
 {
-    __shared__ int wt[kLocalThreads / kWave];
+    __shared__ int wt[THREADS / kWave];
     const int lane = lane_id(), w = threadIdx.x / kWave;
     const int inc = wave_inclusive_scan(v);
     if (lane == kWave - 1) wt[w] = inc;
     __syncthreads();
     int before = 0, all = 0;
 #pragma unroll
-    for (int i = 0; i < kLocalThreads / kWave; ++i) {
+    for (int i = 0; i < THREADS / kWave; ++i) {
         before += (i < w) ? wt[i] : 0;
         all += wt[i];
     }
@@ -513,20 +514,26 @@ __device__ int local_exscan(int v, int *total)
     return before + inc - v;
 }
 
-template <int PMAX>
+template <int PMAX, int kLocalThreads>
 __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
     const int64_t *__restrict__ nodes, int64_t n, int P, int leaf, int sub,
     const int32_t *__restrict__ idx_in, const float *__restrict__ vin,
     int32_t *__restrict__ idx_out, float *__restrict__ vout)
 {
-    __shared__ uint64_t keys[kLocalMax];
     __shared__ uint16_t ord[2][kLocalMax];
     __shared__ uint16_t lpre[kLocalMax];
     __shared__ uint8_t flag[kLocalMax];
     __shared__ uint8_t run_of[kLocalMax];
     __shared__ int rs[kLocalRuns], rl[kLocalRuns], rn[kLocalRuns], rd[kLocalRuns], rsi[kLocalRuns];
     __shared__ int split_list[kLocalSplit];
-    __shared__ uint32_t emin[kLocalSplit][PMAX], emax[kLocalSplit][PMAX];
+    // min / max slots of the splitting runs; during the sort (after the
+    // split projections are chosen) the same memory exchanges keys between
+    // waves
+    __shared__ uint32_t ext_buf[2][kLocalSplit][PMAX];
+    static_assert(sizeof(ext_buf) >= kLocalMax * sizeof(uint64_t), "key exchange fits");
+    auto &emin = ext_buf[0];
+    auto &emax = ext_buf[1];
+    uint64_t *keys = reinterpret_cast<uint64_t *>(&ext_buf[0][0][0]);
     __shared__ int nruns_s, nsplit_s, sortlen_s;
 
     const int64_t *row = nodes + int64_t(blockIdx.x) * kNodeCols;
@@ -537,6 +544,8 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
     int m2 = 1;
     while (m2 < m) m2 <<= 1;
     constexpr int kPer = kLocalMax / kLocalThreads;   // positions per thread
+    constexpr int kSpan = kPer * kWave;   // elements per wave
+    static_assert(kPer * kLocalThreads == kLocalMax, "elements: lane, register, wave bits");
 
     for (int i = tid; i < m; i += kLocalThreads) {
         ord[0][i] = uint16_t(i);
@@ -630,11 +639,12 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
         }
         __syncthreads();
         // sort keys (run, key on the run's split projection, position); runs
-        // that do not split sort by (run, position), i.e. stay in place
+        // that do not split sort by (run, position), i.e. stay in place.
+        // Element e = w * kSpan + r * 64 + lane is register r of that lane.
+        uint64_t kr[kPer];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int i = tid + q * kLocalThreads;
-            if (i >= m2) break;
+        for (int r = 0; r < kPer; ++r) {
+            const int i = w * kSpan + r * kWave + lane;
             uint64_t key = ~uint64_t(0);
             if (i < m) {
                 const int b = run_of[i];
@@ -644,39 +654,62 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
                     key |= uint64_t(orderable(v)) << 12;
                 }
             }
-            keys[i] = key;
+            kr[r] = key;
         }
-        __syncthreads();
         // bitonic sort of every aligned block of L keys, ascending (the last
-        // merge of a block sorts it up whatever its position)
+        // merge of a block sorts it up whatever its position); elements past
+        // m2 hold the largest key and stay in their own blocks.  Partners at
+        // distance j < 64 are lanes of the wave, at j < kSpan registers of
+        // the thread, further off other waves (through LDS).
         const int L = sortlen_s;
         for (int k = 2; k <= L; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
+                if (j >= kSpan) {   // uniform
 #pragma unroll
-                for (int q = 0; q < kPer / 2; ++q) {
-                    // pair number -> lower index i (bit j clear), partner i + j
-                    const int pr = tid + q * kLocalThreads;
-                    const int i = ((pr & ~(j - 1)) << 1) | (pr & (j - 1));
-                    if (i + j < m2) {
-                        const uint64_t a = keys[i], c = keys[i + j];
-                        const bool up = k == L || (i & k) == 0;
+                    for (int r = 0; r < kPer; ++r) keys[w * kSpan + r * kWave + lane] = kr[r];
+                    __syncthreads();
+#pragma unroll
+                    for (int r = 0; r < kPer; ++r) {
+                        const int e = w * kSpan + r * kWave + lane;
+                        const uint64_t o = keys[e ^ j];
+                        const bool up = k == L || (e & k) == 0;
+                        const bool keep_min = ((e & j) == 0) == up;
+                        kr[r] = keep_min ? (kr[r] < o ? kr[r] : o) : (kr[r] > o ? kr[r] : o);
+                    }
+                    __syncthreads();
+                } else if (j >= kWave) {
+                    const int rj = j / kWave;
+#pragma unroll
+                    for (int r = 0; r < kPer; ++r) {
+                        if (r & rj) continue;
+                        const int e = w * kSpan + r * kWave + lane;
+                        const bool up = k == L || (e & k) == 0;
+                        const uint64_t a = kr[r], c = kr[r | rj];
                         if ((a > c) == up) {
-                            keys[i] = c;
-                            keys[i + j] = a;
+                            kr[r] = c;
+                            kr[r | rj] = a;
                         }
                     }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < kPer; ++r) {
+                        const int e = w * kSpan + r * kWave + lane;
+                        const uint64_t o = __shfl_xor(kr[r], j, kWave);
+                        const bool up = k == L || (e & k) == 0;
+                        const bool keep_min = ((e & j) == 0) == up;
+                        kr[r] = keep_min ? (kr[r] < o ? kr[r] : o) : (kr[r] > o ? kr[r] : o);
+                    }
                 }
-                __syncthreads();
             }
         }
         // left flags by old position: sorted rank inside the run < n_left
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int r = tid + q * kLocalThreads;
-            if (r >= m) break;
-            const uint64_t key = keys[r];
+        for (int r = 0; r < kPer; ++r) {
+            const int rank = w * kSpan + r * kWave + lane;
+            if (rank >= m) continue;
+            const uint64_t key = kr[r];
             const int i = int(key & 0xfffu), b = int(key >> 44);
-            flag[i] = (rn[b] >= 0 && r - rs[b] < rn[b]) ? 1 : 0;
+            flag[i] = (rn[b] >= 0 && rank - rs[b] < rn[b]) ? 1 : 0;
         }
         __syncthreads();
         {
@@ -688,7 +721,7 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
                 sum += c[q];
             }
             int tot;
-            int run = local_exscan(sum, &tot);
+            int run = local_exscan<kLocalThreads>(sum, &tot);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int i = 4 * tid + q;
@@ -994,12 +1027,17 @@ hipError_t kd_step(KdRun &r)
     if (pl.has_local) {
         const int64_t *nt = nodes + pl.local.node0 * kNodeCols;
         const unsigned nl = unsigned(pl.local.node1 - pl.local.node0);
+        // 512 threads per subtree when every subtree's workgroup is resident
+        // at once with them (three per CU), else 256 (seven per CU)
+        auto go = [&](auto kern, int threads) {
+            kern<<<nl, threads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, r.idx_in, r.vin, r.perm,
+                                        r.vals_sorted);
+        };
+        const bool wide = nl <= kWideLocalBlocks;
         if (P <= 16)
-            k_kd_local<16><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, r.idx_in,
-                                                        r.vin, r.perm, r.vals_sorted);
+            wide ? go(k_kd_local<16, 512>, 512) : go(k_kd_local<16, 256>, 256);
         else
-            k_kd_local<32><<<nl, kLocalThreads, 0, s>>>(nt, n, P, pl.leaf, pl.sub, r.idx_in,
-                                                        r.vin, r.perm, r.vals_sorted);
+            wide ? go(k_kd_local<32, 512>, 512) : go(k_kd_local<32, 256>, 256);
         return hipGetLastError();
     }
     hipError_t e =
