@@ -380,8 +380,19 @@ __global__ __launch_bounds__(kThreads) void k_super_bounds(int64_t ntiles, int P
 template <int PP>
 __device__ __forceinline__ uint64_t box_test(uint64_t alive, const float (&ub)[PP],
                                              const float (&lb)[PP],
-                                             const float *__restrict__ box)
+                                             const float *__restrict__ box_p)
 {
+    // the whole box as two wave-uniform vector loads (one wait per box,
+    // not one per group); boxes are 2 PP floats, aligned to 2 PP * 4 bytes
+    typedef float boxv __attribute__((ext_vector_type(PP)));
+    const boxv lov = *reinterpret_cast<const boxv *>(box_p);
+    const boxv hiv = *reinterpret_cast<const boxv *>(box_p + PP);
+    float box[2 * PP];
+#pragma unroll
+    for (int j = 0; j < PP; ++j) {
+        box[j] = lov[j];
+        box[PP + j] = hiv[j];
+    }
 #pragma unroll
     for (int g = 0; g < PP; g += 4) {
         uint64_t sv;
