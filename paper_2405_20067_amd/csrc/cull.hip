@@ -425,7 +425,8 @@ template <int PP>
 __global__ __launch_bounds__(kThreads) void k_cull_test(
     int64_t k, int64_t ntiles, int64_t tpad, int P, int tiles_per_wave,
     const float *__restrict__ g_ub, const float *__restrict__ g_lb,
-    const float *__restrict__ tbnd, const float *__restrict__ sbnd, uint64_t *__restrict__ masks)
+    const float *__restrict__ tbnd, const float *__restrict__ sbnd, uint64_t *__restrict__ masks,
+    int64_t per_seg, int32_t *__restrict__ seg_cnt)
 {
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int64_t nchunks = (k + kWave - 1) / kWave;
@@ -457,26 +458,16 @@ __global__ __launch_bounds__(kThreads) void k_cull_test(
                 if (lane == int(t - tb)) mine = m;
             }
         }
-        if (tb + lane < te) masks[c * tpad + tb + lane] = mine;
+        if (tb + lane < te) {
+            masks[c * tpad + tb + lane] = mine;
+            // the candidates of each (chunk segment, tile), for the lists'
+            // offsets (integer atomics: the sums do not depend on order)
+            if (mine) atomicAdd(&seg_cnt[(c / per_seg) * ntiles + tb + lane], __popcll(mine));
+        }
     }
 }
 
 // ---- lists ----------------------------------------------------------------
-__global__ __launch_bounds__(kThreads) void k_seg_count(int64_t ntiles, int64_t tpad,
-                                                        int64_t nchunks, int64_t per_seg,
-                                                        const uint64_t *__restrict__ masks,
-                                                        int32_t *__restrict__ seg_cnt)
-{
-    const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (t >= ntiles) return;
-    const int64_t seg = blockIdx.y;
-    const int64_t c0 = seg * per_seg;
-    const int64_t c1 = (c0 + per_seg < nchunks) ? c0 + per_seg : nchunks;
-    int cnt = 0;
-    for (int64_t c = c0; c < c1; ++c) cnt += __popcll(masks[c * tpad + t]);
-    seg_cnt[seg * ntiles + t] = cnt;
-}
-
 __global__ __launch_bounds__(kThreads) void k_seg_prefix(int64_t ntiles, int nseg,
                                                          int32_t *__restrict__ seg_cnt,
                                                          int32_t *__restrict__ tile_cnt,
@@ -800,14 +791,18 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         if (e != hipSuccess) return e;
         return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands, c->item_cnt, c->item_off, c->scan_tmp, s);
     }
-    // interval test
+    // interval test; it also counts the candidates per (chunk segment, tile)
+    const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
+    k_zero_i32<<<nblk(int64_t(c->nseg) * c->ntiles, kThreads), kThreads, 0, s>>>(
+        c->seg_cnt.as<int32_t>(), int64_t(c->nseg) * c->ntiles);
     const int tiles_per_wave = 512;
     dim3 grid(nblk(c->nchunks, kThreads / kWave), nblk(c->ntiles, tiles_per_wave));
 #define NGD_CULL_TEST(PPV)                                                                   \
     k_cull_test<PPV><<<grid, kThreads, 0, s>>>(k, c->ntiles, c->tpad, P, tiles_per_wave,      \
                                                c->g_ub.as<float>(), c->g_lb.as<float>(),     \
                                                c->tbnd.as<float>(), c->sbnd.as<float>(),     \
-                                               c->masks.as<uint64_t>())
+                                               c->masks.as<uint64_t>(), per_seg,              \
+                                               c->seg_cnt.as<int32_t>())
     switch (PP) {
     case 4: NGD_CULL_TEST(4); break;
     case 8: NGD_CULL_TEST(8); break;
@@ -818,10 +813,6 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     }
 #undef NGD_CULL_TEST
     // per-tile counts -> offsets
-    const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
-    dim3 sgrid(nblk(c->ntiles, kThreads), unsigned(c->nseg));
-    k_seg_count<<<sgrid, kThreads, 0, s>>>(c->ntiles, c->tpad, c->nchunks, per_seg,
-                                           c->masks.as<uint64_t>(), c->seg_cnt.as<int32_t>());
     k_seg_prefix<<<nblk(c->ntiles, kThreads), kThreads, 0, s>>>(
         c->ntiles, c->nseg, c->seg_cnt.as<int32_t>(), c->tile_cnt.as<int32_t>(),
         reinterpret_cast<unsigned long long *>(c->stats.as<int64_t>() + 1));
