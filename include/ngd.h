@@ -196,6 +196,19 @@ int ngd_cull_destroy(ngd_cull *cull);
 int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
              int64_t q, int precision, float *out, void *stream);
 
+/* Builds, ahead of ngd_eval, what a forward of `precision` derives once per
+ * cull build: for NGD_BF16_MFMA the per-Gaussian quadratic coefficients,
+ * the tiles' centres and the per-entry centred terms (the matrix-core
+ * forward of Eq. 1-2 expanded); nothing for NGD_FP32.  ngd_eval builds them
+ * itself when they are missing, so this call only moves that work out of
+ * the first forward (for instance to time the forward kernel alone).
+ *   mix, cull, queries, q as for ngd_eval (a cull is required).
+ * Returns NGD_E_INVAL for a NULL handle or an unknown precision,
+ * NGD_E_STALE for a cull of another mixture version or queries.
+ * Does not synchronise. */
+int ngd_eval_prepare(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
+                     int64_t q, int precision, void *stream);
+
 /* Work counters of the culled forward, for measurement (synchronises).
  * Runs the forward kernel of `precision` on the same cull in a counting mode
  * (no colours written) and returns in counts (host, 5 x int64): the

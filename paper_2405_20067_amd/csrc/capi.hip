@@ -457,6 +457,24 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
     return NGD_OK;
 }
 
+int ngd_eval_prepare(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
+                     int64_t q, int precision, void *stream)
+{
+    if (!mix || !cull) return fail(NGD_E_INVAL, "ngd_eval_prepare: NULL handle");
+    if (precision != NGD_FP32 && precision != NGD_BF16_MFMA)
+        return fail(NGD_E_INVAL, "ngd_eval_prepare: unknown precision %d", precision);
+    if (mix->version == 0) return fail(NGD_E_STALE, "ngd_eval_prepare: mixture has no parameters yet");
+    const int rc = check_cull("ngd_eval_prepare", mix, cull, queries, q);
+    if (rc) return rc;
+    if (precision == NGD_FP32 || q == 0 || mix->k == 0 || cull->nitems == 0) return NGD_OK;
+    ngd_cull *mc = const_cast<ngd_cull *>(cull);
+    const int rr = reserve_mfma("ngd_eval_prepare", mc);
+    if (rr) return rr;
+    const hipError_t e = launch_mfma_prepare(mix, mc, S(stream));
+    if (e != hipSuccess) return hip_fail(e, "ngd_eval_prepare");
+    return NGD_OK;
+}
+
 int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
                    int64_t q, int precision, int64_t *counts, void *stream)
 {

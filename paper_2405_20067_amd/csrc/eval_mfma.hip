@@ -605,11 +605,9 @@ __global__ __launch_bounds__(kMThreads, 3) void k_mfma_filter(
 }
 
 template <int N>
-hipError_t mfma_n(ngd_cull *c, float *out, unsigned long long *stats, hipStream_t s)
+hipError_t mfma_prepare_n(ngd_cull *c, hipStream_t s)
 {
     const int tile = c->params.tile;
-    const unsigned gy = unsigned((tile + kMThreads - 1) / kMThreads);
-    const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
     hipError_t e;
     if (c->mrec_seq != c->build_seq) {
         // once per cull build: per-Gaussian quadratic coefficients, tile
@@ -626,6 +624,17 @@ hipError_t mfma_n(ngd_cull *c, float *out, unsigned long long *stats, hipStream_
         if ((e = hipGetLastError()) != hipSuccess) return e;
         c->mrec_seq = c->build_seq;
     }
+    return hipSuccess;
+}
+
+template <int N>
+hipError_t mfma_n(ngd_cull *c, float *out, unsigned long long *stats, hipStream_t s)
+{
+    const int tile = c->params.tile;
+    const unsigned gy = unsigned((tile + kMThreads - 1) / kMThreads);
+    const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
+    hipError_t e = mfma_prepare_n<N>(c, s);
+    if (e != hipSuccess) return e;
     if (c->ntiles > 0) {
         // every tile's workgroup writes its queries' colours (zeros for a
         // tile with no candidates)
@@ -658,6 +667,19 @@ size_t mfma_rec_bytes(int n)
 }
 
 size_t mfma_entry_bytes() { return 4 * sizeof(bf16x8) + sizeof(float4); }
+
+hipError_t launch_mfma_prepare(const ngd_mixture *mix, ngd_cull *c, hipStream_t s)
+{
+    if (c->q == 0 || c->ntiles == 0) return hipSuccess;
+    switch (mix->n) {
+#define NGD_CASE(NN) \
+    case NN: return mfma_prepare_n<NN>(c, s);
+        NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
+        NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
+#undef NGD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_eval_mfma(const ngd_mixture *mix, ngd_cull *c, float *out,
                             unsigned long long *stats, hipStream_t s)

@@ -226,6 +226,9 @@ hipError_t launch_eval_reduce(const ngd_cull *c, float *out, hipStream_t s);
 // stats[0..4] = (group-candidate pairs examined, not skipped by the matrix
 // filter, passed check 1, passed check 2, kept).  Builds the coefficient
 // records (c->mrec, c->mrow, reserved by the caller) once per cull build.
+// The matrix-core coefficient records of the current cull build (once per
+// build; launch_eval_mfma builds them itself when they are missing).
+hipError_t launch_mfma_prepare(const ngd_mixture *mix, ngd_cull *c, hipStream_t s);
 hipError_t launch_eval_mfma(const ngd_mixture *mix, ngd_cull *c, float *out,
                             unsigned long long *stats, hipStream_t s);
 size_t mfma_rec_bytes(int n);

@@ -15,7 +15,8 @@ import numpy as np
 
 __all__ = [
     "NgdError", "CullParams", "Mixture", "Cull", "lib", "LIB_PATH",
-    "eval_mixture", "eval_backward", "eval_stats", "l2_loss", "FP32", "BF16_MFMA",
+    "eval_mixture", "eval_prepare", "eval_backward", "eval_stats", "l2_loss", "FP32",
+    "BF16_MFMA",
     "E_INVAL", "E_SINGULAR", "E_HIP", "E_NOMEM", "E_STALE",
 ]
 
@@ -70,6 +71,9 @@ _SIGS = [
     ("ngd_eval", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
       ctypes.c_void_p, ctypes.c_void_p]),
+    ("ngd_eval_prepare", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
+      ctypes.c_void_p]),
     ("ngd_eval_stats", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int,
       ctypes.POINTER(ctypes.c_int64), ctypes.c_void_p]),
@@ -255,6 +259,14 @@ def eval_mixture(mix: Mixture, cull: Cull | None, queries, out=None, precision=F
                           _ptr(queries, "queries", q * mix.n), q, int(precision),
                           _ptr(out, "out", q * 3), _stream(stream)))
     return out
+
+
+def eval_prepare(mix: Mixture, cull: Cull, queries, precision=FP32, stream=None):
+    """Builds what a forward of `precision` derives once per cull build
+    (ngd_eval does it itself when it is missing)."""
+    q = queries.numel() // mix.n
+    _check(lib().ngd_eval_prepare(mix.handle, cull.handle, _ptr(queries, "queries", q * mix.n),
+                                  q, int(precision), _stream(stream)))
 
 
 def eval_stats(mix: Mixture, cull: Cull, queries, precision=FP32, stream=None):

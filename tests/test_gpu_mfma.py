@@ -159,3 +159,26 @@ def test_mfma_repeat_and_rebuild(torch_cuda):
 def _proj(cfg):
     _, _, proj = case(cfg["n"], cfg["k"], cfg["q"], seed=cfg["n"] * 7 + cfg["k"])
     return proj
+
+
+def test_mfma_prepare_then_eval(torch_cuda):
+    """ngd_eval_prepare builds the coefficient records ahead of the forward:
+    the forward after it is bitwise the forward that builds them itself, for
+    FP32 it is a no-op, and it rejects a cull of another mixture version."""
+    from paper_2405_20067_amd import ngd
+    cfg = dict(n=10, k=1500, q=4100, tile=256)
+    mix, x, m, xd, c = _setup(cfg)
+    a = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    p = ngd.default_params()
+    c.build(m, xd, _proj(cfg), p)
+    ngd.eval_prepare(m, c, xd, precision=ngd.BF16_MFMA)
+    ngd.eval_prepare(m, c, xd, precision=ngd.BF16_MFMA)   # a second call is a no-op
+    b = host(ngd.eval_mixture(m, c, xd, precision=ngd.BF16_MFMA))
+    np.testing.assert_array_equal(a, b)
+    ngd.eval_prepare(m, c, xd, precision=ngd.FP32)
+    full = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x)
+    assert normwise(b, full) <= TOL_FP32
+    m.update(dev(mix["mean"]), dev(mix["factor"]), dev(mix["weight"]), dev(mix["colour"]))
+    with pytest.raises(ngd.NgdError) as ei:
+        ngd.eval_prepare(m, c, xd, precision=ngd.BF16_MFMA)
+    assert ei.value.code == ngd.E_STALE
