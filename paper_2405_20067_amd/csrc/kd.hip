@@ -56,8 +56,14 @@ constexpr int kWidth[3] = {11, 11, 10};
 
 constexpr int kHistThreads = 512;
 
-constexpr int kLocalMax = 1024;
-constexpr unsigned kWideLocalBlocks = 512;   // subtrees for the 512-thread variant     // points per subtree workgroup (<= 4096: 12-bit positions)
+constexpr int kLocalMax = 1024;    // points per subtree workgroup (<= 4096: 12-bit positions)
+constexpr unsigned kWideLocalBlocks = 512;   // subtrees for the 512-thread variant
+// Min / max key slots come in kExtRep planes of max_nodes x P x 2: a
+// workgroup merges into plane (blockIdx.x mod kExtRep), so that the atomics
+// of the many workgroups of one node (all of them, at the root) spread over
+// as many cache lines; readers reduce the planes.
+constexpr int kExtRep = 16;
+constexpr int kRootPer = 4;        // points per thread of the root's extents
 constexpr int kLocalRuns = 128;     // runs per subtree (8-bit run ids)
 constexpr int kLocalSplit = 64;     // runs split at one level of a subtree
 
@@ -121,16 +127,24 @@ __device__ __forceinline__ uint32_t wave_umax_dpp(uint32_t v)
     return v;
 }
 
+// The plane of min / max key slots a workgroup merges into.
+__device__ __forceinline__ uint32_t *ext_plane(uint32_t *ext, int64_t max_nodes, int P)
+{
+    return ext + int64_t(blockIdx.x % kExtRep) * max_nodes * 2 * P;
+}
+
 // Clears the histograms; resets the root's min / max key slots (P
-// projections) to their identities.
+// projections, every plane) to their identities.
 __global__ __launch_bounds__(kThreads) void k_kd_zero(int32_t *__restrict__ p, int64_t n,
-                                                      uint32_t *__restrict__ ext, int P)
+                                                      uint32_t *__restrict__ ext, int P,
+                                                      int64_t max_nodes)
 {
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i < n) p[i] = 0;
-    if (i < P) {
-        ext[2 * i + 0] = 0xffffffffu;
-        ext[2 * i + 1] = 0u;
+    if (i < int64_t(P) * kExtRep) {
+        uint32_t *e = ext + (i / P) * max_nodes * 2 * P + 2 * (i % P);
+        e[0] = 0xffffffffu;
+        e[1] = 0u;
     }
 }
 
@@ -167,32 +181,36 @@ __device__ void block_merge_ext(const uint32_t (&kmin)[PMAX], const uint32_t (&k
     __syncthreads();
 }
 
-// The root's min / max over its slices.
+// The root's min / max: kRootPer points per thread, all P of their loads
+// in flight together.
 template <int PMAX>
-__global__ __launch_bounds__(kThreads) void k_kd_root_ext(const int64_t *__restrict__ slices,
-                                                          int64_t n, int P,
+__global__ __launch_bounds__(kThreads) void k_kd_root_ext(int64_t n, int P,
                                                           const float *__restrict__ vin,
-                                                          uint32_t *__restrict__ ext)
+                                                          uint32_t *__restrict__ ext,
+                                                          int64_t max_nodes)
 {
-    const int64_t sl = blockIdx.x;
-    const int64_t s0 = slices[sl * kSliceCols + 0], len = slices[sl * kSliceCols + 1];
     uint32_t kmin[PMAX], kmax[PMAX];
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) {
         kmin[j] = 0xffffffffu;
         kmax[j] = 0u;
     }
-    for (int64_t i = threadIdx.x; i < len; i += kThreads) {
+    const int64_t i0 = int64_t(blockIdx.x) * kThreads * kRootPer + threadIdx.x;
 #pragma unroll
-        for (int j = 0; j < PMAX; ++j) {
-            if (j < P) {
-                const uint32_t key = orderable(vin[int64_t(j) * n + s0 + i]);
-                kmin[j] = min(kmin[j], key);
-                kmax[j] = max(kmax[j], key);
+    for (int u = 0; u < kRootPer; ++u) {
+        const int64_t i = i0 + int64_t(u) * kThreads;
+        if (i < n) {
+#pragma unroll
+            for (int j = 0; j < PMAX; ++j) {
+                if (j < P) {
+                    const uint32_t key = orderable(vin[int64_t(j) * n + i]);
+                    kmin[j] = min(kmin[j], key);
+                    kmax[j] = max(kmax[j], key);
+                }
             }
         }
     }
-    block_merge_ext<PMAX>(kmin, kmax, P, ext, 0);
+    block_merge_ext<PMAX>(kmin, kmax, P, ext_plane(ext, max_nodes, P), 0);
 }
 
 // Block exclusive scan of one int64 per thread (THREADS threads).
@@ -281,14 +299,31 @@ __global__ __launch_bounds__(kHistThreads) void k_kd_hist(
         if (round == 0 && first && threadIdx.x == 0) dim[nd] = -1;
         return;
     }
+    // the slice's keys of projection d, loaded before the previous round's
+    // selection so that the two latencies overlap
+    constexpr int kPer = kHistSlice / kHistThreads;
+    uint32_t keys[kPer];
+    auto load_keys = [&](int d) {
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t i = threadIdx.x + int64_t(u) * kHistThreads;
+            keys[u] = i < len ? orderable(vin[int64_t(d) * n + s0 + i]) : 0u;
+        }
+    };
     uint32_t pre = 0u;
     int d;
     if (round == 0) {
         // the projection of largest extent, the first on ties
         if (int(threadIdx.x) < P) {
             const int j = threadIdx.x;
-            s_ext[j] = from_orderable(ext[(nd * P + j) * 2 + 1]) -
-                       from_orderable(ext[(nd * P + j) * 2 + 0]);
+            uint32_t lo = 0xffffffffu, hi = 0u;
+#pragma unroll 4
+            for (int e = 0; e < kExtRep; ++e) {
+                const uint32_t *x = ext + int64_t(e) * max_nodes * 2 * P + (nd * P + j) * 2;
+                lo = min(lo, x[0]);
+                hi = max(hi, x[1]);
+            }
+            s_ext[j] = from_orderable(hi) - from_orderable(lo);
         }
         __syncthreads();
         if (threadIdx.x == 0) {
@@ -299,16 +334,22 @@ __global__ __launch_bounds__(kHistThreads) void k_kd_hist(
         }
         __syncthreads();
         d = s_dim;
+        load_keys(d);
         if (first) {
             if (threadIdx.x == 0) dim[nd] = d;
             const int64_t ch = row[5];
-            if (ext_next && ch >= 0 && int(threadIdx.x) < 2 * P) {   // both children's slots
-                ext_next[(ch * P + threadIdx.x) * 2 + 0] = 0xffffffffu;
-                ext_next[(ch * P + threadIdx.x) * 2 + 1] = 0u;
+            if (ext_next && ch >= 0) {   // both children's slots, every plane
+                for (int t = threadIdx.x; t < 2 * P * kExtRep; t += kHistThreads) {
+                    uint32_t *x = ext_next + int64_t(t / (2 * P)) * max_nodes * 2 * P +
+                                  (ch * P + t % (2 * P)) * 2;
+                    x[0] = 0xffffffffu;
+                    x[1] = 0u;
+                }
             }
         }
     } else {
         d = dim[nd];
+        load_keys(d);
         const uint32_t p0 = round == 1 ? 0u : sel_pre[nd];
         const int64_t r0 = round == 1 ? nleft : sel_rank[nd];
         int64_t r1;
@@ -323,11 +364,12 @@ __global__ __launch_bounds__(kHistThreads) void k_kd_hist(
     __syncthreads();
     const int shift = kShift[round], width = kWidth[round];
     const uint32_t mask = (1u << width) - 1u;
-#pragma unroll 8
-    for (int64_t i = threadIdx.x; i < len; i += kHistThreads) {
-        const uint32_t key = orderable(vin[int64_t(d) * n + s0 + i]);
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const uint32_t key = keys[u];
+        const bool valid = threadIdx.x + int64_t(u) * kHistThreads < len;
         const bool match = (round == 0) || ((key >> (shift + width)) == pre);
-        if (match) atomicAdd(&h[(key >> shift) & mask], 1);
+        if (valid && match) atomicAdd(&h[(key >> shift) & mask], 1);
     }
     __syncthreads();
     int32_t *nh = hist + (round * max_nodes + nd) * kBins;
@@ -350,6 +392,14 @@ __global__ __launch_bounds__(kThreads) void k_kd_count(
     const int d = dim[nd];
     int64_t less = 0, eq = 0;
     if (d >= 0) {   // uniform
+        // the slice's keys first: their loads overlap the selection
+        constexpr int kPer = kSlice / kThreads;
+        uint32_t keys[kPer];
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const int64_t i = threadIdx.x + int64_t(u) * kThreads;
+            keys[u] = i < len ? orderable(vin[int64_t(d) * n + s0 + i]) : 0u;
+        }
         uint32_t pivot;
         int64_t r;
         block_select<kThreads>(hist + (2 * max_nodes + nd) * kBins, kWidth[2],
@@ -358,10 +408,11 @@ __global__ __launch_bounds__(kThreads) void k_kd_count(
             sel_pre[2 * max_nodes + nd] = pivot;
             sel_rank[2 * max_nodes + nd] = r;
         }
-        for (int64_t i = threadIdx.x; i < len; i += kThreads) {
-            const uint32_t key = orderable(vin[int64_t(d) * n + s0 + i]);
-            less += key < pivot;
-            eq += key == pivot;
+#pragma unroll
+        for (int u = 0; u < kPer; ++u) {
+            const bool valid = threadIdx.x + int64_t(u) * kThreads < len;
+            less += valid && keys[u] < pivot;
+            eq += valid && keys[u] == pivot;
         }
     }
     int64_t tl, te;
@@ -418,13 +469,13 @@ __global__ __launch_bounds__(kThreads) void k_kd_scatter(
         }
         return;
     }
-    // points below the pivot, and equal to it, in the node's earlier slices
-    const int64_t sb = row[3] - slice0;
+    const int64_t sb = row[3] - slice0;   // the node's first slice
     if (sl == sb) {   // the node's histograms, clean for the next level
         for (int r = 0; r < 3; ++r)
             for (int b = threadIdx.x; b < kBins; b += kThreads)
                 hist[(r * max_nodes + nd) * kBins + b] = 0;
     }
+    // points below the pivot, and equal to it, in the node's earlier slices
     int64_t l_mine = 0, e_mine = 0;
     for (int64_t s = sb + threadIdx.x; s < sl; s += kThreads) {
         l_mine += cnt[s * 2 + 0];
@@ -488,8 +539,9 @@ __global__ __launch_bounds__(kThreads) void k_kd_scatter(
         }
     }
     if (track) {   // uniform
-        block_merge_ext<PMAX>(lmin, lmax, P, ext_next, ch);
-        block_merge_ext<PMAX>(rmin, rmax, P, ext_next, ch + 1);
+        uint32_t *plane = ext_plane(ext_next, max_nodes, P);
+        block_merge_ext<PMAX>(lmin, lmax, P, plane, ch);
+        block_merge_ext<PMAX>(rmin, rmax, P, plane, ch + 1);
     }
 }
 
@@ -918,8 +970,8 @@ bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P)
     ok &= w.idx[1].ensure(sizeof(int32_t) * nn);
     ok &= w.val[0].ensure(sizeof(float) * P * nn);
     ok &= w.val[1].ensure(sizeof(float) * P * nn);
-    ok &= w.ext[0].ensure(sizeof(uint32_t) * 2 * P * mn);
-    ok &= w.ext[1].ensure(sizeof(uint32_t) * 2 * P * mn);
+    ok &= w.ext[0].ensure(sizeof(uint32_t) * 2 * P * mn * kExtRep);
+    ok &= w.ext[1].ensure(sizeof(uint32_t) * 2 * P * mn * kExtRep);
     ok &= w.hist.ensure(sizeof(int32_t) * 3 * kBins * mn);
     ok &= w.cnt.ensure(sizeof(int64_t) * 2 * ms);
     ok &= w.dim.ensure(sizeof(int32_t) * mn);
@@ -948,8 +1000,8 @@ hipError_t kd_start(KdRun &r, const KdPlan &pl, KdWork &w, int P, const float *v
         w.idx[0].cap < sizeof(int32_t) * size_t(n) || w.idx[1].cap < sizeof(int32_t) * size_t(n) ||
         w.val[0].cap < sizeof(float) * P * size_t(n) ||
         w.val[1].cap < sizeof(float) * P * size_t(n) ||
-        w.ext[0].cap < sizeof(uint32_t) * 2 * P * size_t(mn) ||
-        w.ext[1].cap < sizeof(uint32_t) * 2 * P * size_t(mn) ||
+        w.ext[0].cap < sizeof(uint32_t) * 2 * P * size_t(mn) * kExtRep ||
+        w.ext[1].cap < sizeof(uint32_t) * 2 * P * size_t(mn) * kExtRep ||
         w.hist.cap < sizeof(int32_t) * 3 * kBins * size_t(mn) ||
         w.cnt.cap < sizeof(int64_t) * 2 * size_t(ms) || w.dim.cap < sizeof(int32_t) * size_t(mn) ||
         w.prefix.cap < sizeof(uint32_t) * 3 * size_t(mn) ||
@@ -980,16 +1032,13 @@ hipError_t kd_step(KdRun &r)
     const size_t phase = r.phase++;
     if (phase == 0) {   // the root's extents
         if (nlev == 0) return hipSuccess;
-        k_kd_zero<<<nb(3 * kBins * mn, kThreads), kThreads, 0, s>>>(hist, 3 * kBins * mn,
-                                                                    w.ext[0].as<uint32_t>(), P);
-        const KdLevel &lv = pl.levels[0];
-        const int64_t *st = slices + lv.slice0 * kSliceCols;
+        k_kd_zero<<<nb(3 * kBins * mn, kThreads), kThreads, 0, s>>>(
+            hist, 3 * kBins * mn, w.ext[0].as<uint32_t>(), P, mn);
+        const unsigned nr = nb(n, kThreads * kRootPer);
         if (P <= 16)
-            k_kd_root_ext<16><<<unsigned(lv.slice1 - lv.slice0), kThreads, 0, s>>>(
-                st, n, P, r.vals, w.ext[0].as<uint32_t>());
+            k_kd_root_ext<16><<<nr, kThreads, 0, s>>>(n, P, r.vals, w.ext[0].as<uint32_t>(), mn);
         else
-            k_kd_root_ext<32><<<unsigned(lv.slice1 - lv.slice0), kThreads, 0, s>>>(
-                st, n, P, r.vals, w.ext[0].as<uint32_t>());
+            k_kd_root_ext<32><<<nr, kThreads, 0, s>>>(n, P, r.vals, w.ext[0].as<uint32_t>(), mn);
         return hipGetLastError();
     }
     if (phase <= nlev) {   // upper level phase - 1

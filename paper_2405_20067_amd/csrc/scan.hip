@@ -48,11 +48,14 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int32_t *__r
                                                               int64_t n,
                                                               int64_t *__restrict__ bsum)
 {
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanItems;
+    // a sum: the block's items are read coalesced, in any order
+    const int64_t b0 = int64_t(blockIdx.x) * kScanBlock + threadIdx.x;
     int64_t acc = 0;
 #pragma unroll
-    for (int j = 0; j < kScanItems; ++j)
-        if (base + j < n) acc += in[base + j];
+    for (int j = 0; j < kScanItems; ++j) {
+        const int64_t g = b0 + int64_t(j) * kScanThreads;
+        if (g < n) acc += in[g];
+    }
     int64_t tot;
     block_exclusive_scan64(acc, &tot);
     if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
@@ -72,27 +75,48 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_top(int64_t *__restrict__
     }
 }
 
+// Item i of a block at LDS slot i + i / kScanItems: a thread's run of
+// kScanItems consecutive items then sits at stride kScanItems + 1.
+__device__ __forceinline__ int scan_slot(int i) { return i + i / kScanItems; }
+
 __global__ __launch_bounds__(kScanThreads) void k_scan_down(const int32_t *__restrict__ in,
                                                             int64_t n,
                                                             const int64_t *__restrict__ boff,
                                                             int64_t *__restrict__ out)
 {
-    const int64_t base = int64_t(blockIdx.x) * kScanBlock + int64_t(threadIdx.x) * kScanItems;
-    int32_t v[kScanItems];
+    // Coalesced in and out through LDS; in between each thread scans its
+    // run of kScanItems consecutive items.
+    __shared__ int64_t sb[kScanBlock + kScanBlock / kScanItems];
+    const int64_t b0 = int64_t(blockIdx.x) * kScanBlock;
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int i = threadIdx.x + j * kScanThreads;
+        sb[scan_slot(i)] = (b0 + i < n) ? in[b0 + i] : 0;
+    }
+    __syncthreads();
+    const int t0 = threadIdx.x * kScanItems;
+    int64_t v[kScanItems];
     int64_t acc = 0;
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        v[j] = (base + j < n) ? in[base + j] : 0;
+        v[j] = sb[scan_slot(t0 + j)];
         acc += v[j];
     }
     int64_t tot;
-    int64_t run = boff[blockIdx.x] + block_exclusive_scan64(acc, &tot);
+    int64_t run = boff[blockIdx.x] + block_exclusive_scan64(acc, &tot);   // syncs
 #pragma unroll
     for (int j = 0; j < kScanItems; ++j) {
-        if (base + j < n) out[base + j] = run;
+        sb[scan_slot(t0 + j)] = run;
         run += v[j];
     }
+    const int64_t base = b0 + t0;
     if (base < n && base + kScanItems >= n) out[n] = run;   // thread holding the last item
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kScanItems; ++j) {
+        const int i = threadIdx.x + j * kScanThreads;
+        if (b0 + i < n) out[b0 + i] = sb[scan_slot(i)];
+    }
 }
 
 __global__ void k_fill_i64(int64_t *p, int64_t n, int64_t v)
