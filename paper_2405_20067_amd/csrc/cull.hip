@@ -473,16 +473,27 @@ __global__ __launch_bounds__(kThreads) void k_seg_prefix(int64_t ntiles, int nse
                                                          int32_t *__restrict__ tile_cnt,
                                                          unsigned long long *__restrict__ maxc)
 {
+    // per tile, the exclusive prefix of its segments' counts; kU loads in
+    // flight at a time; the longest list by one atomic per wave
+    constexpr int kU = 16;
     const int64_t t = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (t >= ntiles) return;
+    const bool ok = t < ntiles;
     int run = 0;
-    for (int seg = 0; seg < nseg; ++seg) {
-        const int v = seg_cnt[int64_t(seg) * ntiles + t];
-        seg_cnt[int64_t(seg) * ntiles + t] = run;
-        run += v;
+    for (int seg = 0; seg < nseg; seg += kU) {
+        int v[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            v[u] = (ok && seg + u < nseg) ? seg_cnt[int64_t(seg + u) * ntiles + t] : 0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (ok && seg + u < nseg) seg_cnt[int64_t(seg + u) * ntiles + t] = run;
+            run += v[u];
+        }
     }
-    tile_cnt[t] = run;
-    atomicMax(maxc, static_cast<unsigned long long>(run));
+    if (ok) tile_cnt[t] = run;
+    // counts are non-negative: their bit patterns order as unsigned
+    const int most = __float_as_int(wave_max_nonneg(__int_as_float(run)));
+    if (lane_id() == 0) atomicMax(maxc, static_cast<unsigned long long>(most));
 }
 
 // Candidate lists from the masks: one workgroup per (64 tiles, chunk
@@ -976,9 +987,9 @@ bool cull_reserve_lists(ngd_cull *c)
     ok &= c->keys1.ensure(sizeof(uint32_t) * tot);
     ok &= c->vals0.ensure(sizeof(int32_t) * tot);
     ok &= c->vals1.ensure(sizeof(int32_t) * tot);
-    ok &= c->radix_hist.ensure(sizeof(int32_t) * 256 * nb);
-    ok &= c->radix_off.ensure(sizeof(int64_t) * (256 * nb + 1));
-    ok &= c->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>({256 * nb, T, kk, tot})));
+    ok &= c->radix_hist.ensure(sizeof(int32_t) * kRadixMaxBins * nb);
+    ok &= c->radix_off.ensure(sizeof(int64_t) * (kRadixMaxBins * nb + 1));
+    ok &= c->scan_tmp.ensure(scan_tmp_bytes(std::max<int64_t>({kRadixMaxBins * nb, T, kk, tot})));
     ok &= c->item_tile.ensure(sizeof(int32_t) * size_t(c->nitems > 0 ? c->nitems : 1));
     ok &= c->fpart.ensure(sizeof(float) * 3 * size_t(c->nitems) * size_t(c->params.tile));
     ok &= c->gitem_g.ensure(sizeof(int32_t) * size_t(c->gitems_cap > 0 ? c->gitems_cap : 1));
@@ -996,7 +1007,7 @@ bool cull_reserve_front(ngd_cull *c)
     const int64_t qk = std::max(qq, kk);
     const int64_t nb_sort = (qk + kRadixPerBlock - 1) / kRadixPerBlock;
     const int64_t nparts = (qq + kThreads - 1) / kThreads;
-    const int64_t scan_n = std::max<int64_t>({256 * nb_sort, T, kk});
+    const int64_t scan_n = std::max<int64_t>({kRadixMaxBins * nb_sort, T, kk});
     bool ok = true;
     ok &= c->proj.ensure(sizeof(float) * P * n);
     ok &= c->qr.ensure(sizeof(float) * P * qq);
@@ -1008,8 +1019,8 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->keys1.ensure(sizeof(uint32_t) * qk);
     ok &= c->vals0.ensure(sizeof(int32_t) * qk);
     ok &= c->vals1.ensure(sizeof(int32_t) * qk);
-    ok &= c->radix_hist.ensure(sizeof(int32_t) * 256 * nb_sort);
-    ok &= c->radix_off.ensure(sizeof(int64_t) * (256 * nb_sort + 1));
+    ok &= c->radix_hist.ensure(sizeof(int32_t) * kRadixMaxBins * nb_sort);
+    ok &= c->radix_off.ensure(sizeof(int64_t) * (kRadixMaxBins * nb_sort + 1));
     ok &= c->perm.ensure(sizeof(int32_t) * qq);
     ok &= c->gperm.ensure(sizeof(int32_t) * kk);
     ok &= c->qs.ensure(sizeof(float) * n * qq);

@@ -251,9 +251,11 @@ hipError_t launch_l2_loss(const float *f, const float *target, int64_t q, float 
 // Stable LSD radix sort of (key, value) pairs by the low nbits of the keys,
 // kRadixPerBlock keys per block.  n is the count, or an upper bound when
 // n_dev (a device count) is given.  Buffers: keys/vals ping-pong of n,
-// hist 256 x blocks int32, off 256 x blocks + 1 int64, scan_tmp for a scan
-// of 256 x blocks.  *which tells which ping-pong buffer holds the result.
+// hist kRadixMaxBins x blocks int32, off kRadixMaxBins x blocks + 1 int64,
+// scan_tmp for a scan of kRadixMaxBins x blocks.  *which tells which
+// ping-pong buffer holds the result.
 constexpr int kRadixPerBlock = 4096;
+constexpr int kRadixMaxBins = 1024;   // digits of up to 10 bits
 // Tiles per super-tile of the interval test (a k-d node of 16 tiles): a
 // chunk of Gaussians outside a super-tile's bounds is outside each of its
 // tiles' bounds.

@@ -1,10 +1,12 @@
-// Stable LSD radix sort of (key, value) pairs, 8-bit digits.
+// Stable LSD radix sort of (key, value) pairs, digits of up to 10 bits.
 //
-// Per pass: each block counts the digits of its 4096 keys (a histogram in
-// LDS), one exclusive scan turns the digit-major counts into output offsets,
-// and each block scatters its keys in order: every wave ranks its 64 keys
-// among equal digits with ballots (a match mask built from the 8 digit bits,
-// popcount of the lower lanes), so equal keys keep their input order.
+// The key bits are split into the fewest passes of at most kRadixMaxBits
+// (18 bits: two passes of 9).  Per pass: each block counts the digits of
+// its 4096 keys (a histogram in LDS), one exclusive scan turns the
+// digit-major counts into output offsets, and each block scatters its keys
+// in order: every wave ranks its 64 keys among equal digits with ballots (a
+// match mask built from the digit's bits, popcount of the lower lanes), so
+// equal keys keep their input order.
 // The element count may live on the device (n_dev) with the host giving an
 // upper bound: blocks past the count only write zero histogram columns.
 #include <utility>
@@ -15,11 +17,13 @@
 namespace ngd {
 namespace {
 
-// ---- stable LSD radix sort (8-bit digits) ------------------------------
+// ---- stable LSD radix sort ----------------------------------------------
 constexpr int kThreads = 256;
+constexpr int kRadixMaxBits = 10;
 constexpr int kRadixItems = 16;                        // per lane
 constexpr int kRadixPerWave = kRadixItems * kWave;     // 1024
 static_assert(kRadixPerWave * (kThreads / kWave) == kRadixPerBlock, "block size");
+static_assert((1 << kRadixMaxBits) == kRadixMaxBins, "bins");
 
 // Element count: the host bound, or the device count when one is given.
 __device__ __forceinline__ int64_t count_of(int64_t n_max, const int64_t *n_dev)
@@ -30,45 +34,52 @@ __device__ __forceinline__ int64_t count_of(int64_t n_max, const int64_t *n_dev)
 }
 
 __global__ __launch_bounds__(kThreads) void k_radix_count(int64_t n_max, const int64_t *n_dev,
-                                                          int shift,
+                                                          int shift, int width,
                                                           const uint32_t *__restrict__ keys,
                                                           int32_t *__restrict__ hist,
                                                           int64_t nblocks)
 {
-    __shared__ int cnt[256];
+    __shared__ int cnt[kRadixMaxBins];
     const int64_t n = count_of(n_max, n_dev);
-    cnt[threadIdx.x] = 0;
+    const int bins = 1 << width;
+    const uint32_t mask = uint32_t(bins - 1);
+    for (int b = threadIdx.x; b < bins; b += kThreads) cnt[b] = 0;
     __syncthreads();
     const int64_t base = int64_t(blockIdx.x) * kRadixPerBlock;
     for (int it = threadIdx.x; it < kRadixPerBlock; it += kThreads) {
         const int64_t i = base + it;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & 0xffu], 1);
+        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1);
     }
     __syncthreads();
-    hist[int64_t(threadIdx.x) * nblocks + blockIdx.x] = cnt[threadIdx.x];
+    for (int b = threadIdx.x; b < bins; b += kThreads)
+        hist[int64_t(b) * nblocks + blockIdx.x] = cnt[b];
 }
 
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(
-    int64_t n_max, const int64_t *n_dev, int shift, const uint32_t *__restrict__ keys_in,
+    int64_t n_max, const int64_t *n_dev, int shift, int width,
+    const uint32_t *__restrict__ keys_in,
     const int32_t *__restrict__ vals_in, uint32_t *__restrict__ keys_out,
     int32_t *__restrict__ vals_out, const int64_t *__restrict__ off, int64_t nblocks)
 {
     constexpr int W = kThreads / kWave;
-    __shared__ int wcnt[W][256];
-    __shared__ int wbase[W][256];
+    __shared__ int wcnt[W][kRadixMaxBins];
+    __shared__ int wbase[W][kRadixMaxBins];
     const int64_t n = count_of(n_max, n_dev);
     const int w = threadIdx.x / kWave, lane = lane_id();
+    const int bins = 1 << width;
+    const uint32_t mask = uint32_t(bins - 1);
+    for (int b = threadIdx.x; b < bins; b += kThreads) {
 #pragma unroll
-    for (int i = 0; i < W; ++i) wcnt[i][threadIdx.x] = 0;
+        for (int i = 0; i < W; ++i) wcnt[i][b] = 0;
+    }
     __syncthreads();
     const int64_t wstart = int64_t(blockIdx.x) * kRadixPerBlock + int64_t(w) * kRadixPerWave;
     for (int it = 0; it < kRadixItems; ++it) {
         const int64_t i = wstart + int64_t(it) * kWave + lane;
-        if (i < n) atomicAdd(&wcnt[w][(keys_in[i] >> shift) & 0xffu], 1);
+        if (i < n) atomicAdd(&wcnt[w][(keys_in[i] >> shift) & mask], 1);
     }
     __syncthreads();
-    {
-        const int d = threadIdx.x;
+    for (int d = threadIdx.x; d < bins; d += kThreads) {
         int run = int(off[int64_t(d) * nblocks + blockIdx.x]);
 #pragma unroll
         for (int i = 0; i < W; ++i) {
@@ -81,10 +92,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         const int64_t i = wstart + int64_t(it) * kWave + lane;
         const bool valid = i < n;
         const uint32_t key = valid ? keys_in[i] : 0u;
-        const int d = int((key >> shift) & 0xffu);
+        const int d = int((key >> shift) & mask);
         uint64_t match = ballot(valid);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < width; ++b) {
             const bool bit = (d >> b) & 1;
             const uint64_t m = ballot(valid && bit);
             match &= bit ? m : ~m;
@@ -115,20 +125,24 @@ hipError_t radix_sort(int64_t n, const int64_t *n_dev, int nbits, DevBuf &k0, De
     if (n == 0) return hipSuccess;
     const int64_t nb = (n + kRadixPerBlock - 1) / kRadixPerBlock;
     const size_t kv = sizeof(uint32_t) * size_t(n);
-    if (k0.cap < kv || k1.cap < kv || v0.cap < kv || v1.cap < kv ||
-        hist_buf.cap < sizeof(int32_t) * size_t(256 * nb))
+    if (nbits < 0 || nbits > 32 || k0.cap < kv || k1.cap < kv || v0.cap < kv || v1.cap < kv ||
+        hist_buf.cap < sizeof(int32_t) * size_t(kRadixMaxBins * nb))
         return hipErrorInvalidValue;
+    // the fewest passes of at most kRadixMaxBits, the bits spread evenly
+    const int passes = (nbits + kRadixMaxBits - 1) / kRadixMaxBits;
+    const int width = passes > 0 ? (nbits + passes - 1) / passes : 0;
     int32_t *hist = hist_buf.as<int32_t>();
     const int64_t *off = off_buf.as<int64_t>();
     uint32_t *kin = k0.as<uint32_t>(), *kout = k1.as<uint32_t>();
     int32_t *vin = v0.as<int32_t>(), *vout = v1.as<int32_t>();
-    for (int shift = 0; shift < nbits; shift += 8) {
-        k_radix_count<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, n_dev, shift, kin, hist, nb);
-        hipError_t e = scan_counts(hist_buf, off_buf, 256 * nb, scan_tmp, s);
+    for (int p = 0; p < passes; ++p) {
+        const int shift = p * width;
+        const int wd = shift + width <= 32 ? width : 32 - shift;
+        k_radix_count<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, n_dev, shift, wd, kin, hist, nb);
+        hipError_t e = scan_counts(hist_buf, off_buf, (int64_t(1) << wd) * nb, scan_tmp, s);
         if (e != hipSuccess) return e;
-        k_radix_scatter<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, n_dev, shift, kin, vin, kout,
-                                                               vout,
-                                                               off, nb);
+        k_radix_scatter<<<dim3(unsigned(nb)), kThreads, 0, s>>>(n, n_dev, shift, wd, kin, vin,
+                                                               kout, vout, off, nb);
         std::swap(kin, kout);
         std::swap(vin, vout);
         *which ^= 1;
