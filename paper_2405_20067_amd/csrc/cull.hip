@@ -70,14 +70,17 @@ __global__ __launch_bounds__(kThreads) void k_gauss_proj(int64_t k, int P,
     }
 }
 
-template <int N, int PMAX>
+// The queries' projections (P x q, SoA) and per block each projection's
+// min and max: as floats (KEYS false: the range of the locality keys), or as
+// order-preserving keys (KEYS true: the k-d root's extents).
+template <int N, int PMAX, bool KEYS>
 __global__ __launch_bounds__(kThreads) void k_query_proj(int64_t q, int P,
                                                          const float *__restrict__ queries,
                                                          const float *__restrict__ proj,
                                                          float *__restrict__ qr,
                                                          float *__restrict__ part)
 {
-    __shared__ float smin[kThreads / kWave][PMAX], smax[kThreads / kWave][PMAX];
+    __shared__ uint32_t smin[kThreads / kWave][PMAX], smax[kThreads / kWave][PMAX];
     const int64_t p = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     const bool valid = p < q;
     const int w = threadIdx.x / kWave;
@@ -91,25 +94,47 @@ __global__ __launch_bounds__(kThreads) void k_query_proj(int64_t q, int P,
 #pragma unroll
             for (int a = 0; a < N; ++a) acc = fmaf(x[a], proj[j * N + a], acc);
             if (valid) qr[j * q + p] = acc;
-            const float lo = wave_min(valid ? acc : INFINITY);
-            const float hi = wave_max(valid ? acc : -INFINITY);
-            if (lane_id() == 0) {
-                smin[w][j] = lo;
-                smax[w][j] = hi;
+            if constexpr (KEYS) {
+                const uint32_t key = orderable(acc);
+                const uint32_t lo = wave_umin_dpp(valid ? key : 0xffffffffu);
+                const uint32_t hi = wave_umax_dpp(valid ? key : 0u);
+                if (lane_id() == kWave - 1) {
+                    smin[w][j] = lo;
+                    smax[w][j] = hi;
+                }
+            } else {
+                const float lo = wave_min(valid ? acc : INFINITY);
+                const float hi = wave_max(valid ? acc : -INFINITY);
+                if (lane_id() == 0) {
+                    smin[w][j] = __float_as_uint(lo);
+                    smax[w][j] = __float_as_uint(hi);
+                }
             }
         }
     }
     __syncthreads();
     if (threadIdx.x < P) {
         const int j = threadIdx.x;
-        float lo = INFINITY, hi = -INFINITY;
+        uint32_t *pk = reinterpret_cast<uint32_t *>(part);
+        if constexpr (KEYS) {
+            uint32_t lo = 0xffffffffu, hi = 0u;
 #pragma unroll
-        for (int i = 0; i < kThreads / kWave; ++i) {
-            lo = fminf(lo, smin[i][j]);
-            hi = fmaxf(hi, smax[i][j]);
+            for (int i = 0; i < kThreads / kWave; ++i) {
+                lo = min(lo, smin[i][j]);
+                hi = max(hi, smax[i][j]);
+            }
+            pk[(int64_t(blockIdx.x) * P + j) * 2 + 0] = lo;
+            pk[(int64_t(blockIdx.x) * P + j) * 2 + 1] = hi;
+        } else {
+            float lo = INFINITY, hi = -INFINITY;
+#pragma unroll
+            for (int i = 0; i < kThreads / kWave; ++i) {
+                lo = fminf(lo, __uint_as_float(smin[i][j]));
+                hi = fmaxf(hi, __uint_as_float(smax[i][j]));
+            }
+            part[(int64_t(blockIdx.x) * P + j) * 2 + 0] = lo;
+            part[(int64_t(blockIdx.x) * P + j) * 2 + 1] = hi;
         }
-        part[(int64_t(blockIdx.x) * P + j) * 2 + 0] = lo;
-        part[(int64_t(blockIdx.x) * P + j) * 2 + 1] = hi;
     }
 }
 
@@ -142,6 +167,37 @@ __global__ __launch_bounds__(kThreads) void k_range_final(int64_t nparts, int P,
     qrange[P + j] = hi;
     qrange[2 * P + j] =
         (hi > lo) ? float(double(1u << key_bits) / (double(hi) - double(lo))) : 0.0f;
+}
+
+// The k-d root's extents from the per-block key partials: ext[2j] and
+// ext[2j + 1] get projection j's min and max key; one block per projection.
+__global__ __launch_bounds__(kThreads) void k_root_keys(int64_t nparts, int P,
+                                                        const float *__restrict__ part,
+                                                        uint32_t *__restrict__ ext)
+{
+    __shared__ uint32_t slo[kThreads / kWave], shi[kThreads / kWave];
+    const int j = blockIdx.x;
+    const uint32_t *pk = reinterpret_cast<const uint32_t *>(part);
+    uint32_t lo = 0xffffffffu, hi = 0u;
+    for (int64_t b = threadIdx.x; b < nparts; b += kThreads) {
+        lo = min(lo, pk[(b * P + j) * 2 + 0]);
+        hi = max(hi, pk[(b * P + j) * 2 + 1]);
+    }
+    lo = wave_umin_dpp(lo);
+    hi = wave_umax_dpp(hi);
+    if (lane_id() == kWave - 1) {
+        slo[threadIdx.x / kWave] = lo;
+        shi[threadIdx.x / kWave] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+#pragma unroll
+    for (int i = 0; i < kThreads / kWave; ++i) {
+        lo = min(lo, slo[i]);
+        hi = max(hi, shi[i]);
+    }
+    ext[2 * j + 0] = lo;
+    ext[2 * j + 1] = hi;
 }
 
 // Locality key of row i of a P x n SoA array of projections.
@@ -679,16 +735,30 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
             c->g_mr.as<float>(), c->g_thr.as<float>());
     }
     const int64_t nparts = (q + kThreads - 1) / kThreads;
+    // With the k-d tiling of the queries the projection kernel's block
+    // extents are taken as keys, and their reduction is the root's extents
+    // of the queries' k-d order (no pass of its own over the projections).
+    const bool kd_queries = c->params.tiling == 0 && q > std::min(c->params.tile, kWave);
+    const bool root_keys =
+        kd_queries && c->kd_work.ext[0].cap >= sizeof(uint32_t) * 2 * size_t(P);
     if (q > 0) {
-        if (P <= 16)
-            k_query_proj<N, 16><<<nblk(q, kThreads), kThreads, 0, s>>>(
-                q, P, queries, c->proj.as<float>(), c->qr.as<float>(), c->range_part.as<float>());
+        auto go = [&](auto kern) {
+            kern<<<nblk(q, kThreads), kThreads, 0, s>>>(q, P, queries, c->proj.as<float>(),
+                                                        c->qr.as<float>(),
+                                                        c->range_part.as<float>());
+        };
+        if (root_keys)
+            P <= 16 ? go(k_query_proj<N, 16, true>) : go(k_query_proj<N, 32, true>);
         else
-            k_query_proj<N, 32><<<nblk(q, kThreads), kThreads, 0, s>>>(
-                q, P, queries, c->proj.as<float>(), c->qr.as<float>(), c->range_part.as<float>());
+            P <= 16 ? go(k_query_proj<N, 16, false>) : go(k_query_proj<N, 32, false>);
     }
-    k_range_final<<<dim3(unsigned(P)), kThreads, 0, s>>>(nparts, P, c->params.key_bits,
-                                         c->range_part.as<float>(), c->qrange.as<float>());
+    if (root_keys)
+        k_root_keys<<<dim3(unsigned(P)), kThreads, 0, s>>>(nparts, P, c->range_part.as<float>(),
+                                                           c->kd_work.ext[0].as<uint32_t>());
+    else
+        k_range_final<<<dim3(unsigned(P)), kThreads, 0, s>>>(nparts, P, c->params.key_bits,
+                                                             c->range_part.as<float>(),
+                                                             c->qrange.as<float>());
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
     int which = 0;
@@ -721,7 +791,7 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
                 k_iota<<<nblk(q, kThreads), kThreads, 0, s>>>(c->perm.as<int32_t>(), q);
             } else {
                 e = kd_start(rq, c->kd_q, c->kd_work, P, c->qr.as<float>(), q,
-                             c->perm.as<int32_t>(), c->qr_s.as<float>(), s);
+                             c->perm.as<int32_t>(), c->qr_s.as<float>(), s, root_keys);
                 qr_s = c->qr_s.as<float>();
             }
         }

@@ -74,17 +74,6 @@ constexpr int kNodeCols = 8;
 // slice table row: start, length, node
 constexpr int kSliceCols = 3;
 
-__device__ __forceinline__ uint32_t orderable(float v)
-{
-    const uint32_t u = __float_as_uint(v);
-    return (u >> 31) ? ~u : (u | 0x80000000u);
-}
-
-__device__ __forceinline__ float from_orderable(uint32_t k)
-{
-    return __uint_as_float((k >> 31) ? (k & 0x7fffffffu) : ~k);
-}
-
 __device__ __forceinline__ uint32_t wave_umin(uint32_t v)
 {
 #pragma unroll
@@ -99,34 +88,6 @@ __device__ __forceinline__ uint32_t wave_umax(uint32_t v)
     return v;
 }
 
-// Min / max over the 64 lanes by DPP (no LDS traffic), valid in lane 63:
-// within each row of 16 lanes a running min over row_shr 1, 2, 4, 8 (lanes
-// shifted in from outside the row take the identity), then row_bcast 15
-// carries rows 0 and 2 into rows 1 and 3 and row_bcast 31 carries lane 31
-// into rows 2 and 3.
-__device__ __forceinline__ uint32_t wave_umin_dpp(uint32_t v)
-{
-    const int id = -1;   // 0xffffffff
-    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr1, 0xf, 0xf, false)));
-    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr2, 0xf, 0xf, false)));
-    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr4, 0xf, 0xf, false)));
-    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr8, 0xf, 0xf, false)));
-    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowBcast15, 0xa, 0xf, false)));
-    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowBcast31, 0xc, 0xf, false)));
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_umax_dpp(uint32_t v)
-{
-    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr1, 0xf, 0xf, false)));
-    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr2, 0xf, 0xf, false)));
-    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr4, 0xf, 0xf, false)));
-    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr8, 0xf, 0xf, false)));
-    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowBcast15, 0xa, 0xf, false)));
-    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowBcast31, 0xc, 0xf, false)));
-    return v;
-}
-
 // The plane of min / max key slots a workgroup merges into.
 __device__ __forceinline__ uint32_t *ext_plane(uint32_t *ext, int64_t max_nodes, int P)
 {
@@ -134,14 +95,14 @@ __device__ __forceinline__ uint32_t *ext_plane(uint32_t *ext, int64_t max_nodes,
 }
 
 // Clears the histograms; resets the root's min / max key slots (P
-// projections, every plane) to their identities.
+// projections) of planes first_plane.. to their identities.
 __global__ __launch_bounds__(kThreads) void k_kd_zero(int32_t *__restrict__ p, int64_t n,
                                                       uint32_t *__restrict__ ext, int P,
-                                                      int64_t max_nodes)
+                                                      int64_t max_nodes, int first_plane)
 {
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i < n) p[i] = 0;
-    if (i < int64_t(P) * kExtRep) {
+    if (i >= int64_t(P) * first_plane && i < int64_t(P) * kExtRep) {
         uint32_t *e = ext + (i / P) * max_nodes * 2 * P + 2 * (i % P);
         e[0] = 0xffffffffu;
         e[1] = 0u;
@@ -981,9 +942,10 @@ bool kd_reserve(KdWork &w, const KdPlan &pl, int64_t n, int P)
 }
 
 hipError_t kd_start(KdRun &r, const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
-                    int32_t *perm, float *vals_sorted, hipStream_t s)
+                    int32_t *perm, float *vals_sorted, hipStream_t s, bool root_given)
 {
     r = KdRun{};
+    r.root_given = root_given;
     r.pl = &pl;
     r.w = &w;
     r.P = P;
@@ -1033,7 +995,8 @@ hipError_t kd_step(KdRun &r)
     if (phase == 0) {   // the root's extents
         if (nlev == 0) return hipSuccess;
         k_kd_zero<<<nb(3 * kBins * mn, kThreads), kThreads, 0, s>>>(
-            hist, 3 * kBins * mn, w.ext[0].as<uint32_t>(), P, mn);
+            hist, 3 * kBins * mn, w.ext[0].as<uint32_t>(), P, mn, r.root_given ? 1 : 0);
+        if (r.root_given) return hipGetLastError();
         const unsigned nr = nb(n, kThreads * kRootPer);
         if (P <= 16)
             k_kd_root_ext<16><<<nr, kThreads, 0, s>>>(n, P, r.vals, w.ext[0].as<uint32_t>(), mn);

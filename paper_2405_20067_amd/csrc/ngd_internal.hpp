@@ -96,9 +96,12 @@ struct KdRun {
     const float *vin = nullptr;
     int cur = 0;
     bool done = true;
+    // the root's min / max keys are already in plane 0 of w.ext[0] (slots
+    // 2j and 2j + 1 of projection j), written by the caller ahead of the run
+    bool root_given = false;
 };
 hipError_t kd_start(KdRun &r, const KdPlan &pl, KdWork &w, int P, const float *vals, int64_t n,
-                    int32_t *perm, float *vals_sorted, hipStream_t s);
+                    int32_t *perm, float *vals_sorted, hipStream_t s, bool root_given = false);
 hipError_t kd_step(KdRun &r);
 
 }  // namespace ngd

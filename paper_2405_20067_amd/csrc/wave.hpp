@@ -164,6 +164,46 @@ __device__ __forceinline__ float wave_max(float v)
     return v;
 }
 
+// Float to a key whose unsigned order is the float order (and back).
+__device__ __forceinline__ uint32_t orderable(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return (u >> 31) ? ~u : (u | 0x80000000u);
+}
+
+__device__ __forceinline__ float from_orderable(uint32_t k)
+{
+    return __uint_as_float((k >> 31) ? (k & 0x7fffffffu) : ~k);
+}
+
+// Min / max over the 64 lanes by DPP (no LDS traffic), valid in lane 63:
+// within each row of 16 lanes a running min over row_shr 1, 2, 4, 8 (lanes
+// shifted in from outside the row take the identity), then row_bcast 15
+// carries rows 0 and 2 into rows 1 and 3 and row_bcast 31 carries lane 31
+// into rows 2 and 3.
+__device__ __forceinline__ uint32_t wave_umin_dpp(uint32_t v)
+{
+    const int id = -1;   // 0xffffffff
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr1, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr2, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr4, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowShr8, 0xf, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowBcast15, 0xa, 0xf, false)));
+    v = min(v, uint32_t(__builtin_amdgcn_update_dpp(id, int(v), kDppRowBcast31, 0xc, 0xf, false)));
+    return v;
+}
+
+__device__ __forceinline__ uint32_t wave_umax_dpp(uint32_t v)
+{
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr1, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr2, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr4, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowShr8, 0xf, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowBcast15, 0xa, 0xf, false)));
+    v = max(v, uint32_t(__builtin_amdgcn_update_dpp(0, int(v), kDppRowBcast31, 0xc, 0xf, false)));
+    return v;
+}
+
 template <typename T> __device__ __forceinline__ T uniform(T v)
 {
     return __builtin_amdgcn_readfirstlane(v);
