@@ -248,6 +248,18 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull,
 int ngd_l2_loss(const float *f, const float *target, int64_t q, float *loss,
                 float *grad, void *stream);
 
+/* Relative squared error, the loss the paper trains with (Sec. 4.1 names a
+ * relative L2 loss after Noise2Noise): each error is divided by the squared
+ * prediction scale, which is held constant for the gradient,
+ *   w = 1 / (|f| + eps)^2,
+ *   loss = 1/(3q) sum w (f - target)^2,  grad = 2 w (f - target) / (3q).
+ * (|f| makes the weight finite for any prediction; for f >= 0 it is the
+ * Noise2Noise form, whose eps is 0.01.)  f, target, grad device q x 3; loss
+ * device, one float.  eps must be finite and > 0, else NGD_E_INVAL.  Same
+ * reduction and errors as ngd_l2_loss.  Does not synchronise. */
+int ngd_rel_l2_loss(const float *f, const float *target, int64_t q, float eps,
+                    float *loss, float *grad, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -28,6 +28,7 @@ __all__ = [
     "gaussian",
     "cull",
     "kappa2_from_tau",
+    "rel_l2",
     "threads",
 ]
 
@@ -199,6 +200,29 @@ def msq_pairs(mean, factor, queries, qi, gi) -> np.ndarray:
                                     qi.size, _p(qi, _i64p), _p(gi, _i64p), _p(out, _f64p))
     assert rc == 0
     return out
+
+
+def rel_l2(f, target, eps=0.01):
+    """The relative squared error and its gradient, in float64.
+
+    Sec. 4.1 trains with a relative L2 loss after Noise2Noise; its form is
+    taken from there: every squared error is divided by the squared scale of
+    the prediction, (|f| + eps)^2, and that scale is treated as a constant
+    when differentiating.  With m = f.size:
+        loss = (1/m) sum_i (f_i - t_i)^2 / (|f_i| + eps)^2
+        grad_i = 2 (f_i - t_i) / (|f_i| + eps)^2 / m
+    Returns (loss, grad) with grad shaped like f.
+    """
+    f = np.asarray(f, np.float64)
+    t = np.asarray(target, np.float64)
+    m = f.size
+    if m == 0:
+        return 0.0, np.zeros_like(f)
+    scale = np.abs(f) + float(eps)
+    err = f - t
+    loss = float(np.sum(err * err / (scale * scale)) / m)
+    grad = 2.0 * err / (scale * scale) / m
+    return loss, grad
 
 
 def kappa2_from_tau(tau: float) -> np.float32:

@@ -96,6 +96,37 @@ void DevBuf::release()
 
 using namespace ngd;
 
+namespace {
+// The shared body of the two losses (rel_eps 0: the plain one).
+int l2_loss_impl(const char *who, const float *f, const float *target, int64_t q, float *loss,
+                 float *grad, float rel_eps, void *stream)
+{
+    if (q < 0 || q >= (int64_t(1) << 31))
+        return fail(NGD_E_INVAL, "%s: q=%lld outside [0, 2^31)", who, (long long)q);
+    if (!loss || (q > 0 && (!f || !target || !grad)))
+        return fail(NGD_E_INVAL, "%s: NULL array", who);
+    if (!aligned4(f) || !aligned4(target) || !aligned4(grad) || !aligned4(loss))
+        return fail(NGD_E_INVAL, "%s: arrays must be 4-byte aligned", who);
+    // per-device partial-sum workspace, kept for the life of the process
+    constexpr int kParts = 1024;
+    static std::mutex mu;
+    static DevBuf parts[64];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (dev < 0 || dev >= 64) return fail(NGD_E_INVAL, "%s: device %d", who, dev);
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        if (!parts[dev].ensure(sizeof(double) * kParts))
+            return fail(NGD_E_NOMEM, "%s: workspace allocation failed", who);
+    }
+    e = launch_l2_loss(f, target, q, loss, grad, parts[dev].as<float>(), kParts, S(stream),
+                       rel_eps);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return NGD_OK;
+}
+}  // namespace
+
 extern "C" {
 
 const char *ngd_last_error(void) { return g_err.c_str(); }
@@ -573,28 +604,15 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull, const float 
 int ngd_l2_loss(const float *f, const float *target, int64_t q, float *loss, float *grad,
                 void *stream)
 {
-    if (q < 0 || q >= (int64_t(1) << 31))
-        return fail(NGD_E_INVAL, "ngd_l2_loss: q=%lld outside [0, 2^31)", (long long)q);
-    if (!loss || (q > 0 && (!f || !target || !grad)))
-        return fail(NGD_E_INVAL, "ngd_l2_loss: NULL array");
-    if (!aligned4(f) || !aligned4(target) || !aligned4(grad) || !aligned4(loss))
-        return fail(NGD_E_INVAL, "ngd_l2_loss: arrays must be 4-byte aligned");
-    // per-device partial-sum workspace, kept for the life of the process
-    constexpr int kParts = 1024;
-    static std::mutex mu;
-    static DevBuf parts[64];
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "ngd_l2_loss");
-    if (dev < 0 || dev >= 64) return fail(NGD_E_INVAL, "ngd_l2_loss: device %d", dev);
-    {
-        std::lock_guard<std::mutex> lk(mu);
-        if (!parts[dev].ensure(sizeof(double) * kParts))
-            return fail(NGD_E_NOMEM, "ngd_l2_loss: workspace allocation failed");
-    }
-    e = launch_l2_loss(f, target, q, loss, grad, parts[dev].as<float>(), kParts, S(stream));
-    if (e != hipSuccess) return hip_fail(e, "ngd_l2_loss");
-    return NGD_OK;
+    return l2_loss_impl("ngd_l2_loss", f, target, q, loss, grad, 0.0f, stream);
+}
+
+int ngd_rel_l2_loss(const float *f, const float *target, int64_t q, float eps, float *loss,
+                    float *grad, void *stream)
+{
+    if (!(eps > 0.0f) || !std::isfinite(eps))
+        return fail(NGD_E_INVAL, "ngd_rel_l2_loss: eps=%g must be finite and > 0", double(eps));
+    return l2_loss_impl("ngd_rel_l2_loss", f, target, q, loss, grad, eps, stream);
 }
 
 }  // extern "C"

@@ -248,8 +248,11 @@ hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s);
 // Groups the entries with a kept query group by Gaussian (a_cnt, a_off, the
 // sorted entries in vals0/vals1) and builds the backward work items.
 hipError_t launch_backward_prepare(ngd_cull *c, hipStream_t s);
+// Mean squared error over q x 3 and its gradient; rel_eps > 0: each error
+// weighted by 1 / (|f| + rel_eps)^2, the weight held constant.
 hipError_t launch_l2_loss(const float *f, const float *target, int64_t q, float *loss,
-                          float *grad, float *partials, int nparts, hipStream_t s);
+                          float *grad, float *partials, int nparts, hipStream_t s,
+                          float rel_eps = 0.0f);
 
 // Stable LSD radix sort of (key, value) pairs by the low nbits of the keys,
 // kRadixPerBlock keys per block.  n is the count, or an upper bound when

@@ -148,10 +148,14 @@ __device__ double block_sum_f64(double v)
     return s;
 }
 
+// Per chunk of the q x 3 values: the gradient, and the chunk's sum of
+// squared errors.  REL: each error weighted by w = 1 / (|f| + eps)^2, the
+// prediction's own scale, taken as a constant (no gradient through it).
+template <bool REL>
 __global__ __launch_bounds__(kLossThreads) void k_l2_partial(const float *__restrict__ f,
                                                              const float *__restrict__ t,
                                                              int64_t m, float inv_scale2,
-                                                             int64_t chunk,
+                                                             float eps, int64_t chunk,
                                                              float *__restrict__ grad,
                                                              double *__restrict__ parts)
 {
@@ -159,9 +163,17 @@ __global__ __launch_bounds__(kLossThreads) void k_l2_partial(const float *__rest
     const int64_t hi = (lo + chunk < m) ? lo + chunk : m;
     double acc = 0.0;
     for (int64_t i = lo + threadIdx.x; i < hi; i += kLossThreads) {
-        const float d = f[i] - t[i];
-        grad[i] = d * inv_scale2;
-        acc += double(d) * double(d);
+        const float fi = f[i];
+        const float d = fi - t[i];
+        if constexpr (REL) {
+            const float den = fabsf(fi) + eps;
+            const float w = 1.0f / (den * den);
+            grad[i] = d * w * inv_scale2;
+            acc += double(d) * double(d) * double(w);
+        } else {
+            grad[i] = d * inv_scale2;
+            acc += double(d) * double(d);
+        }
     }
     const double s = block_sum_f64(acc);
     if (threadIdx.x == 0) parts[blockIdx.x] = s;
@@ -215,7 +227,8 @@ hipError_t launch_zero_f32(float *p, int64_t n, hipStream_t s)
 }
 
 hipError_t launch_l2_loss(const float *f, const float *target, int64_t q, float *loss,
-                          float *grad, float *partials, int nparts, hipStream_t s)
+                          float *grad, float *partials, int nparts, hipStream_t s,
+                          float rel_eps)
 {
     const int64_t m = 3 * q;
     if (m == 0) {
@@ -226,8 +239,12 @@ hipError_t launch_l2_loss(const float *f, const float *target, int64_t q, float 
     const int64_t chunk = (m + nparts - 1) / nparts;
     const int used = int((m + chunk - 1) / chunk);
     double *parts = reinterpret_cast<double *>(partials);
-    k_l2_partial<<<dim3(unsigned(used)), kLossThreads, 0, s>>>(
-        f, target, m, float(2.0 / double(m)), chunk, grad, parts);
+    if (rel_eps > 0.0f)
+        k_l2_partial<true><<<dim3(unsigned(used)), kLossThreads, 0, s>>>(
+            f, target, m, float(2.0 / double(m)), rel_eps, chunk, grad, parts);
+    else
+        k_l2_partial<false><<<dim3(unsigned(used)), kLossThreads, 0, s>>>(
+            f, target, m, float(2.0 / double(m)), 0.0f, chunk, grad, parts);
     k_l2_final<<<1, kLossThreads, 0, s>>>(parts, used, 1.0 / double(m), loss);
     return hipGetLastError();
 }

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "NgdError", "CullParams", "Mixture", "Cull", "lib", "LIB_PATH",
-    "eval_mixture", "eval_prepare", "eval_backward", "eval_stats", "l2_loss", "FP32",
+    "eval_mixture", "eval_prepare", "eval_backward", "eval_stats", "l2_loss", "rel_l2_loss", "FP32",
     "BF16_MFMA",
     "E_INVAL", "E_SINGULAR", "E_HIP", "E_NOMEM", "E_STALE",
 ]
@@ -83,6 +83,9 @@ _SIGS = [
     ("ngd_l2_loss", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p]),
+    ("ngd_rel_l2_loss", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_float, ctypes.c_void_p,
+      ctypes.c_void_p, ctypes.c_void_p]),
 ]
 EXPORTED = [s[0] for s in _SIGS]
 
@@ -302,6 +305,21 @@ def eval_backward(mix: Mixture, cull: Cull | None, queries, grad_out, grads=None
                                    _ptr(gw, "g_weight", mix.k),
                                    _ptr(gc, "g_colour", mix.k * 3), _stream(stream)))
     return grads
+
+
+def rel_l2_loss(f, target, eps=0.01, loss=None, grad=None, stream=None):
+    """(loss, grad): relative squared error over q x 3, weights 1/(|f| + eps)^2
+    held constant (include/ngd.h, ngd_rel_l2_loss)."""
+    import torch
+    q = f.numel() // 3
+    if loss is None:
+        loss = torch.empty((1,), dtype=torch.float32, device=f.device)
+    if grad is None:
+        grad = torch.empty_like(f)
+    _check(lib().ngd_rel_l2_loss(_ptr(f, "f", q * 3), _ptr(target, "target", q * 3), q,
+                                 float(eps), _ptr(loss, "loss", 1),
+                                 _ptr(grad, "grad", q * 3), _stream(stream)))
+    return loss, grad
 
 
 def l2_loss(f, target, loss=None, grad=None, stream=None):

@@ -85,6 +85,16 @@ def test_l2_loss_argument_checks(L):
                          ctypes.c_void_p(16), None) == ngd.E_INVAL   # misaligned
 
 
+def test_rel_l2_loss_argument_checks(L):
+    one = ctypes.c_void_p(16)
+    for eps in (0.0, -0.01, float("nan"), float("inf")):
+        assert L.ngd_rel_l2_loss(one, one, 5, eps, one, one, None) == ngd.E_INVAL
+    assert L.ngd_rel_l2_loss(None, None, -1, 0.01, None, None, None) == ngd.E_INVAL
+    assert L.ngd_rel_l2_loss(None, None, 5, 0.01, one, None, None) == ngd.E_INVAL
+    assert L.ngd_rel_l2_loss(ctypes.c_void_p(2), one, 5, 0.01, one, one,
+                             None) == ngd.E_INVAL   # misaligned
+
+
 def test_allocator_failure_is_reported_as_nomem(L):
     calls = []
 

@@ -278,6 +278,23 @@ def test_edge_cases(torch_cuda):
     assert float(ngd.eval_mixture(m0, None, xd).abs().max()) == 0.0
 
 
+def test_rel_l2_loss(torch_cuda):
+    """The relative loss against the float64 oracle: predictions of both
+    signs and of magnitudes from 1e-3 to 1e3, sizes across one and many
+    reduction chunks."""
+    from paper_2405_20067_amd import ngd
+    rng = np.random.default_rng(1)
+    for q in (1, 1000, 300001):
+        mag = 10.0 ** rng.uniform(-3, 3, (q, 3))
+        f = (mag * rng.choice([-1.0, 1.0], (q, 3))).astype(np.float32)
+        t = (f * rng.uniform(0.5, 1.5, (q, 3)) + rng.standard_normal((q, 3))).astype(np.float32)
+        for eps in (0.01, 1.0):
+            loss, grad = ngd.rel_l2_loss(dev(f), dev(t), eps=eps)
+            want_loss, want_grad = oracle.rel_l2(f, t, eps=np.float32(eps))
+            assert float(host(loss)[0]) == pytest.approx(want_loss, rel=1e-5)
+            np.testing.assert_allclose(host(grad), want_grad, rtol=1e-5, atol=0)
+
+
 def test_l2_loss(torch_cuda):
     from paper_2405_20067_amd import ngd
     rng = np.random.default_rng(0)

@@ -311,3 +311,55 @@ def test_msq_pairs_cauchy_schwarz():
             d = x[qi[e]].astype(np.float64) - mix["mean"][gi[e]]
             s2 = np.sum((L.T @ rv) ** 2)
             assert (rv @ d) ** 2 <= s2 * M[e] * (1 + 1e-12)
+
+
+# ---- the relative L2 loss (Sec. 4.1, Noise2Noise form) --------------------
+
+def test_rel_l2_constant_prediction_is_scaled_mse():
+    """With every prediction equal to c the weight is the constant
+    1/(|c| + eps)^2, so the loss and gradient are the textbook mean squared
+    error and its gradient times that constant (c < 0 pins the |f|)."""
+    rng = np.random.default_rng(5)
+    t = rng.standard_normal((257, 3))
+    for c in (0.0, 0.7, -2.5):
+        f = np.full_like(t, c)
+        loss, grad = oracle.rel_l2(f, t, eps=0.01)
+        k = (abs(c) + 0.01) ** 2
+        d = f - t
+        assert loss * k == pytest.approx(float(np.mean(d * d)), rel=1e-12)
+        np.testing.assert_allclose(grad * k, 2.0 * d / d.size, rtol=1e-12)
+
+
+def test_rel_l2_is_scale_invariant():
+    """Scaling predictions, targets and eps together leaves a relative loss
+    unchanged and divides its gradient by the scale (a wrong power of the
+    weight breaks this)."""
+    rng = np.random.default_rng(6)
+    f = rng.standard_normal((100, 3))
+    t = rng.standard_normal((100, 3))
+    l1, g1 = oracle.rel_l2(f, t, eps=0.03)
+    for s in (1e-3, 7.0, 2.0 ** 20):
+        l2, g2 = oracle.rel_l2(s * f, s * t, eps=0.03 * s)
+        assert l2 == pytest.approx(l1, rel=1e-12)
+        np.testing.assert_allclose(g2 * s, g1, rtol=1e-12)
+
+
+def test_rel_l2_large_eps_is_plain_mse():
+    """For eps far above every |f| the weight tends to 1/eps^2 and the
+    gradient to that of the plain mean squared error, 2 (f - t) / m."""
+    rng = np.random.default_rng(7)
+    f = rng.uniform(-3, 3, (64, 3))
+    t = rng.uniform(-3, 3, (64, 3))
+    eps = 1e7
+    loss, grad = oracle.rel_l2(f, t, eps=eps)
+    d = f - t
+    assert loss * eps ** 2 == pytest.approx(float(np.mean(d * d)), rel=1e-5)
+    np.testing.assert_allclose(grad * eps ** 2, 2.0 * d / d.size, rtol=1e-5)
+
+
+def test_rel_l2_zero_at_target_and_empty():
+    f = np.linspace(-1, 1, 30).reshape(10, 3)
+    loss, grad = oracle.rel_l2(f, f.copy())
+    assert loss == 0.0 and not grad.any()
+    loss, grad = oracle.rel_l2(np.zeros((0, 3)), np.zeros((0, 3)))
+    assert loss == 0.0 and grad.shape == (0, 3)
