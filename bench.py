@@ -121,6 +121,67 @@ def cpu_baseline(w, mix, x, budget_s: float):
                 fwd_s=tf, bwd_s=tb, pairs=pairs)
 
 
+def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-3,
+              lr_alpha: float = 1e-2):
+    """The 10-D fitting loop (Adam, children from the second phase,
+    materialised above t = 0.01): K starts at 32,768 Gaussians and may grow
+    to 524,288; 2^21 queries near the hidden K=4,096 target mixture and
+    uniform, their target values computed once.  The start stands in for an
+    initialisation from the data: 8 Gaussians per target component, means
+    drawn from that component, factors 1.5x wider, brightness 1/8, colours
+    random.  Every step is timed; set-up (query pool, targets, handles) is
+    not."""
+    import torch
+    from paper_2405_20067_amd import inputs, ngd
+    from paper_2405_20067_amd.fit import Fit
+    w = inputs.WORKLOADS["10d-fwdbwd"]
+    k0, q, max_k = 32768, 1 << 21, 524288
+    tgt = inputs.workload_mixture(w, k=w.k_target, seed=inputs.SEED_TARGET)
+    rng = np.random.default_rng(inputs.SEED_MIXTURE)
+    rep = k0 // w.k_target
+    src = np.repeat(np.arange(w.k_target), rep)
+    lfull = np.zeros((k0, w.n, w.n))
+    r, c = np.tril_indices(w.n)
+    lfull[:, r, c] = tgt["factor"][src]
+    z = rng.standard_normal((k0, w.n))
+    mix = dict(mean=tgt["mean"][src] + np.einsum("kij,kj->ki", lfull, z),
+               factor=1.5 * tgt["factor"][src], weight=tgt["weight"][src] / rep,
+               colour=rng.uniform(0.05, 0.95, (k0, 3)))
+    mix = {a: np.ascontiguousarray(v, np.float32) for a, v in mix.items()}
+    x = inputs.gen_workload_queries(w, q=q, mixtures=[tgt])
+    proj = inputs.gen_projections(w.n, 16, inputs.SEED_PROJ)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    dev = dict(x=d(x))
+    target = targets(w, tgt, dev, proj)
+    prec = ngd.BF16_MFMA if precision_name == "bf16_mfma" else ngd.FP32
+    fit = Fit(d(mix["mean"]), d(mix["factor"]), d(mix["weight"]), d(mix["colour"]), lr=lr,
+              lr_alpha=lr_alpha, phase=phase, max_k=max_k, precision=prec)
+    log(f"fit: n={w.n} k0={k0} q={q} steps={steps} phase={phase} lr={lr}/{lr_alpha} "
+        f"{precision_name}")
+    ks, losses = [], []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        loss = fit.step(dev["x"], target, proj)
+        if i == 0 or (i + 1) % phase == 0 or i + 1 == steps:
+            losses.append((i + 1, float(loss[0])))   # synchronises: a few times per run
+            ks.append((i + 1, fit.k))
+            log(f"fit step {i + 1}: loss {losses[-1][1]:.5g}, K {fit.k}")
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    print(json.dumps(dict(
+        metric="10-D fitting loop time per step (update, cull, fwd, loss, bwd, Adam, refinement)",
+        value=ms, unit="ms/step", n_gpus=1, steps=steps, warmup=0, ms_per_step=ms,
+        higher_is_better=False, scaling="weak", vs_baseline=None,
+        dtype="bf16+f32" if prec == ngd.BF16_MFMA else "f32", data="synthetic",
+        config=dict(workload="10d-fit", n=w.n, k_start=k0, k_max=max_k, q=q, phase=phase,
+                    lr=lr, lr_alpha=lr_alpha, threshold=fit.threshold, loss="l2",
+                    precision=precision_name, init="8 per target component",
+                    k_target=w.k_target),
+        initial_loss=losses[0][1], final_loss=losses[-1][1], loss_trajectory=losses,
+        k_trajectory=ks)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,6 +197,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3 (3 steps, 1 warmup, no CPU/dense legs) "
                          "plus one 256 MiB device copy to calibrate memory counters")
+    ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
+                    help="instead of the step benchmark, run the 10-D fitting loop for "
+                         "STEPS steps and print its own line (ms/step, losses, K)")
     args = ap.parse_args()
     if args.profile:
         args.steps, args.warmup, args.no_cpu_baseline, args.no_dense = 3, 1, True, True
@@ -148,6 +212,9 @@ def main():
     from paper_2405_20067_amd import ngd
     torch.cuda.set_device(0)
     ngd.lib()
+    if args.fit > 0:
+        fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma")
+        return
     w, mix, tgt, x, proj, dev = setup(args.workload)
     target = targets(w, tgt, dev, proj) if w.backward else None
 

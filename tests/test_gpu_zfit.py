@@ -1,0 +1,103 @@
+"""The fitting loop on the GPU path (Sec. 3.3, 4.1): Adam lowers the loss,
+default children change the represented function by no more than their own
+brightness, and materialising children keeps it."""
+
+import numpy as np
+import pytest
+
+from gpu_helpers import dev, host
+from paper_2405_20067_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TAU = 1e-4
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _problem(torch, n=4, k=64, q=32768, seed=5):
+    from paper_2405_20067_amd import ngd
+    tgt = inputs.gen_mixture(n, k, seed=seed)
+    x = np.concatenate([inputs.gen_queries(n, q // 2, seed=seed + 1),
+                        inputs.gen_near_queries([tgt], q - q // 2, seed=seed + 2)])
+    proj = inputs.gen_projections(n, 16, inputs.SEED_PROJ)
+    xd = dev(x)
+    mt = ngd.Mixture(n, k)
+    mt.update(dev(tgt["mean"]), dev(tgt["factor"]), dev(tgt["weight"]), dev(tgt["colour"]))
+    target = ngd.eval_mixture(mt, None, xd)          # dense: the exact target values
+    rng = np.random.default_rng(seed + 3)
+    init = dict(mean=tgt["mean"] + 0.03 * rng.standard_normal(tgt["mean"].shape),
+                factor=tgt["factor"], weight=tgt["weight"] * 0.6,
+                colour=np.clip(tgt["colour"] + 0.2 * rng.standard_normal((k, 3)), 0.05, 0.95))
+    init = {a: dev(np.asarray(v, np.float32)) for a, v in init.items()}
+    return xd, target, proj, init
+
+
+def _fit(torch, init, **kw):
+    from paper_2405_20067_amd.fit import Fit
+    return Fit(init["mean"], init["factor"], init["weight"], init["colour"], **kw)
+
+
+def test_fit_lowers_the_loss(torch_cuda):
+    torch = torch_cuda
+    xd, target, proj, init = _problem(torch)
+    for loss_kind in ("l2", "rel"):
+        fit = _fit(torch, init, lr=2e-3, phase=10 ** 9, loss=loss_kind)
+        losses = [float(host(fit.step(xd, target, proj))[0]) for _ in range(200)]
+        print(f"[fit {loss_kind}] loss {losses[0]:.4g} -> {losses[-1]:.4g}", flush=True)
+        assert np.isfinite(losses).all()
+        assert losses[-1] < 0.5 * losses[0]
+
+
+def _alpha_sum(fit, torch):
+    w = [torch.exp(fit.a)]
+    if fit.child is not None:
+        w.append(torch.exp(fit.child[2]))
+    return float(torch.cat(w).detach().sum())
+
+
+def test_default_children_are_negligible(torch_cuda):
+    torch = torch_cuda
+    xd, target, proj, init = _problem(torch)
+    fit = _fit(torch, init, child_alpha=1e-4)
+    f0 = host(fit.evaluate(xd, proj))
+    a0 = _alpha_sum(fit, torch)
+    fit.add_children()
+    assert fit.k == 2 * 64
+    f1 = host(fit.evaluate(xd, proj))
+    kids = float(torch.exp(fit.child[2].detach()).sum())
+    bound = kids + 2 * TAU * (a0 + kids) + 1e-6   # children's total + the cull's bound
+    assert np.abs(f1 - f0).max() <= bound
+    # a step moves the children's parameters too
+    before = [t.detach().clone() for t in fit.child]
+    fit.step(xd, target, proj)
+    assert any(not torch.equal(b, t.detach()) for b, t in zip(before, fit.child))
+
+
+def test_materialising_children_keeps_the_function(torch_cuda):
+    torch = torch_cuda
+    xd, target, proj, init = _problem(torch)
+    fit = _fit(torch, init, child_alpha=1e-4, threshold=0.01, child_jitter=0.3)
+    fit.add_children()
+    with torch.no_grad():   # a third of the children grow bright
+        fit.child[2][::3] = np.log(0.05)
+    bright = int((torch.exp(fit.child[2]) > 0.01).sum())
+    f0 = host(fit.evaluate(xd, proj))
+    a0 = _alpha_sum(fit, torch)
+    count = fit.refine()
+    assert count == bright
+    assert fit.mean.shape[0] == 64 + count and fit.child[0].shape[0] == 64 + count
+    f1 = host(fit.evaluate(xd, proj))
+    # the materialised children are now parents with the same absolute
+    # parameters; what changed is their slots' and the new parents' fresh
+    # children (negligible), up to the cull's bound
+    fresh = float(torch.exp(fit.child[2].detach()).sum())
+    bound = fresh + 2 * TAU * (a0 + _alpha_sum(fit, torch)) + 1e-6
+    assert np.abs(f1 - f0).max() <= bound
+    assert fit.refine() == 0   # nothing bright is left
