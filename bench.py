@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -182,6 +183,65 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
         k_trajectory=ks)), flush=True)
 
 
+def sweep_bench(reps: int = 5, sample: int = 4096):
+    """The cull's thresholds on the 10-D workload (Q = 2^20, K = 2^18): for
+    each (tau, tile) the candidate fraction of the tile x Gaussian pairs,
+    the cull build and both forwards' times (median of reps), and the
+    normwise error of the culled FP32 forward against the dense float32 sum
+    on a seeded sample of queries.  tau = exp(-4.5) is the 3-sigma cut."""
+    import torch
+    from paper_2405_20067_amd import inputs, ngd
+    w, mix, tgt, x, proj, dev = setup("10d-fwdbwd")
+    m = ngd.Mixture(w.n, w.k)
+    m.update(dev["mean"], dev["factor"], dev["weight"], dev["colour"])
+    idx = torch.from_numpy(np.sort(np.random.default_rng(inputs.SEED_QUERIES).choice(
+        w.q, sample, replace=False))).to("cuda")
+    xs = dev["x"][idx].contiguous()
+    dense = ngd.eval_mixture(m, None, xs).double()
+    s3 = math.exp(-4.5)
+    grid = [(t, 256) for t in (1e-2, s3, 1e-3, 1e-4, 1e-5, 1e-6)] + \
+           [(1e-4, t) for t in (64, 128, 512, 1024)]
+
+    def med(fn):
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.median(out))
+
+    rows = []
+    for tau, tile in grid:
+        p = ngd.default_params()
+        p.tau, p.tile = tau, tile
+        c = ngd.Cull().build(m, dev["x"], proj, p)
+        f = ngd.eval_mixture(m, c, dev["x"])
+        torch.cuda.synchronize()
+        st = c.stats()
+        err = float((f[idx].double() - dense).abs().max() / dense.abs().max())
+        row = dict(tau=tau, tile=tile, candidates=st["total"],
+                   fraction=st["total"] / max(st["ntiles"] * w.k, 1),
+                   cull_ms=med(lambda: c.build(m, dev["x"], proj, p)),
+                   fwd_fp32_ms=med(lambda: ngd.eval_mixture(m, c, dev["x"], out=f)),
+                   fwd_bf16_ms=med(lambda: ngd.eval_mixture(m, c, dev["x"], out=f,
+                                                            precision=ngd.BF16_MFMA)),
+                   err_fp32=err)
+        log(f"sweep tau={tau:.4g} tile={tile}: {row['fraction']:.4%} of pairs, cull "
+            f"{row['cull_ms']:.3f} ms, fwd {row['fwd_fp32_ms']:.3f} / {row['fwd_bf16_ms']:.3f} "
+            f"ms, err {err:.2e}")
+        rows.append(row)
+    print(json.dumps(dict(
+        metric="cull thresholds on the 10-D workload: candidate fraction, cull and forward "
+               "time, error against the dense sum",
+        unit="ms", n_gpus=1, data="synthetic", dtype="f32 / bf16+f32",
+        config=dict(workload="10d-fwdbwd", n=w.n, k=w.k, q=w.q, n_proj=16,
+                    error_sample=sample, reps=reps),
+        rows=rows)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -197,6 +257,9 @@ def main():
     ap.add_argument("--profile", action="store_true",
                     help="short run for rocprofv3 (3 steps, 1 warmup, no CPU/dense legs) "
                          "plus one 256 MiB device copy to calibrate memory counters")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the step benchmark, sweep the cull threshold tau and "
+                         "the tile size and print one line of rows")
     ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
                     help="instead of the step benchmark, run the 10-D fitting loop for "
                          "STEPS steps and print its own line (ms/step, losses, K)")
@@ -214,6 +277,9 @@ def main():
     ngd.lib()
     if args.fit > 0:
         fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma")
+        return
+    if args.sweep:
+        sweep_bench()
         return
     w, mix, tgt, x, proj, dev = setup(args.workload)
     target = targets(w, tgt, dev, proj) if w.backward else None
