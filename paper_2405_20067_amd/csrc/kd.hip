@@ -602,38 +602,84 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
         __syncthreads();
         const int nsplit = nsplit_s;
         if (nsplit == 0) break;
-        // extent of every projection over every splitting run: one wave per
-        // 64 consecutive positions loads all projections of its points, then
-        // reduces per run present in the wave and merges by LDS atomics
+        // extent of every projection over every splitting run.  Each wave
+        // covers kSpan consecutive positions, each lane kPer consecutive ones
+        // of them: when every lane's positions lie in one splitting run (or
+        // past the end), which holds for runs aligned to kPer, the lane first
+        // reduces its own positions in registers; otherwise the wave takes
+        // its span 64 positions at a time.  Then one DPP min / max per run
+        // present in the wave and projection, merged by LDS atomics.
         for (int t = tid; t < nsplit * PMAX; t += kLocalThreads) {
             emin[t / PMAX][t % PMAX] = 0xffffffffu;
             emax[t / PMAX][t % PMAX] = 0u;
         }
         __syncthreads();
-        for (int base = w * kWave; base < m; base += kLocalThreads) {
-            const int i = base + lane;
-            const int si = i < m ? rsi[run_of[i]] : -1;
-            uint32_t kv[PMAX];
+        {
+            auto merge = [&](int si, const uint32_t (&lo)[PMAX], const uint32_t (&hi)[PMAX]) {
+                uint64_t todo = ballot(si >= 0);
+                while (todo) {
+                    const int src = __ffsll((unsigned long long)todo) - 1;
+                    const int cur_si = __builtin_amdgcn_readlane(si, src);
+                    const bool mine = si == cur_si;
+                    todo &= ~ballot(mine);
 #pragma unroll
-            for (int j = 0; j < PMAX; ++j)
-                kv[j] = (j < P && si >= 0) ? orderable(vin[int64_t(j) * n + start + ord[cur][i]])
-                                           : 0u;
-            uint64_t todo = ballot(si >= 0);
-            while (todo) {
-                const int src = __ffsll((unsigned long long)todo) - 1;
-                const int cur_si = __builtin_amdgcn_readlane(si, src);
-                const bool mine = si == cur_si;
-                todo &= ~ballot(mine);
-#pragma unroll
-                for (int j = 0; j < PMAX; ++j) {
-                    if (j < P) {
-                        const uint32_t a = wave_umin_dpp(mine ? kv[j] : 0xffffffffu);
-                        const uint32_t c = wave_umax_dpp(mine ? kv[j] : 0u);
-                        if (lane == kWave - 1) {
-                            atomicMin(&emin[cur_si][j], a);
-                            atomicMax(&emax[cur_si][j], c);
+                    for (int j = 0; j < PMAX; ++j) {
+                        if (j < P) {
+                            const uint32_t a = wave_umin_dpp(mine ? lo[j] : 0xffffffffu);
+                            const uint32_t c = wave_umax_dpp(mine ? hi[j] : 0u);
+                            if (lane == kWave - 1) {
+                                atomicMin(&emin[cur_si][j], a);
+                                atomicMax(&emax[cur_si][j], c);
+                            }
                         }
                     }
+                }
+            };
+            const int p0 = w * kSpan + lane * kPer;
+            int sl[kPer];
+            int lr = -1;
+            bool same = true;
+#pragma unroll
+            for (int u = 0; u < kPer; ++u) {
+                sl[u] = p0 + u < m ? rsi[run_of[p0 + u]] : -1;
+                if (sl[u] >= 0) {
+                    if (lr < 0) lr = sl[u];
+                    else if (sl[u] != lr) same = false;
+                }
+            }
+            if (ballot(!same) == 0) {
+                uint32_t lo[PMAX], hi[PMAX];
+#pragma unroll
+                for (int j = 0; j < PMAX; ++j) {
+                    lo[j] = 0xffffffffu;
+                    hi[j] = 0u;
+                }
+#pragma unroll 1
+                for (int u = 0; u < kPer; ++u) {
+                    if (p0 + u >= m || rsi[run_of[p0 + u]] < 0) continue;
+                    const int o = ord[cur][p0 + u];
+#pragma unroll
+                    for (int j = 0; j < PMAX; ++j) {
+                        if (j < P) {
+                            const uint32_t k = orderable(vin[int64_t(j) * n + start + o]);
+                            lo[j] = min(lo[j], k);
+                            hi[j] = max(hi[j], k);
+                        }
+                    }
+                }
+                merge(lr, lo, hi);
+            } else {
+#pragma unroll 1
+                for (int u = 0; u < kPer; ++u) {
+                    const int i = w * kSpan + u * kWave + lane;
+                    const int si = i < m ? rsi[run_of[i]] : -1;
+                    uint32_t kv[PMAX];
+#pragma unroll
+                    for (int j = 0; j < PMAX; ++j)
+                        kv[j] = (j < P && si >= 0)
+                                    ? orderable(vin[int64_t(j) * n + start + ord[cur][i]])
+                                    : 0u;
+                    merge(si, kv, kv);
                 }
             }
         }
