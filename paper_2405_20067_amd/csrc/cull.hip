@@ -571,6 +571,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
     __shared__ uint64_t sm[kFillTiles][kWave + 1];   // [tile][chunk]
     __shared__ int32_t stage[kThreads / kWave][kFillStage];
     __shared__ int64_t run[kFillTiles];
+    __shared__ int64_t tend[kFillTiles];   // the tiles' list ends, loaded once
     const int64_t t0 = int64_t(blockIdx.x) * kFillTiles;
     const int64_t seg = blockIdx.y;
     const int64_t c0 = seg * per_seg;
@@ -579,6 +580,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
     if (int(threadIdx.x) < kFillTiles) {
         const int64_t t = t0 + threadIdx.x;
         run[threadIdx.x] = t < ntiles ? tile_off[t] + seg_cnt[seg * ntiles + t] : 0;
+        tend[threadIdx.x] = t < ntiles ? tile_off[t + 1] : 0;
     }
     int32_t *st = stage[w];
     for (int64_t cb = c0; cb < c1; cb += kWave) {
@@ -597,7 +599,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
             const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
             if (total == 0) continue;   // uniform
             const int32_t gbase = int32_t((cb + lane) * kWave);
-            const int64_t base = run[tl], end = tile_off[t + 1];
+            const int64_t base = run[tl], end = tend[tl];
             int k = incl - cnt;
             if (total <= kFillStage) {   // uniform
                 while (m) {
