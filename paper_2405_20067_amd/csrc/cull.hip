@@ -731,8 +731,18 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     const int R = rec_stride(N);
     const int nbits = c->params.key_proj * c->params.key_bits;
     hipError_t e;
+    // The Gaussians' projections feed only their own k-d order, which runs
+    // on the second stream: with the k-d tiling (and more than one chunk of
+    // Gaussians) they go there too, after the fork, so that the queries'
+    // projections start at once.
+    bool forked = false;
+    if (c->params.tiling == 0 && k > kWave) {
+        if ((e = hipEventRecord(c->ev_fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
+        forked = true;
+    }
     if (k > 0) {
-        k_gauss_proj<N><<<nblk(k, kThreads), kThreads, 0, s>>>(
+        k_gauss_proj<N><<<nblk(k, kThreads), kThreads, 0, forked ? c->side : s>>>(
             k, P, mix->rec.as<float>(), R, mix->lfac.as<float>(), c->proj.as<float>(), c->kappa2,
             c->g_mr.as<float>(), c->g_thr.as<float>());
     }
@@ -761,7 +771,13 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         k_range_final<<<dim3(unsigned(P)), kThreads, 0, s>>>(nparts, P, c->params.key_bits,
                                                              c->range_part.as<float>(),
                                                              c->qrange.as<float>());
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) {
+        if (forked) {   // the main stream still waits for the second one
+            (void)hipEventRecord(c->ev_join, c->side);
+            (void)hipStreamWaitEvent(s, c->ev_join, 0);
+        }
+        return e;
+    }
 
     int which = 0;
     // the k-d order leaves the projections in order: tile bounds and the
@@ -772,16 +788,12 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         // k-d order of the query projections (runs of `tile`, and of 64
         // inside those) and of the projected means (runs of 64, the chunks
         // of the interval test).  The two are independent: the Gaussians'
-        // order runs on a second stream, forked after their projections and
-        // joined before anything reads it.  Both are enqueued a phase (a
+        // order runs on the second stream, forked before their projections
+        // and joined before anything reads it.  Both are enqueued a phase (a
         // level) at a time, alternately, so that each stream has work while
         // the host enqueues the other's.
-        bool forked = false;
         KdRun rg, rq;
-        if (k > kWave) {
-            if ((e = hipEventRecord(c->ev_fork, s)) != hipSuccess) return e;
-            if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
-            forked = true;
+        if (forked) {   // forked above, behind the Gaussians' projections
             e = kd_start(rg, c->kd_g, c->kd_work_g, P, c->g_mr.as<float>(), k,
                          c->gperm.as<int32_t>(), c->g_mr_s.as<float>(), c->side);
             g_sorted = true;
