@@ -131,10 +131,3 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(ngd, "_lib", None)
     with pytest.raises(ImportError):
         ngd.lib()
-
-
-def test_record_stride_matches_documented_layout():
-    # m (n) | S' (n(n+1)/2) | alpha c (3) | alpha | c (3), padded to 4 floats
-    for n, want in [(1, 12), (4, 24), (6, 36), (10, 72), (12, 100)]:
-        assert (n + n * (n + 1) // 2 + 7 + 3) // 4 * 4 == want
-    assert np.dtype(np.float32).itemsize == 4

@@ -195,7 +195,7 @@ def test_symmetries_permutation_and_linearity():
 def test_spd_from_any_factor():
     """Sec. 3.1: V = L L^T is symmetric positive definite for any L with a
     nonzero diagonal, and its Cholesky factor is L up to the signs of the
-    columns (P:295's uniqueness up to unitary transforms)."""
+    columns (Sec. 3.1: the factor is unique up to the signs of its columns)."""
     rng = np.random.default_rng(11)
     mix = inputs.gen_mixture(10, 64, "pos3+nrm3+view3+rough1", (10, 200), 5.0, seed=5)
     r, c = np.tril_indices(10)
