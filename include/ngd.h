@@ -248,6 +248,26 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull,
 int ngd_l2_loss(const float *f, const float *target, int64_t q, float *loss,
                 float *grad, void *stream);
 
+/* Largest q the allocation-free loss accepts (its scratch does not grow
+ * with q: 1024 float64 partial sums, 8 KiB per device). */
+#define NGD_NOALLOC_MAX_Q 2147483647LL
+
+/* ngd_l2_loss without any allocation, for callers that cannot allocate
+ * device memory while they run: code under HIP graph capture, tight serving
+ * or training loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels, partition and result (bit for bit) as ngd_l2_loss.  Its partial
+ * sums live in a static device array of 8 KiB, one per GPU, held until the
+ * process ends; its device address is looked up once per device on the
+ * first call with that device current (hipGetSymbolAddress).  Every call on
+ * one GPU shares that array: calls that overlap on one GPU (two streams, two
+ * threads) race and may return wrong sums.  Each partial is written before
+ * it is read, so nothing is cleared between calls.  q outside
+ * [0, NGD_NOALLOC_MAX_Q] or NULL / misaligned arrays: NGD_E_INVAL before any
+ * device work.  No hipMalloc, hipFree or allocating library call.  Does not
+ * synchronise. */
+int ngd_l2_loss_noalloc(const float *f, const float *target, int64_t q, float *loss,
+                        float *grad, void *stream);
+
 /* Relative squared error, the loss the paper trains with (Sec. 4.1 names a
  * relative L2 loss after Noise2Noise): each error is divided by the squared
  * prediction scale, which is held constant for the gradient,

@@ -125,6 +125,34 @@ int l2_loss_impl(const char *who, const float *f, const float *target, int64_t q
     if (e != hipSuccess) return hip_fail(e, who);
     return NGD_OK;
 }
+// Partial sums of the allocation-free loss: one array per device, held
+// until the process ends.  Host code never passes this name to a kernel or
+// a copy (on the host it is only a stand-in for the symbol); it uses the
+// device address hipGetSymbolAddress returns for the current device.
+constexpr int kStaticParts = 1024;
+static __device__ __align__(256) double scratch[kStaticParts];
+
+// The device address of `scratch` on the current device, looked up once per
+// device with that device current.
+int static_scratch(const char *who, double **out)
+{
+    static std::mutex mu;
+    static double *addr[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, who);
+    if (dev < 0 || dev >= 64) return fail(NGD_E_INVAL, "%s: device %d", who, dev);
+    std::lock_guard<std::mutex> lk(mu);
+    if (!addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, who);
+        addr[dev] = static_cast<double *>(p);
+    }
+    *out = addr[dev];
+    return NGD_OK;
+}
 }  // namespace
 
 extern "C" {
@@ -605,6 +633,28 @@ int ngd_l2_loss(const float *f, const float *target, int64_t q, float *loss, flo
                 void *stream)
 {
     return l2_loss_impl("ngd_l2_loss", f, target, q, loss, grad, 0.0f, stream);
+}
+
+int ngd_l2_loss_noalloc(const float *f, const float *target, int64_t q, float *loss,
+                        float *grad, void *stream)
+{
+    const char *who = "ngd_l2_loss_noalloc";
+    if (q < 0 || q > NGD_NOALLOC_MAX_Q)
+        return fail(NGD_E_INVAL, "%s: q=%lld outside [0, %lld]", who, (long long)q,
+                    (long long)NGD_NOALLOC_MAX_Q);
+    if (!loss || (q > 0 && (!f || !target || !grad)))
+        return fail(NGD_E_INVAL, "%s: NULL array", who);
+    if (!aligned4(f) || !aligned4(target) || !aligned4(grad) || !aligned4(loss))
+        return fail(NGD_E_INVAL, "%s: arrays must be 4-byte aligned", who);
+    double *parts = nullptr;
+    int rc = static_scratch(who, &parts);
+    if (rc != NGD_OK) return rc;
+    // the same kernels and partition as ngd_l2_loss (kStaticParts partials,
+    // each written before the final pass reads it: nothing to clear)
+    const hipError_t e = launch_l2_loss(f, target, q, loss, grad, reinterpret_cast<float *>(parts),
+                                        kStaticParts, S(stream), 0.0f);
+    if (e != hipSuccess) return hip_fail(e, who);
+    return NGD_OK;
 }
 
 int ngd_rel_l2_loss(const float *f, const float *target, int64_t q, float eps, float *loss,

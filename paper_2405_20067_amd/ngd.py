@@ -15,8 +15,8 @@ import numpy as np
 
 __all__ = [
     "NgdError", "CullParams", "Mixture", "Cull", "lib", "LIB_PATH",
-    "eval_mixture", "eval_prepare", "eval_backward", "eval_stats", "l2_loss", "rel_l2_loss", "FP32",
-    "BF16_MFMA",
+    "eval_mixture", "eval_prepare", "eval_backward", "eval_stats", "l2_loss", "l2_loss_noalloc",
+    "rel_l2_loss", "FP32", "BF16_MFMA",
     "E_INVAL", "E_SINGULAR", "E_HIP", "E_NOMEM", "E_STALE",
 ]
 
@@ -81,6 +81,9 @@ _SIGS = [
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
       ctypes.c_int] + [ctypes.c_void_p] * 5),
     ("ngd_l2_loss", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_void_p]),
+    ("ngd_l2_loss_noalloc", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p]),
     ("ngd_rel_l2_loss", ctypes.c_int,
@@ -333,4 +336,14 @@ def l2_loss(f, target, loss=None, grad=None, stream=None):
     _check(lib().ngd_l2_loss(_ptr(f, "f", q * 3), _ptr(target, "target", q * 3), q,
                              _ptr(loss, "loss", 1), _ptr(grad, "grad", q * 3),
                              _stream(stream)))
+    return loss, grad
+
+
+def l2_loss_noalloc(f, target, loss, grad, stream=None):
+    """ngd_l2_loss_noalloc: the mean squared error and its gradient into the
+    caller's `loss` (1) and `grad` (q x 3), with no allocation anywhere."""
+    q = f.numel() // 3
+    _check(lib().ngd_l2_loss_noalloc(_ptr(f, "f", q * 3), _ptr(target, "target", q * 3), q,
+                                     _ptr(loss, "loss", 1), _ptr(grad, "grad", q * 3),
+                                     _stream(stream)))
     return loss, grad

@@ -85,6 +85,16 @@ def test_l2_loss_argument_checks(L):
                          ctypes.c_void_p(16), None) == ngd.E_INVAL   # misaligned
 
 
+def test_l2_loss_noalloc_argument_checks(L):
+    one = ctypes.c_void_p(16)
+    assert L.ngd_l2_loss_noalloc(None, None, -1, one, one, None) == ngd.E_INVAL
+    assert L.ngd_l2_loss_noalloc(one, one, 1 << 31, one, one, None) == ngd.E_INVAL
+    assert b"outside" in L.ngd_last_error()
+    assert L.ngd_l2_loss_noalloc(None, None, 5, one, None, None) == ngd.E_INVAL
+    assert L.ngd_l2_loss_noalloc(ctypes.c_void_p(2), one, 5, one, one,
+                                 None) == ngd.E_INVAL   # misaligned
+
+
 def test_rel_l2_loss_argument_checks(L):
     one = ctypes.c_void_p(16)
     for eps in (0.0, -0.01, float("nan"), float("inf")):
