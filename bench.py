@@ -29,7 +29,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-FP32_VALU_PEAK_TFLOPS = 157.3   # published dense FP32 vector peak (packed)
+# Published dense FP32 vector peak without packed-FP32 instructions: the
+# library is built with those disabled, so 157.3 (packed) is out of reach.
+FP32_VALU_PEAK_TFLOPS = 78.6
 BF16_MFMA_PEAK_TFLOPS = 2500.0  # published dense BF16 matrix peak
 TRAFFIC_FILES = dict(fp32=os.path.join(ROOT, "profiles", "forward_10d_traffic.json"),
                      bf16_mfma=os.path.join(ROOT, "profiles", "forward_mfma_10d_traffic.json"))
@@ -45,6 +47,21 @@ def stage_flops(n: int):
     k1, k2 = min(3, n), min(6, n)
     rows = lambda a, b: sum(1 + 1 + 2 * r + 2 for r in range(a, b))
     return rows(0, k1), rows(k1, k2), rows(k2, n), 1 + 6
+
+
+def fp32_pair_flops(n: int) -> int:
+    """Algorithmic float32 flops of one (query, Gaussian) pair of the direct
+    sum: n subtractions, the triangular product y = S'(x - m) (n(n+1)/2
+    fmas), the squared norm (n fmas), exp2 and the 3 colour fmas -- 38, 66
+    and 146 at n = 4, 6, 10."""
+    return 3 * n + n * (n + 1) + 6
+
+
+def mfma_pair_flops(n: int) -> int:
+    """Algorithmic matrix-core flops of one (query, candidate) pair: one
+    multiply-add per quadratic feature (1 + n + n(n+1)/2; 132 flops at
+    n = 10)."""
+    return 2 * (1 + n + n * (n + 1) // 2)
 
 
 def source_hash(*paths):
@@ -91,11 +108,15 @@ def targets(w, tgt, dev, proj):
     return t
 
 
-def cpu_baseline(w, mix, x, budget_s: float):
+def cpu_baseline(w, mix, x, budget_s: float, threads: int = 0):
     """The float64 oracle, fwd (direct sum over all K) + bwd (gradient of all
-    K Gaussians) on a sample of queries, timed on this host."""
+    K Gaussians) on a sample of queries, timed on this host with `threads`
+    OpenMP threads (0: all the library starts with)."""
     import oracle
     from paper_2405_20067_amd import inputs
+    full = oracle.threads() if not hasattr(cpu_baseline, "full") else cpu_baseline.full
+    cpu_baseline.full = full
+    oracle.set_threads(threads if threads > 0 else full)
     rng = np.random.default_rng(12345)
     g_all = inputs.gen_grad_out(w.q, seed=77)
     def run(nq):
@@ -109,29 +130,35 @@ def cpu_baseline(w, mix, x, budget_s: float):
         return t1 - t0, t2 - t1
     # probe with enough queries to keep every core busy, then scale the
     # sample to the time budget
-    probe = 256
+    used = int(oracle.threads())
+    probe = max(4, min(256, 16 * used))
     a, b = run(probe)
     nq = int(max(probe, min(w.q, probe * budget_s / max(a + b, 1e-6))))
     tf, tb = run(nq)
+    oracle.set_threads(full)
     pairs = nq * w.k
     return dict(value=pairs / (tf + tb), unit="Gaussian-query evals/s",
-                cores=int(oracle.threads()), kind="oracle",
+                cores=used, kind="oracle",
                 sample=f"{nq} of the {w.q} queries (seeded), every one of the {w.k} "
                        f"Gaussians: float64 forward sum ({tf:.1f}s) + gradient of all "
-                       f"Gaussians over those queries ({tb:.1f}s)",
+                       f"Gaussians over those queries ({tb:.1f}s), {used} thread(s)",
                 fwd_s=tf, bwd_s=tb, pairs=pairs)
 
 
 def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-3,
-              lr_alpha: float = 1e-2):
+              lr_alpha: float = 3e-2, init_scale: float = 0.7, per_component: int = 8,
+              child_alpha: float = 1e-4, checkpoint: str | None = None):
     """The 10-D fitting loop (Adam, children from the second phase,
     materialised above t = 0.01): K starts at 32,768 Gaussians and may grow
     to 524,288; 2^21 queries near the hidden K=4,096 target mixture and
     uniform, their target values computed once.  The start stands in for an
-    initialisation from the data: 8 Gaussians per target component, means
-    drawn from that component, factors 1.5x wider, brightness 1/8, colours
-    random.  Every step is timed; set-up (query pool, targets, handles) is
-    not."""
+    initialisation from the data: `per_component` Gaussians per target
+    component, means drawn from that component, factors scaled by
+    `init_scale` (below 1: narrower than the target, so the start
+    under-covers it and children have room to grow), brightness
+    1/per_component, colours random.  Every step is timed; set-up (query
+    pool, targets, handles) is not.  `checkpoint`: the fit's state is saved
+    there at the end."""
     import torch
     from paper_2405_20067_amd import inputs, ngd
     from paper_2405_20067_amd.fit import Fit
@@ -139,14 +166,15 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
     k0, q, max_k = 32768, 1 << 21, 524288
     tgt = inputs.workload_mixture(w, k=w.k_target, seed=inputs.SEED_TARGET)
     rng = np.random.default_rng(inputs.SEED_MIXTURE)
-    rep = k0 // w.k_target
+    rep = per_component
+    k0 = rep * w.k_target
     src = np.repeat(np.arange(w.k_target), rep)
     lfull = np.zeros((k0, w.n, w.n))
     r, c = np.tril_indices(w.n)
     lfull[:, r, c] = tgt["factor"][src]
     z = rng.standard_normal((k0, w.n))
     mix = dict(mean=tgt["mean"][src] + np.einsum("kij,kj->ki", lfull, z),
-               factor=1.5 * tgt["factor"][src], weight=tgt["weight"][src] / rep,
+               factor=init_scale * tgt["factor"][src], weight=tgt["weight"][src] / rep,
                colour=rng.uniform(0.05, 0.95, (k0, 3)))
     mix = {a: np.ascontiguousarray(v, np.float32) for a, v in mix.items()}
     x = inputs.gen_workload_queries(w, q=q, mixtures=[tgt])
@@ -156,7 +184,8 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
     target = targets(w, tgt, dev, proj)
     prec = ngd.BF16_MFMA if precision_name == "bf16_mfma" else ngd.FP32
     fit = Fit(d(mix["mean"]), d(mix["factor"]), d(mix["weight"]), d(mix["colour"]), lr=lr,
-              lr_alpha=lr_alpha, phase=phase, max_k=max_k, precision=prec)
+              lr_alpha=lr_alpha, phase=phase, max_k=max_k, precision=prec,
+              child_alpha=child_alpha)
     log(f"fit: n={w.n} k0={k0} q={q} steps={steps} phase={phase} lr={lr}/{lr_alpha} "
         f"{precision_name}")
     ks, losses = [], []
@@ -170,6 +199,8 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
             log(f"fit step {i + 1}: loss {losses[-1][1]:.5g}, K {fit.k}")
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
+    if checkpoint:
+        fit.save(checkpoint)
     print(json.dumps(dict(
         metric="10-D fitting loop time per step (update, cull, fwd, loss, bwd, Adam, refinement)",
         value=ms, unit="ms/step", n_gpus=1, steps=steps, warmup=0, ms_per_step=ms,
@@ -177,8 +208,9 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
         dtype="bf16+f32" if prec == ngd.BF16_MFMA else "f32", data="synthetic",
         config=dict(workload="10d-fit", n=w.n, k_start=k0, k_max=max_k, q=q, phase=phase,
                     lr=lr, lr_alpha=lr_alpha, threshold=fit.threshold, loss="l2",
-                    precision=precision_name, init="8 per target component",
-                    k_target=w.k_target),
+                    precision=precision_name,
+                    init=f"{rep} per target component, factors x{init_scale}",
+                    child_alpha=child_alpha, k_target=w.k_target),
         initial_loss=losses[0][1], final_loss=losses[-1][1], loss_trajectory=losses,
         k_trajectory=ks)), flush=True)
 
@@ -242,46 +274,69 @@ def sweep_bench(reps: int = 5, sample: int = 4096):
         rows=rows)), flush=True)
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="10d-fwdbwd")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-dense", action="store_true")
-    ap.add_argument("--precision", default="both", choices=["fp32", "bf16_mfma", "both"],
-                    help="forward arithmetic of the timed step; 'both' times the step once "
-                         "with each and reports the faster as the headline")
-    ap.add_argument("--profile", action="store_true",
-                    help="short run for rocprofv3 (3 steps, 1 warmup, no CPU/dense legs) "
-                         "plus one 256 MiB device copy to calibrate memory counters")
-    ap.add_argument("--sweep", action="store_true",
-                    help="instead of the step benchmark, sweep the cull threshold tau and "
-                         "the tile size and print one line of rows")
-    ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
-                    help="instead of the step benchmark, run the 10-D fitting loop for "
-                         "STEPS steps and print its own line (ms/step, losses, K)")
-    args = ap.parse_args()
-    if args.profile:
-        args.steps, args.warmup, args.no_cpu_baseline, args.no_dense = 3, 1, True, True
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(run with --gpus 1)", file=sys.stderr)
-        sys.exit(2)
+def forward_roofline(w, m, cull, dev, prec, name, t, cand_pairs):
+    """Roofline of one path's culled forward kernel.  `t` is its launch time
+    (median over the timed steps, HIP events on the library's stream).
 
+    FP32 (ALU bound): the float32 flops the kernel executes, counted by the
+    same kernel in a counting mode on the same cull (its staged checks skip
+    most of the candidate pairs' rows), against the non-packed FP32 peak.
+    BF16-MFMA (matrix-core bound): the algorithmic contraction, one
+    multiply-add per quadratic feature for every (query, candidate) pair the
+    cull kept, against the dense BF16 peak; what the kernel executes (three
+    split products, padded k-steps) is reported beside it."""
+    from paper_2405_20067_amd import ngd
+    cnt = ngd.eval_stats(m, cull, dev["x"], precision=prec)
+    f1, f2, f3, f4 = stage_flops(w.n)
+    valu = 64 * (f1 * cnt["filtered"] + f2 * cnt["pass1"] + f3 * cnt["pass2"]
+                 + f4 * cnt["kept"])
+    src = (KERNEL_SRC,) if name == "fp32" else (MFMA_SRC, KERNEL_SRC)
+    traffic = None
+    tf = TRAFFIC_FILES[name]
+    if os.path.exists(tf):
+        tr = json.load(open(tf))
+        if tr.get("source_sha256_16") == source_hash(*src) and tr.get("workload") == w.name:
+            traffic = tr.get("hbm_bytes_per_launch")
+    if name == "fp32":
+        a = valu / t / 1e12
+        return dict(bound="alu", kernel="forward: k_eval_items + k_eval_reduce (ngd_eval)",
+                    achieved=a, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=a / FP32_VALU_PEAK_TFLOPS, traffic=traffic,
+                    units=dict(group_candidate_pairs=cnt,
+                               flops_per_lane_per_stage=[f1, f2, f3, f4],
+                               lanes_per_pair=64, flops_per_launch=valu,
+                               algorithmic_flops_per_pair=fp32_pair_flops(w.n),
+                               candidate_pairs=cand_pairs,
+                               launch_ms=t * 1e3))
+    nf = 1 + w.n + w.n * (w.n + 1) // 2
+    ks = 1 + (w.n * (w.n + 1) // 2 + 15) // 16
+    alg = cand_pairs * mfma_pair_flops(w.n)
+    a = alg / t / 1e12
+    return dict(bound="mfma", kernel="forward: k_mfma_filter (ngd_eval, NGD_BF16_MFMA; "
+                                     "its once-per-build records timed apart as "
+                                     "eval_prepare)",
+                achieved=a, peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
+                frac=a / BF16_MFMA_PEAK_TFLOPS, traffic=traffic,
+                units=dict(candidate_pairs=cand_pairs, features=nf,
+                           flops_per_pair=mfma_pair_flops(w.n),
+                           flops_per_launch=alg, launch_ms=t * 1e3,
+                           group_candidate_pairs=cnt,
+                           executed_split_flops=cnt["examined"] * 64 * nf * 2 * 3,
+                           executed_padded_flops=cnt["examined"] * 64 * ks * 16 * 2 * 3,
+                           executed_split_tflops=cnt["examined"] * 64 * nf * 6 / t / 1e12,
+                           fp32_survivor_flops=valu,
+                           fp32_survivor_tflops=valu / t / 1e12))
+
+
+def run_workload(name: str, args, precisions, with_dense: bool, steps: int, warmup: int,
+                 profile_copy: bool = False):
+    """Times `steps` steps of one workload (after `warmup` untimed ones) for
+    each forward precision, and returns the workload's record: per path the
+    step time, its stages, dense-equivalent evals/s and the forward's
+    roofline; the cull's statistics; the dense float32 direct sum once."""
     import torch
     from paper_2405_20067_amd import ngd
-    torch.cuda.set_device(0)
-    ngd.lib()
-    if args.fit > 0:
-        fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma")
-        return
-    if args.sweep:
-        sweep_bench()
-        return
-    w, mix, tgt, x, proj, dev = setup(args.workload)
+    w, mix, tgt, x, proj, dev = setup(name)
     target = targets(w, tgt, dev, proj) if w.backward else None
 
     m = ngd.Mixture(w.n, w.k)
@@ -322,14 +377,14 @@ def main():
         mark(6)
 
     def timed(prec):
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             step(prec)
         torch.cuda.synchronize()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(len(stages) + 1)]
-               for _ in range(args.steps)]
+               for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             step(prec, evs[i])
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -337,32 +392,33 @@ def main():
         for e in evs:
             for j, s in enumerate(stages):
                 per_stage[s].append(e[j].elapsed_time(e[j + 1]))
-        return wall * 1e3 / args.steps, {s: float(np.median(v)) for s, v in per_stage.items()}
+        return wall * 1e3 / steps, {s: float(np.median(v)) for s, v in per_stage.items()}
 
     precs = {"fp32": ngd.FP32, "bf16_mfma": ngd.BF16_MFMA}
-    chosen = list(precs) if args.precision == "both" else [args.precision]
-    if not w.culled:
-        chosen = ["fp32"]
+    chosen = list(precisions) if w.culled else ["fp32"]
     paths = {}
-    for name in chosen:
-        ms, sm = timed(precs[name])
-        paths[name] = dict(ms_per_step=ms, value=w.q * w.k / (ms * 1e-3), stages_ms=sm)
-        log(f"{name}: step {ms:.3f} ms; stages " +
+    for pname in chosen:
+        ms, sm = timed(precs[pname])
+        paths[pname] = dict(ms_per_step=ms, value=w.q * w.k / (ms * 1e-3), stages_ms=sm)
+        log(f"{name} {pname}: step {ms:.3f} ms; stages " +
             ", ".join(f"{s} {v:.3f}" for s, v in sm.items()))
     head = min(paths, key=lambda k: paths[k]["ms_per_step"])
-    ms_step, stage_ms = paths[head]["ms_per_step"], paths[head]["stages_ms"]
-    value = paths[head]["value"]
-    prec = precs[head]
 
     st = cull.stats() if w.culled else dict(total=w.k, ntiles=1, max_per_tile=w.k)
     tile = params.tile
-    cand_pairs = st["total"] * tile if w.culled else w.q * w.k
-    log(f"headline {head}: step {ms_step:.3f} ms"
+    if w.culled:
+        # every tile but the last holds `tile` queries; the workloads' query
+        # counts are multiples of the tile, so candidates x tile is exact
+        assert w.q % tile == 0
+        cand_pairs = st["total"] * tile
+    else:
+        cand_pairs = w.q * w.k
+    log(f"{name} headline {head}: step {paths[head]['ms_per_step']:.3f} ms"
         f"; candidates {st['total']} ({st['total'] / max(st['ntiles'] * w.k, 1):.4%} of "
         f"tile x Gaussian pairs), max/tile {st['max_per_tile']}")
 
     dense = None
-    if not args.no_dense:
+    if with_dense:
         # the plain float32 direct-sum kernels, no culling, same inputs
         e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         e[0].record()
@@ -373,96 +429,145 @@ def main():
         e[2].record()
         torch.cuda.synchronize()
         dense = dict(forward_ms=e[0].elapsed_time(e[1]), backward_ms=e[1].elapsed_time(e[2]))
-        dense["speedup_vs_dense"] = ((dense["forward_ms"] + dense["backward_ms"]) /
-                                     (stage_ms["eval_prepare"] + stage_ms["forward"] +
-                                      stage_ms["backward"]))
-        log(f"dense fp32 direct sum: fwd {dense['forward_ms']:.1f} ms, "
+        if w.culled:
+            # the culled side pays for its cull build and prepare every step
+            for pname, pth in paths.items():
+                sm = pth["stages_ms"]
+                culled = (sm["cull_build"] + sm["eval_prepare"] + sm["forward"] +
+                          sm["backward"])
+                pth["speedup_vs_dense"] = (dense["forward_ms"] + dense["backward_ms"]) / culled
+            dense["speedup_vs_dense"] = paths[head]["speedup_vs_dense"]
+        log(f"{name} dense fp32 direct sum: fwd {dense['forward_ms']:.1f} ms, "
             f"bwd {dense['backward_ms']:.1f} ms")
 
-    fwd_pairs_s = cand_pairs / ((stage_ms["eval_prepare"] + stage_ms["forward"]) * 1e-3)
-
-    def forward_roofline(name):
-        """Roofline of the forward kernel of one path, from the work counted
-        by the same kernel on the same cull and the forward time measured in
-        the timed steps (HIP events on the library's stream)."""
-        cnt = ngd.eval_stats(m, cull, dev["x"], precision=precs[name])
-        f1, f2, f3, f4 = stage_flops(w.n)
-        valu = 64 * (f1 * cnt["filtered"] + f2 * cnt["pass1"] + f3 * cnt["pass2"]
-                     + f4 * cnt["kept"])
-        t = paths[name]["stages_ms"]["forward"] * 1e-3
-        src = (KERNEL_SRC,) if name == "fp32" else (MFMA_SRC, KERNEL_SRC)
-        traffic = None
-        tf = TRAFFIC_FILES[name]
-        if os.path.exists(tf):
-            tr = json.load(open(tf))
-            if tr.get("source_sha256_16") == source_hash(*src) and tr.get("workload") == w.name:
-                traffic = tr.get("hbm_bytes_per_launch")
-        if name == "fp32":
-            a = valu / t / 1e12
-            return dict(bound="alu", kernel="forward: k_eval_items + k_eval_reduce (ngd_eval)",
-                        achieved=a, peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s",
-                        frac=a / FP32_VALU_PEAK_TFLOPS, traffic=traffic,
-                        units=dict(group_candidate_pairs=cnt,
-                                   flops_per_lane_per_stage=[f1, f2, f3, f4],
-                                   lanes_per_pair=64, flops_per_launch=valu,
-                                   launch_ms=t * 1e3))
-        nf = 1 + w.n + w.n * (w.n + 1) // 2
-        ks = 1 + (w.n * (w.n + 1) // 2 + 15) // 16
-        alg = cnt["examined"] * 64 * nf * 2 * 3
-        a = alg / t / 1e12
-        return dict(bound="mfma", kernel="forward: k_mfma_filter (ngd_eval, NGD_BF16_MFMA; "
-                                         "its once-per-build records timed apart as "
-                                         "eval_prepare)",
-                    achieved=a, peak=BF16_MFMA_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=a / BF16_MFMA_PEAK_TFLOPS, traffic=traffic,
-                    units=dict(group_candidate_pairs=cnt, features=nf,
-                               mfma_flops_per_group_pair=64 * nf * 2 * 3,
-                               mfma_flops_per_launch=alg,
-                               mfma_flops_executed_padded=cnt["examined"] * 64 * ks * 16 * 2 * 3,
-                               fp32_survivor_flops=valu,
-                               fp32_survivor_tflops=valu / t / 1e12, launch_ms=t * 1e3))
-
-    roofline = None
-    rooflines = {}
-    if w.culled:
-        for name in paths:
-            rooflines[name] = forward_roofline(name)
-            log(f"{name} forward: {rooflines[name]['units']['group_candidate_pairs']}; "
-                f"{rooflines[name]['achieved']:.1f} {rooflines[name]['unit']} "
-                f"({rooflines[name]['bound']})")
-        roofline = rooflines[head]
-    if args.profile:
+    fl = fp32_pair_flops(w.n)
+    for pname in paths:
+        t = paths[pname]["stages_ms"]["forward"] * 1e-3
+        if not w.culled:
+            a = cand_pairs * fl / t / 1e12
+            paths[pname]["roofline"] = dict(
+                bound="alu", kernel="forward: k_eval_dense (ngd_eval, no cull)", achieved=a,
+                peak=FP32_VALU_PEAK_TFLOPS, unit="TFLOP/s", frac=a / FP32_VALU_PEAK_TFLOPS,
+                traffic=None,
+                units=dict(pairs=cand_pairs, flops_per_pair=fl, launch_ms=t * 1e3))
+        else:
+            paths[pname]["roofline"] = forward_roofline(w, m, cull, dev, precs[pname], pname, t,
+                                                        cand_pairs)
+        r = paths[pname]["roofline"]
+        log(f"{name} {pname} forward: {r['achieved']:.1f} {r['unit']} ({r['bound']}, "
+            f"frac {r['frac']:.3f})")
+    if profile_copy:
         src = torch.empty(64 << 20, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         log("calibration copy: 268435456 bytes read, 268435456 bytes written")
+        del src, dst
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle ...")
-        cpu = cpu_baseline(w, mix, x, args.cpu_seconds)
-
-    out = dict(
-        metric="Gaussian-query evals/sec, culled fwd+bwd 10-D, + % HBM/MFMA roofline",
-        value=value, unit="Gaussian-query evals/s (dense-equivalent Q*K per step time)",
-        n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=ms_step,
-        higher_is_better=True, scaling="weak", vs_baseline=None,
-        dtype="f32" if head == "fp32" else "bf16+f32",
-        data="synthetic",
-        config=dict(workload=w.name, description=w.description, n=w.n, k=w.k, q=w.q,
-                    k_target=w.k_target, near_frac=w.near_frac, n_proj=params.n_proj,
-                    tau=params.tau, tile=params.tile,
-                    tiling="k-d" if params.tiling == 0 else "morton"),
-        precision=head, stages_ms=stage_ms,
-        paths={k: dict(v, roofline=rooflines.get(k)) for k, v in paths.items()},
+    rec = dict(
+        workload=w.name, description=w.description, n=w.n, k=w.k, q=w.q,
+        k_target=w.k_target, near_frac=w.near_frac, n_proj=params.n_proj,
+        tau=params.tau, tile=params.tile,
+        tiling="k-d" if params.tiling == 0 else "morton",
+        head=head, value=paths[head]["value"], ms_per_step=paths[head]["ms_per_step"],
+        stages_ms=paths[head]["stages_ms"], paths=paths,
         cull=dict(candidates=st["total"], ntiles=st["ntiles"], max_per_tile=st["max_per_tile"],
                   candidate_pairs=cand_pairs,
                   survivor_fraction=st["total"] / max(st["ntiles"] * w.k, 1)),
-        candidate_pairs_per_s_forward=fwd_pairs_s,
-        dense_fp32=dense, roofline=roofline, cpu_baseline=cpu)
+        candidate_pairs_per_s_forward=cand_pairs / (
+            (paths[head]["stages_ms"]["eval_prepare"] + paths[head]["stages_ms"]["forward"])
+            * 1e-3),
+        dense_fp32=dense)
+    return rec, (w, mix, x)
+
+
+# the workloads of the other configurations, timed after the headline one
+# and reported beside it in the same line
+OTHER_WORKLOADS = ("4d-dense", "6d-culled", "10d-4m")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="10d-fwdbwd")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense", action="store_true")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="time only --workload, not the other configurations")
+    ap.add_argument("--precision", default="both", choices=["fp32", "bf16_mfma", "both"],
+                    help="forward arithmetic of the timed step; 'both' times the step once "
+                         "with each and reports the faster as the headline")
+    ap.add_argument("--profile", action="store_true",
+                    help="short run for rocprofv3 (3 steps, 1 warmup, no CPU/dense legs, "
+                         "no other configurations) plus one 256 MiB device copy to "
+                         "calibrate memory counters")
+    ap.add_argument("--sweep", action="store_true",
+                    help="instead of the step benchmark, sweep the cull threshold tau and "
+                         "the tile size and print one line of rows")
+    ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
+                    help="instead of the step benchmark, run the 10-D fitting loop for "
+                         "STEPS steps and print its own line (ms/step, losses, K)")
+    args = ap.parse_args()
+    if args.profile:
+        args.steps, args.warmup = 3, 1
+        args.no_cpu_baseline = args.no_dense = args.no_configs = True
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2405_20067_amd import ngd
+    torch.cuda.set_device(0)
+    ngd.lib()
+    if args.fit > 0:
+        fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma")
+        return
+    if args.sweep:
+        sweep_bench()
+        return
+    precisions = ["fp32", "bf16_mfma"] if args.precision == "both" else [args.precision]
+    rec, (w, mix, x) = run_workload(args.workload, args, precisions, not args.no_dense,
+                                    args.steps, args.warmup, profile_copy=args.profile)
+    torch.cuda.empty_cache()
+    others = {}
+    if not args.no_configs:
+        for name in OTHER_WORKLOADS:
+            if name == args.workload:
+                continue
+            others[name], _ = run_workload(name, args, precisions, not args.no_dense,
+                                           max(3, args.steps // 2), max(1, args.warmup))
+            torch.cuda.empty_cache()
+
+    cpu = cpu1 = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle (all threads, then one) ...")
+        cpu = cpu_baseline(w, mix, x, args.cpu_seconds)
+        cpu1 = cpu_baseline(w, mix, x, max(2.0, args.cpu_seconds / 3), threads=1)
+        cpu["single_core"] = cpu1
+
+    head = rec["head"]
+    out = dict(
+        metric="Gaussian-query evals/sec, culled fwd+bwd 10-D, + % HBM/MFMA roofline",
+        value=rec["value"], unit="Gaussian-query evals/s (dense-equivalent Q*K per step time)",
+        n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=rec["ms_per_step"],
+        higher_is_better=True, scaling="weak", vs_baseline=None,
+        dtype="f32" if head == "fp32" else "bf16+f32",
+        data="synthetic",
+        config=dict(workload=rec["workload"], description=rec["description"], n=rec["n"],
+                    k=rec["k"], q=rec["q"], k_target=rec["k_target"],
+                    near_frac=rec["near_frac"], n_proj=rec["n_proj"], tau=rec["tau"],
+                    tile=rec["tile"], tiling=rec["tiling"]),
+        precision=head, stages_ms=rec["stages_ms"], paths=rec["paths"], cull=rec["cull"],
+        candidate_pairs_per_s_forward=rec["candidate_pairs_per_s_forward"],
+        dense_fp32=rec["dense_fp32"], roofline=rec["paths"][head]["roofline"],
+        cpu_baseline=cpu, configs=others)
     if cpu is not None:
-        out["speedup_vs_cpu_oracle"] = value / cpu["value"]
+        out["speedup_vs_cpu_oracle"] = rec["value"] / cpu["value"]
+        out["speedup_vs_cpu_oracle_1core"] = rec["value"] / cpu1["value"]
     print(json.dumps(out), flush=True)
 
 

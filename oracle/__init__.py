@@ -55,6 +55,8 @@ def lib():
     i, i64, p = ctypes.c_int, ctypes.c_int64, ctypes.c_void_p
     L.ngd_oracle_threads.argtypes = []
     L.ngd_oracle_threads.restype = ctypes.c_int
+    L.ngd_oracle_set_threads.argtypes = [i]
+    L.ngd_oracle_set_threads.restype = ctypes.c_int
     L.ngd_oracle_gaussian.argtypes = [i, _f64p, _f64p, _f64p]
     L.ngd_oracle_gaussian.restype = ctypes.c_double
     L.ngd_oracle_eval.argtypes = [i, i64, _f64p, _f64p, _f64p, _f64p, i64, _f64p, _f64p]
@@ -107,6 +109,11 @@ def _check_mix(mean, factor, weight, colour):
 def threads() -> int:
     """OpenMP threads the oracle uses."""
     return lib().ngd_oracle_threads()
+
+
+def set_threads(t: int) -> int:
+    """Sets the OpenMP threads of later calls; returns the count in force."""
+    return lib().ngd_oracle_set_threads(int(t))
 
 
 def gaussian(mean, factor, x) -> float:

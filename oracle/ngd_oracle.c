@@ -53,6 +53,19 @@ int ngd_oracle_threads(void)
 #endif
 }
 
+/* Sets the threads of the later parallel loops (timing on one core or all);
+ * returns the count now in force. */
+int ngd_oracle_set_threads(int t)
+{
+#ifdef _OPENMP
+    if (t > 0) omp_set_num_threads(t);
+    return omp_get_max_threads();
+#else
+    (void)t;
+    return 1;
+#endif
+}
+
 static inline int64_t tri_idx(int i, int j) { return (int64_t)i * (i + 1) / 2 + j; }
 
 /* Solve L y = d (forward substitution), return y^T y. */
