@@ -510,6 +510,14 @@ def main():
     ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
                     help="instead of the step benchmark, run the 10-D fitting loop for "
                          "STEPS steps and print its own line (ms/step, losses, K)")
+    ap.add_argument("--fit-lr-alpha", type=float, default=3e-2,
+                    help="Adam learning rate of the log-brightnesses in --fit")
+    ap.add_argument("--fit-init-scale", type=float, default=0.7,
+                    help="factor scale of the start relative to the target's in --fit")
+    ap.add_argument("--fit-child-alpha", type=float, default=1e-4,
+                    help="brightness of a new child in --fit")
+    ap.add_argument("--fit-checkpoint", default=None,
+                    help="file the fit's final state is saved to (--fit)")
     args = ap.parse_args()
     if args.profile:
         args.steps, args.warmup = 3, 1
@@ -524,7 +532,9 @@ def main():
     torch.cuda.set_device(0)
     ngd.lib()
     if args.fit > 0:
-        fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma")
+        fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma",
+                  lr_alpha=args.fit_lr_alpha, init_scale=args.fit_init_scale,
+                  child_alpha=args.fit_child_alpha, checkpoint=args.fit_checkpoint)
         return
     if args.sweep:
         sweep_bench()

@@ -1,25 +1,34 @@
 """Fitting loop on the culled path, with optimisation-controlled refinement.
 
-Each step runs the library's path unchanged (ngd_mixture_update,
-ngd_cull_build, ngd_eval, the loss, ngd_eval_backward); torch holds the raw
-parameters, applies the activations of Sec. 4.1 (brightness alpha = exp(a),
-colour c = sigmoid(c_raw); mean and factor L are used as they are) and the
-parent-child composition of Sec. 3.3, takes the chain rule from the
-library's gradients with respect to the activated parameters, and steps
-Adam.
+Each step is one differentiable evaluation through the torch.autograd layer
+(`NgdMixtureEval`: ngd_mixture_update, ngd_cull_build, ngd_eval; its
+backward ngd_eval_backward), the library's loss (`NgdL2Loss`), and an Adam
+step on raw parameters.  The activations are torch ops, so autograd chains
+the library's gradients through them:
+
+    Sec. 3.1  factor L: exp on the diagonal, 2 sigmoid - 1 strictly below it
+    Sec. 4.1  brightness alpha = exp(a), colour c = sigmoid(c_raw)
+
+so every factor the library receives has a positive diagonal.
 
 Refinement (Sec. 3.3, Eq. 6-7): from the second phase on, every parent
 carries one child defined in the parent's frame by a relative factor U
-(lower triangular) and offset m_u:
+(lower triangular, the same activations as L) and offset m_u:
 
     L_child = L_parent U,    m_child = L_parent m_u + m_parent,
 
 so that the child follows every update of its parent.  A new child spans its
-parent (U = I, m_u = 0 up to a small random perturbation) with a negligible
-brightness.  At the end of each phase the children whose brightness exceeds
-the threshold t are materialised: they become parents (with their absolute
-parameters, so the represented function does not change), and their slot,
-like every new parent, gets a fresh default child.
+parent (raw U = 0, i.e. U = I, and m_u = 0, up to a small random
+perturbation) with a negligible brightness.  At the end of each phase the
+children whose brightness exceeds the threshold t are materialised: they
+become parents (with their absolute parameters, so the represented function
+does not change), and their slot, like every new parent, gets a fresh
+default child.
+
+`state_dict` / `load_state_dict` (and `save` / `load`, plain tensors through
+torch.save) carry the raw parameters, the children, Adam's moments, the step
+count and the random generator, so that a run resumed from a checkpoint
+takes the same steps as one that was not interrupted.
 """
 
 from __future__ import annotations
@@ -29,8 +38,9 @@ import math
 import torch
 
 from . import ngd
+from .autograd import Evaluator, NgdL2Loss, NgdMixtureEval, activate_factor, raw_factor
 
-__all__ = ["compose_child", "pack", "unpack", "Fit"]
+__all__ = ["compose_child", "pack", "unpack", "absolute_params", "Fit"]
 
 
 def _tril(n: int, device):
@@ -64,10 +74,26 @@ def compose_child(l_parent, m_parent, u, m_u):
     return pack(lc), mc
 
 
+def absolute_params(n, mean, factor_raw, a, c, child=None):
+    """(mean, L, alpha, colour) of the whole mixture, parents then children,
+    from raw parameters: the activations of Sec. 3.1 / 4.1 and, for the
+    children (raw u, m_u, a, c), the composition of Eq. 6-7."""
+    lp = activate_factor(factor_raw, n)
+    w = torch.exp(a)
+    col = torch.sigmoid(c)
+    if child is None:
+        return mean, lp, w, col
+    u, m_u, a_c, c_c = child
+    lc, mc = compose_child(lp, mean, activate_factor(u, n), m_u)
+    return (torch.cat([mean, mc]), torch.cat([lp, lc]),
+            torch.cat([w, torch.exp(a_c)]), torch.cat([col, torch.sigmoid(c_c)]))
+
+
 class Fit:
     """Adam on raw parameters of a mixture, children from the second phase.
 
-    mean (K, n), factor (K, n(n+1)/2), weight (K,) > 0, colour (K, 3) in
+    mean (K, n), factor (K, n(n+1)/2) with a positive diagonal and
+    strictly-lower entries in (-1, 1), weight (K,) > 0, colour (K, 3) in
     (0, 1): the initial mixture (activated values), any device tensors.
     """
 
@@ -85,13 +111,13 @@ class Fit:
         self.gen.manual_seed(seed)
         f32 = dict(dtype=torch.float32, device=dev)
         self.mean = mean.detach().to(**f32).clone().requires_grad_(True)
-        self.factor = factor.detach().to(**f32).clone().requires_grad_(True)
+        self.factor = raw_factor(factor.detach().to(**f32), self.n).requires_grad_(True)
         self.a = torch.log(weight.detach().to(**f32)).requires_grad_(True)
         self.c = torch.logit(colour.detach().to(**f32).clamp(1e-4, 1 - 1e-4)).requires_grad_(True)
-        self.child = None   # (u, m_u, a, c) once the second phase starts
+        self.child = None   # raw (u, m_u, a, c) once the second phase starts
         self.steps = 0
-        self._mix = None
-        self._cull = ngd.Cull()
+        self.ev = Evaluator(self.n, None, self.params, precision)
+        self.ev.cull = ngd.Cull()
         self._new_optimizer()
 
     # -- parameters ------------------------------------------------------
@@ -117,10 +143,9 @@ class Fit:
     def _default_children(self, count: int):
         n, dev = self.n, self.mean.device
         tri = n * (n + 1) // 2
-        eye = pack(torch.eye(n, device=dev).expand(count, n, n).contiguous())
         j = self.child_jitter
         rnd = lambda *s: torch.randn(*s, generator=self.gen, device=dev)
-        u = eye + j * rnd(count, tri)
+        u = j * rnd(count, tri)            # raw U near 0: U near the identity
         m_u = j * rnd(count, n)
         a = math.log(self.child_alpha) + 0.1 * rnd(count)
         c = rnd(count, 3)
@@ -135,53 +160,35 @@ class Fit:
 
     def absolute(self):
         """The activated mixture (parents, then children), in the graph."""
-        w = torch.exp(self.a)
-        col = torch.sigmoid(self.c)
-        if self.child is None:
-            return self.mean, self.factor, w, col
-        u, m_u, a_c, c_c = self.child
-        lc, mc = compose_child(self.factor, self.mean, u, m_u)
-        return (torch.cat([self.mean, mc]), torch.cat([self.factor, lc]),
-                torch.cat([w, torch.exp(a_c)]), torch.cat([col, torch.sigmoid(c_c)]))
+        return absolute_params(self.n, self.mean, self.factor, self.a, self.c, self.child)
 
     # -- one step --------------------------------------------------------
-    def _mixture(self, mean, factor, weight, colour):
-        k = mean.shape[0]
-        if self._mix is None or self._mix.k != k:
-            self._mix = ngd.Mixture(self.n, k)
-        self._mix.update(mean.detach().contiguous(), factor.detach().contiguous(),
-                         weight.detach().contiguous(), colour.detach().contiguous())
-        return self._mix
-
     def evaluate(self, queries, proj):
         """The current mixture's values at the queries (no gradient)."""
+        self.ev.proj = proj
         with torch.no_grad():
-            mix = self._mixture(*self.absolute())
-            self._cull.build(mix, queries, proj, self.params)
-            return ngd.eval_mixture(mix, self._cull, queries, precision=self.precision)
+            return NgdMixtureEval.apply(*self.absolute(), queries, self.ev)
 
     def step(self, queries, target, proj):
         """One Adam step on the loss of the mixture against target at the
-        queries; returns the loss (a device tensor of one float)."""
-        mean, factor, weight, colour = self.absolute()
-        mix = self._mixture(mean, factor, weight, colour)
-        self._cull.build(mix, queries, proj, self.params)
-        f = ngd.eval_mixture(mix, self._cull, queries, precision=self.precision)
-        if self.loss_kind == "rel":
-            loss, g = ngd.rel_l2_loss(f, target, eps=self.eps)
-        else:
-            loss, g = ngd.l2_loss(f, target)
-        grads = ngd.eval_backward(mix, self._cull, queries, g, precision=self.precision)
+        queries; returns the loss (a device tensor of one float).  At each
+        phase end the loss is read back (one synchronisation per phase) and
+        a non-finite loss raises."""
+        self.ev.proj = proj
+        f = NgdMixtureEval.apply(*self.absolute(), queries, self.ev)
+        loss = NgdL2Loss.apply(f, target, self.eps if self.loss_kind == "rel" else 0.0)
         self.opt.zero_grad(set_to_none=True)
-        torch.autograd.backward([mean, factor, weight, colour], list(grads))
+        loss.backward()
         self.opt.step()
         self.steps += 1
         if self.steps % self.phase == 0:
+            if not math.isfinite(float(loss.detach()[0])):
+                raise FloatingPointError(f"fit: non-finite loss at step {self.steps}")
             if self.child is None:
                 self.add_children()
             else:
                 self.refine()
-        return loss
+        return loss.detach()
 
     # -- refinement --------------------------------------------------------
     def refine(self) -> int:
@@ -197,8 +204,12 @@ class Fit:
             count = int(sel.numel())
             if count == 0:
                 return 0
-            lc, mc = compose_child(self.factor[sel], self.mean[sel], u[sel], m_u[sel])
-            new_parent = [torch.cat([self.mean, mc]), torch.cat([self.factor, lc]),
+            lp = activate_factor(self.factor[sel], self.n)
+            lc, mc = compose_child(lp, self.mean[sel], activate_factor(u[sel], self.n),
+                                   m_u[sel])
+            # the new parents' raw factors (positive diagonal: L_p,ii U_ii > 0)
+            new_parent = [torch.cat([self.mean, mc]),
+                          torch.cat([self.factor, raw_factor(lc, self.n)]),
                           torch.cat([self.a, a_c[sel]]), torch.cat([self.c, c_c[sel]])]
             self.mean, self.factor, self.a, self.c = (t.contiguous().requires_grad_(True)
                                                       for t in new_parent)
@@ -212,3 +223,53 @@ class Fit:
             self.child = tuple(kids)
         self._new_optimizer()
         return count
+
+    # -- checkpoints -------------------------------------------------------
+    def state_dict(self) -> dict:
+        """Raw parameters, children, Adam's state, step count and generator
+        state, as plain tensors and numbers."""
+        names = ["mean", "factor", "a", "c"]
+        st = {f"param.{k}": getattr(self, k).detach().clone() for k in names}
+        if self.child is not None:
+            for k, t in zip(("u", "m_u", "a", "c"), self.child):
+                st[f"child.{k}"] = t.detach().clone()
+        opt = self.opt.state_dict()
+        for i, leaf in enumerate(self._leaves()):
+            s = self.opt.state.get(leaf, {})
+            for key, v in s.items():
+                st[f"adam.{i}.{key}"] = v.detach().clone() if torch.is_tensor(v) else \
+                    torch.tensor(v)
+        st["adam.groups"] = torch.tensor([len(g["params"]) for g in opt["param_groups"]])
+        st["steps"] = torch.tensor(self.steps)
+        st["gen"] = self.gen.get_state()
+        return st
+
+    def load_state_dict(self, st: dict):
+        """Restores what state_dict saved (tensors moved to this fit's
+        device); the hyper-parameters are the constructor's."""
+        dev = self.mean.device
+        get = lambda k: st[k].to(dev)
+        with torch.no_grad():
+            self.mean, self.factor, self.a, self.c = (
+                get(f"param.{k}").clone().requires_grad_(True) for k in ("mean", "factor", "a",
+                                                                          "c"))
+            if "child.u" in st:
+                self.child = tuple(get(f"child.{k}").clone().requires_grad_(True)
+                                   for k in ("u", "m_u", "a", "c"))
+            else:
+                self.child = None
+        self._new_optimizer()
+        for i, leaf in enumerate(self._leaves()):
+            s = {key.split(".", 2)[2]: v for key, v in st.items()
+                 if key.startswith(f"adam.{i}.")}
+            if s:
+                self.opt.state[leaf] = {key: (v.to(dev) if key != "step" else v.clone())
+                                        for key, v in s.items()}
+        self.steps = int(st["steps"])
+        self.gen.set_state(st["gen"])
+
+    def save(self, path: str):
+        torch.save(self.state_dict(), path)
+
+    def load(self, path: str):
+        self.load_state_dict(torch.load(path, map_location="cpu", weights_only=True))

@@ -74,3 +74,53 @@ def per_gaussian_csr(c, q, tile):
         qoff.append(qoff[-1] + qs.size)
     qidx = np.concatenate(qidx) if qidx else np.zeros(0, np.int64)
     return np.array(sel, np.int64), np.array(qoff, np.int64), qidx.astype(np.int64)
+
+
+def queries_of_gaussians(c, sel, q, tile):
+    """(qoff, qidx): the queries of the candidate tiles of each caller
+    Gaussian sel[j] (caller's indices), from an exported cull."""
+    pos = np.empty(len(c["gperm"]), np.int64)
+    pos[c["gperm"]] = np.arange(len(c["gperm"]))
+    qoff, qidx = [0], []
+    for gi in sel:
+        s_pos = pos[gi]
+        tiles = c["g_tiles"][c["g_off"][s_pos]:c["g_off"][s_pos + 1]]
+        qs = (np.concatenate([c["perm"][t * tile:min((t + 1) * tile, q)] for t in tiles])
+              if tiles.size else np.zeros(0, np.int64))
+        qidx.append(qs.astype(np.int64))
+        qoff.append(qoff[-1] + qs.size)
+    qidx = np.concatenate(qidx) if qidx else np.zeros(0, np.int64)
+    return np.array(qoff, np.int64), qidx
+
+
+def omitted_pairs_grad_bound(mix, g, sel, tau):
+    """Per selected Gaussian, a bound on what the pairs the culled gradient
+    leaves out can add to each gradient output, from the cull's guarantee.
+
+    A pair is left out only when the interval test of Eq. 5 rejects it (then
+    by Cauchy-Schwarz, (r^T d)^2 <= sigma_r^2 M, its Mahalanobis distance is
+    M >= kappa^2 = 2 ln(1/tau) at every query of the tile) or when the
+    in-kernel skip certifies G < tau 2^-20 (M larger still).  For M >=
+    kappa^2 >= 2: G <= tau, G sqrt(M) <= tau kappa and G M <= tau kappa^2
+    (exp(-M/2) M^p decreases for M >= 2p).  The pair's terms are
+    d alpha = G s, d c = alpha G g, d m = alpha G s z and d L = tril(alpha G s
+    z y^T), with s = g . c, |y| = sqrt(M) and |z| = |L^-T y| <= |L^-1|_2
+    sqrt(M).  Summed over every query (a superset of the ones left out),
+    with a 1% margin for the float32 rounding of the interval test.
+    Returns (mean, factor, weight, colour) bounds of shapes (s,), (s,),
+    (s,), (s, 3), each bounding every entry of that output."""
+    n = mix["mean"].shape[1]
+    k2 = 2.0 * np.log(1.0 / tau)
+    assert k2 >= 2.0
+    kap = np.sqrt(k2)
+    gsum = np.abs(np.asarray(g, np.float64)).sum(0)          # sum over queries of |g_ch|
+    sel = np.asarray(sel, np.int64)
+    r, cidx = np.tril_indices(n)
+    L = np.zeros((sel.size, n, n))
+    L[:, r, cidx] = mix["factor"][sel]
+    snorm = np.linalg.norm(np.linalg.inv(L), 2, axis=(1, 2))
+    alpha = mix["weight"][sel].astype(np.float64)
+    ssum = np.abs(mix["colour"][sel].astype(np.float64)) @ gsum   # sum over queries of |s|
+    out = (alpha * ssum * snorm * tau * kap, alpha * ssum * snorm * tau * k2, ssum * tau,
+           alpha[:, None] * tau * gsum[None, :])
+    return tuple(1.01 * v for v in out)

@@ -3,7 +3,9 @@ configuration the benchmark times (same inputs, same cull parameters).
 
 The oracle cannot sum every pair at these sizes, so it computes sampled
 outputs one by one: the full float64 sum over all K Gaussians at sampled
-queries, and the float64 gradient of sampled Gaussians over all queries.
+queries, and the float64 gradient of sampled Gaussians, both over their
+candidate tiles' queries (the arithmetic error, bar 1e-4) and over all
+queries (the left-out pairs' terms within the cull's bound).
 The cull is compared with the CPU re-implementation over its whole output.
 """
 
@@ -11,7 +13,8 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_helpers import dev, host, normwise
+from gpu_helpers import (dev, host, normwise, omitted_pairs_grad_bound,
+                         queries_of_gaussians)
 from paper_2405_20067_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -72,17 +75,34 @@ def test_full_size_cull_forward_backward(torch_cuda, name):
     slack = 1e-4 * 2.0 ** -20 * ac.sum(0)
     assert np.all(np.abs(fm.astype(np.float64) - f) <= slack + 1e-6 * np.abs(f).max())
     gm = [host(t) for t in ngd.eval_backward(m, c, xd, dev(g), precision=ngd.BF16_MFMA)]
-    # backward: sampled Gaussians (the ones with the largest gradients among a
-    # random subset, so the comparison is not of zeros) over all queries
+    _check_sampled_backward(mix, x, g, grads, gm, got, w, rng)
+
+
+def _check_sampled_backward(mix, x, g, grads, gm, exported, w, rng, nsel=24):
+    """Sampled Gaussians (the ones with the largest gradients among a random
+    subset, so the comparison is not of zeros): both precisions' gradients
+    against the float64 gradient over the queries of their candidate tiles at
+    1e-4, and against the full float64 gradient over all queries within 1e-4
+    plus the bound on the left-out pairs' terms."""
     pool = rng.choice(w.k, 4096, replace=False)
     mag = np.abs(grads[2][pool])
-    sel = pool[np.argsort(-mag)[:24]]
-    go = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g, sel=sel)
-    for name_o, a, am, b in zip(("mean", "factor", "weight", "colour"), grads, gm, go):
-        # the culled pairs' terms are in the oracle's sum but not in the GPU's;
-        # their share is checked by the small cases; here the bar is 2e-3
-        assert normwise(a[sel], b) <= 2e-3, name_o
-        assert normwise(am[sel], b) <= 2e-3, name_o
+    sel = pool[np.argsort(-mag)[:nsel]]
+    qoff, qidx = queries_of_gaussians(exported, sel, w.q, 256)
+    part = oracle.grad_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g,
+                             sel, qoff, qidx)
+    full = oracle.grad(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g, sel=sel)
+    bounds = omitted_pairs_grad_bound(mix, g, sel, 1e-4)
+    for name_o, a, am, b, f, bd in zip(("mean", "factor", "weight", "colour"), grads, gm, part,
+                                       full, bounds):
+        e32, e16 = normwise(a[sel], b), normwise(am[sel], b)
+        ef = normwise(a[sel], f)
+        print(f"  d{name_o}: fp32 {e32:.2e}, bf16 {e16:.2e} vs candidate pairs; "
+              f"fp32 {ef:.2e} vs all pairs", flush=True)
+        assert e32 <= TOL_FP32, name_o
+        assert e16 <= TOL_FP32, name_o
+        lim = TOL_FP32 * np.abs(f).max() + bd.reshape(len(sel), -1)
+        assert np.all(np.abs(a[sel] - f).reshape(len(sel), -1) <= lim), name_o
+        assert np.all(np.abs(am[sel] - f).reshape(len(sel), -1) <= lim), name_o
 
 
 def test_full_size_4m_queries_both_precisions(torch_cuda):
@@ -105,3 +125,10 @@ def test_full_size_4m_queries_both_precisions(torch_cuda):
     ac = mix["weight"].astype(np.float64)[:, None] * np.abs(mix["colour"])
     slack = 1e-4 * 2.0 ** -20 * ac.sum(0)
     assert np.all(np.abs(fm.astype(np.float64) - ff) <= slack + 1e-6 * np.abs(ff).max())
+    # the backward of both precisions on the same cull
+    g = inputs.gen_grad_out(w.q, seed=37, scale=1.0 / w.q)
+    gd = dev(g)
+    gm = [host(t) for t in ngd.eval_backward(m, c, xd, gd, precision=ngd.BF16_MFMA)]
+    ngd.eval_mixture(m, c, xd, precision=ngd.FP32)
+    grads = [host(t) for t in ngd.eval_backward(m, c, xd, gd, precision=ngd.FP32)]
+    _check_sampled_backward(mix, x, g, grads, gm, c.export(), w, rng)

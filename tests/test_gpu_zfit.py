@@ -101,3 +101,52 @@ def test_materialising_children_keeps_the_function(torch_cuda):
     bound = fresh + 2 * TAU * (a0 + _alpha_sum(fit, torch)) + 1e-6
     assert np.abs(f1 - f0).max() <= bound
     assert fit.refine() == 0   # nothing bright is left
+
+
+def test_fit_gradients_match_the_oracle_chain(torch_cuda):
+    """One fit step's gradients with respect to every raw parameter (parents
+    and children) against the float64 chain: the oracle's value and gradient
+    over the same candidate pairs with respect to the absolute parameters,
+    carried through the activations (Sec. 3.1, 4.1) and the composition
+    (Eq. 6-7) by float64 autograd on the CPU.  Bar 1e-4 normwise."""
+    torch = torch_cuda
+    import oracle
+    from gpu_helpers import normwise, per_gaussian_csr, per_query_csr
+    from paper_2405_20067_amd import ngd
+    from paper_2405_20067_amd.autograd import NgdL2Loss, NgdMixtureEval
+    from paper_2405_20067_amd.fit import absolute_params
+    for n, prec in ((4, ngd.FP32), (10, ngd.BF16_MFMA)):
+        print(f"[fit chain] n={n} precision={prec}", flush=True)
+        xd, target, proj, init = _problem(torch, n=n, k=64, q=16384)
+        fit = _fit(torch, init, child_jitter=0.3, precision=prec)
+        fit.add_children()
+        with torch.no_grad():        # children bright enough to matter
+            fit.child[2].copy_(torch.log(torch.full_like(fit.child[2], 0.05)))
+        fit.ev.proj = proj
+        f = NgdMixtureEval.apply(*fit.absolute(), xd, fit.ev)
+        loss = NgdL2Loss.apply(f, target, 0.0)
+        fit.opt.zero_grad(set_to_none=True)
+        loss.backward()
+        got = [host(t.grad) for t in fit._leaves()]
+
+        q = xd.shape[0]
+        ex = fit.ev.cull.export()
+        x = host(xd).astype(np.float64)
+        leaves = [t.detach().double().cpu().requires_grad_(True) for t in fit._leaves()]
+        ab = absolute_params(n, *leaves[:4], tuple(leaves[4:]))
+        abn = [t.detach().numpy() for t in ab]
+        qoff, gidx = per_query_csr(ex, q, 256)
+        fo = oracle.eval_lists(*abn, x, qoff, gidx)
+        go = 2.0 * (fo - host(target)) / fo.size
+        sel, qoff_g, qidx = per_gaussian_csr(ex, q, 256)
+        part = oracle.grad_lists(*abn, x, go, sel, qoff_g, qidx)
+        full = []
+        for t, p in zip(ab, part):
+            z = np.zeros(t.shape)
+            z[sel] = p.reshape((len(sel),) + tuple(t.shape[1:]))
+            full.append(torch.from_numpy(z))
+        torch.autograd.backward(list(ab), full)
+        for i, (a, leaf) in enumerate(zip(got, leaves)):
+            e = normwise(a, leaf.grad.numpy())
+            print(f"  leaf {i}: normwise {e:.2e}", flush=True)
+            assert e <= 1e-4, (n, i, e)
