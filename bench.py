@@ -147,7 +147,8 @@ def cpu_baseline(w, mix, x, budget_s: float, threads: int = 0):
 
 def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-3,
               lr_alpha: float = 3e-2, init_scale: float = 0.7, per_component: int = 8,
-              child_alpha: float = 1e-4, checkpoint: str | None = None):
+              child_alpha: float = 1e-4, child_jitter: float = 1e-2,
+              checkpoint: str | None = None):
     """The 10-D fitting loop (Adam, children from the second phase,
     materialised above t = 0.01): K starts at 32,768 Gaussians and may grow
     to 524,288; 2^21 queries near the hidden K=4,096 target mixture and
@@ -185,7 +186,7 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
     prec = ngd.BF16_MFMA if precision_name == "bf16_mfma" else ngd.FP32
     fit = Fit(d(mix["mean"]), d(mix["factor"]), d(mix["weight"]), d(mix["colour"]), lr=lr,
               lr_alpha=lr_alpha, phase=phase, max_k=max_k, precision=prec,
-              child_alpha=child_alpha)
+              child_alpha=child_alpha, child_jitter=child_jitter)
     log(f"fit: n={w.n} k0={k0} q={q} steps={steps} phase={phase} lr={lr}/{lr_alpha} "
         f"{precision_name}")
     ks, losses = [], []
@@ -210,7 +211,8 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
                     lr=lr, lr_alpha=lr_alpha, threshold=fit.threshold, loss="l2",
                     precision=precision_name,
                     init=f"{rep} per target component, factors x{init_scale}",
-                    child_alpha=child_alpha, k_target=w.k_target),
+                    child_alpha=child_alpha, child_jitter=child_jitter,
+                    k_target=w.k_target),
         initial_loss=losses[0][1], final_loss=losses[-1][1], loss_trajectory=losses,
         k_trajectory=ks)), flush=True)
 
@@ -219,8 +221,9 @@ def sweep_bench(reps: int = 5, sample: int = 4096):
     """The cull's thresholds on the 10-D workload (Q = 2^20, K = 2^18): for
     each (tau, tile) the candidate fraction of the tile x Gaussian pairs,
     the cull build and both forwards' times (median of reps), and the
-    normwise error of the culled FP32 forward against the dense float32 sum
-    on a seeded sample of queries.  tau = exp(-4.5) is the 3-sigma cut."""
+    normwise error of the culled FP32 forward against the float64 oracle's
+    full sum on a seeded sample of queries.  tau = exp(-4.5) is the 3-sigma
+    cut."""
     import torch
     from paper_2405_20067_amd import inputs, ngd
     w, mix, tgt, x, proj, dev = setup("10d-fwdbwd")
@@ -228,8 +231,12 @@ def sweep_bench(reps: int = 5, sample: int = 4096):
     m.update(dev["mean"], dev["factor"], dev["weight"], dev["colour"])
     idx = torch.from_numpy(np.sort(np.random.default_rng(inputs.SEED_QUERIES).choice(
         w.q, sample, replace=False))).to("cuda")
-    xs = dev["x"][idx].contiguous()
-    dense = ngd.eval_mixture(m, None, xs).double()
+    # the reference: the float64 oracle's full sum over all K at the sample
+    import oracle
+    t1 = time.perf_counter()
+    dense = torch.from_numpy(oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"],
+                                                 mix["colour"], x[idx.cpu().numpy()])).to("cuda")
+    log(f"sweep: oracle on {sample} queries in {time.perf_counter() - t1:.1f}s")
     s3 = math.exp(-4.5)
     grid = [(t, 256) for t in (1e-2, s3, 1e-3, 1e-4, 1e-5, 1e-6)] + \
            [(1e-4, t) for t in (64, 128, 512, 1024)]
@@ -267,7 +274,7 @@ def sweep_bench(reps: int = 5, sample: int = 4096):
         rows.append(row)
     print(json.dumps(dict(
         metric="cull thresholds on the 10-D workload: candidate fraction, cull and forward "
-               "time, error against the dense sum",
+               "time, error against the float64 oracle",
         unit="ms", n_gpus=1, data="synthetic", dtype="f32 / bf16+f32",
         config=dict(workload="10d-fwdbwd", n=w.n, k=w.k, q=w.q, n_proj=16,
                     error_sample=sample, reps=reps),
@@ -486,6 +493,131 @@ def run_workload(name: str, args, precisions, with_dense: bool, steps: int, warm
 OTHER_WORKLOADS = ("4d-dense", "6d-culled", "10d-4m")
 
 
+def image_bench(reps: int = 5, sample: int = 2048, width: int = 800, k: int = 262144):
+    """The cull on image-coherent queries (the paper's setting, Sec. 3.2): a
+    synthetic 10-D G-buffer of width x width pixels laid out in 16 x 16 pixel
+    tiles, a K-Gaussian mixture sitting on its features.  For each tiling
+    (the image's own 16 x 16 tiles, the k-d order, the Morton order) and
+    threshold (tau = 1e-4 and the paper's 3 sigma): the candidate fraction,
+    the cull build and both forwards (median of reps), and the normwise error
+    of the culled FP32 forward against the float64 oracle's full sum on a
+    seeded sample of pixels; the dense FP32 forward for the speedup.  Then
+    the global-conditioning case: with every input but the position constant
+    over the image, the mixture conditioned on those values (a 3-D mixture,
+    ngd_mixture_condition) against the 10-D path on the same pixels."""
+    import torch
+    import oracle
+    from paper_2405_20067_amd import inputs, ngd
+    n = 10
+    t0 = time.time()
+    x = inputs.gen_gbuffer(width, width)
+    mix = inputs.gen_mixture_on(x, k, (10.0, 200.0), 5.0, jitter=0.02, seed=inputs.SEED_MIXTURE)
+    proj = inputs.gen_projections(n, 16, inputs.SEED_PROJ)
+    q = x.shape[0]
+    log(f"image: {width}x{width} G-buffer, k={k}, generated in {time.time() - t0:.1f}s")
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
+    xd = d(x)
+    m = ngd.Mixture(n, k)
+    m.update(d(mix["mean"]), d(mix["factor"]), d(mix["weight"]), d(mix["colour"]))
+    m.validate()
+    rng = np.random.default_rng(inputs.SEED_QUERIES)
+    idx = np.sort(rng.choice(q, sample, replace=False))
+    t1 = time.perf_counter()
+    fo = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x[idx])
+    log(f"oracle on {sample} pixels: {time.perf_counter() - t1:.1f}s")
+
+    def med(fn):
+        out = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            torch.cuda.synchronize()
+            out.append(a.elapsed_time(b))
+        return float(np.median(out))
+
+    f = torch.empty((q, 3), device="cuda")
+    dense_ms = med(lambda: ngd.eval_mixture(m, None, xd, out=f))
+    s3 = math.exp(-4.5)
+    rows = []
+    for tiling, tau in ((2, 1e-4), (0, 1e-4), (1, 1e-4), (2, s3), (0, s3)):
+        p = ngd.default_params()
+        p.tiling, p.tau = tiling, tau
+        c = ngd.Cull().build(m, xd, proj, p)
+        fc = ngd.eval_mixture(m, c, xd)
+        torch.cuda.synchronize()
+        st = c.stats()
+        err = float(np.abs(fc[torch.from_numpy(idx).to("cuda")].double().cpu().numpy() - fo).max()
+                    / max(np.abs(fo).max(), 1e-300))
+        row = dict(tiling={0: "k-d", 1: "morton", 2: "image 16x16"}[tiling], tau=tau,
+                   candidates=st["total"], fraction=st["total"] / max(st["ntiles"] * k, 1),
+                   cull_ms=med(lambda: c.build(m, xd, proj, p)),
+                   fwd_fp32_ms=med(lambda: ngd.eval_mixture(m, c, xd, out=f)),
+                   fwd_bf16_ms=med(lambda: ngd.eval_mixture(m, c, xd, out=f,
+                                                            precision=ngd.BF16_MFMA)),
+                   err_fp32_vs_oracle=err)
+        row["speedup_fwd_vs_dense"] = dense_ms / (row["cull_ms"] + row["fwd_fp32_ms"])
+        log(f"image tiling={row['tiling']} tau={tau:.4g}: {row['fraction']:.4%} of pairs, cull "
+            f"{row['cull_ms']:.3f} ms, fwd {row['fwd_fp32_ms']:.3f} / {row['fwd_bf16_ms']:.3f} ms, "
+            f"err {err:.2e}")
+        rows.append(row)
+
+    # global conditioning: every input but the position constant over the image
+    xc = np.array([0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 0.5], np.float32)
+    xg = inputs.gen_gbuffer(width, width, constant_features=xc)
+    xgd = d(xg)
+    xg3 = d(np.ascontiguousarray(xg[:, :3]))
+    p10 = ngd.default_params()
+    p10.tiling = 2
+    c10 = ngd.Cull().build(m, xgd, proj, p10)
+    f10 = ngd.eval_mixture(m, c10, xgd)
+    proj3 = inputs.gen_projections(3, 16, inputs.SEED_PROJ)
+    c3 = ngd.Cull()
+    f3 = torch.empty((q, 3), device="cuda")
+    w_src = d(mix["weight"])
+    state = {}
+
+    def cond_path():
+        # the conditioned factor exp(-M_c/2) bounds every value of that
+        # Gaussian on the image, so the ones below tau are dropped (the
+        # threshold the 10-D cull applies per tile); the selection is done
+        # in torch (one device-to-host read of the count)
+        cm, cf, cw, cc = m.condition(3, xc)
+        keep = torch.nonzero(cw > p10.tau * w_src).flatten()
+        kk = int(keep.numel())
+        if state.get("k") != kk:
+            state["m3"], state["k"] = ngd.Mixture(3, kk), kk
+        m3 = state["m3"]
+        m3.update(cm[keep].contiguous(), cf[keep].contiguous(), cw[keep].contiguous(),
+                  cc[keep].contiguous())
+        c3.build(m3, xg3, proj3, p10)
+        ngd.eval_mixture(m3, c3, xg3, out=f3)
+
+    cond_path()
+    torch.cuda.synchronize()
+    state["m3"].validate()
+    scale = float(f10.abs().max())
+    diff = float((f10 - f3).abs().max()) / max(scale, 1e-300)
+    fog = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], xg[idx])
+    err3 = float(np.abs(f3[torch.from_numpy(idx).to("cuda")].double().cpu().numpy() - fog).max()
+                 / max(np.abs(fog).max(), 1e-300))
+    glob = dict(xc=xc.tolist(), ms_10d=med(lambda: (c10.build(m, xgd, proj, p10),
+                                                     ngd.eval_mixture(m, c10, xgd, out=f10))),
+                ms_conditioned_3d=med(cond_path), candidates_10d=c10.stats()["total"],
+                candidates_3d=c3.stats()["total"], k_conditioned_kept=state["k"],
+                max_rel_diff_3d_vs_10d=diff,
+                err_3d_vs_oracle=err3, value_scale=scale)
+    log(f"global conditioning: 10-D cull+fwd {glob['ms_10d']:.3f} ms, condition+3-D cull+fwd "
+        f"{glob['ms_conditioned_3d']:.3f} ms, rel diff {diff:.2e}, err vs oracle {err3:.2e}")
+    print(json.dumps(dict(
+        metric="cull on an image-coherent 10-D G-buffer: tilings and thresholds; global "
+               "conditioning", unit="ms", n_gpus=1, data="synthetic", dtype="f32 / bf16+f32",
+        config=dict(workload="10d-gbuffer", width=width, height=width, tile_pixels=16, n=n,
+                    k=k, q=q, n_proj=16, error_sample=sample, reps=reps),
+        dense_fp32_fwd_ms=dense_ms, rows=rows, global_conditioning=glob)), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -507,6 +639,10 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="instead of the step benchmark, sweep the cull threshold tau and "
                          "the tile size and print one line of rows")
+    ap.add_argument("--image", action="store_true",
+                    help="instead of the step benchmark, the cull on an image-coherent "
+                         "G-buffer (16 x 16 pixel tiles against the k-d and Morton orders) "
+                         "and the global-conditioning case; prints its own line")
     ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
                     help="instead of the step benchmark, run the 10-D fitting loop for "
                          "STEPS steps and print its own line (ms/step, losses, K)")
@@ -516,6 +652,8 @@ def main():
                     help="factor scale of the start relative to the target's in --fit")
     ap.add_argument("--fit-child-alpha", type=float, default=1e-4,
                     help="brightness of a new child in --fit")
+    ap.add_argument("--fit-child-jitter", type=float, default=1e-2,
+                    help="spread of a new child's relative parameters in --fit")
     ap.add_argument("--fit-checkpoint", default=None,
                     help="file the fit's final state is saved to (--fit)")
     args = ap.parse_args()
@@ -534,10 +672,14 @@ def main():
     if args.fit > 0:
         fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma",
                   lr_alpha=args.fit_lr_alpha, init_scale=args.fit_init_scale,
-                  child_alpha=args.fit_child_alpha, checkpoint=args.fit_checkpoint)
+                  child_alpha=args.fit_child_alpha, child_jitter=args.fit_child_jitter,
+                  checkpoint=args.fit_checkpoint)
         return
     if args.sweep:
         sweep_bench()
+        return
+    if args.image:
+        image_bench()
         return
     precisions = ["fp32", "bf16_mfma"] if args.precision == "both" else [args.precision]
     rec, (w, mix, x) = run_workload(args.workload, args, precisions, not args.no_dense,

@@ -86,7 +86,11 @@ typedef struct {
                           projection of largest extent, down to runs of `tile`;
                           Gaussians ordered the same way in runs of 64
                        1  Morton: stable sort on key_proj projections quantised
-                          to key_bits each, bits interleaved */
+                          to key_bits each, bits interleaved
+                       2  given order: tile t is queries [t*tile, (t+1)*tile)
+                          as the caller laid them out -- for queries of an
+                          image arranged tile by tile (the paper's 16 x 16
+                          pixel tiles, Sec. 3.2); Gaussians as with 0 */
 } ngd_cull_params;
 
 /* Message for the last failing call on this thread ("" if none). */
@@ -130,8 +134,36 @@ int ngd_mixture_update(ngd_mixture *mix, const float *mean, const float *factor,
                        const float *weight, const float *colour, void *stream);
 
 /* Synchronises; NGD_E_SINGULAR if the last update saw a zero or non-finite
- * factor diagonal or a non-finite parameter. */
+ * factor diagonal or a non-finite parameter; NGD_E_INVAL if the last
+ * composed update saw a parent index outside [0, kp) or out of order. */
 int ngd_mixture_validate(const ngd_mixture *mix, void *stream);
+
+/* Parent-child composition of the refinement (Sec. 3.3, Eq. 6-7) done by the
+ * library: Gaussians 0 .. kp-1 are parents, given absolutely; Gaussians
+ * kp + j (j < kc = k - kp) are children, each given in its parent's frame by
+ * a lower-triangular factor U_j and an offset m_u,j:
+ *   L = L_parent[j] U_j,   m = L_parent[j] m_u,j + m_parent[j].
+ *   mean       device kp x n        (parents)
+ *   factor     device kp x n(n+1)/2 (parents, packed like ngd_mixture_update)
+ *   weight     device k             (parents, then children)
+ *   colour     device k x 3         (parents, then children)
+ *   parent     device kc int32, non-decreasing, each in [0, kp)
+ *   rel_factor device kc x n(n+1)/2 (U, packed the same way)
+ *   rel_mean   device kc x n        (m_u)
+ * The children's factor and mean are formed in float64 (exact products of
+ * the float32 inputs, sums in ascending order) and rounded to float32; from
+ * there every Gaussian is prepared as by ngd_mixture_update and the cull and
+ * evaluation see no difference between parents and children.  The relative
+ * parameters are copied (the backward uses the copies).  A parent index
+ * outside [0, kp) or smaller than its predecessor's is reported by
+ * ngd_mixture_validate (NGD_E_INVAL); that child is then a unit Gaussian
+ * at the origin (finite, so nothing downstream faults).  kp outside [0, k], kc > 0 with kp = 0, NULL or misaligned arrays:
+ * NGD_E_INVAL before any device work.  Bumps the version.  Does not
+ * synchronise. */
+int ngd_mixture_update_composed(ngd_mixture *mix, int64_t kp, const float *mean,
+                                const float *factor, const float *weight, const float *colour,
+                                const int32_t *parent, const float *rel_factor,
+                                const float *rel_mean, void *stream);
 
 /* Number of dimensions / Gaussians / current version. */
 int ngd_mixture_info(const ngd_mixture *mix, int *n, int64_t *k, int64_t *version);
@@ -239,6 +271,49 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull,
                       const float *queries, int64_t q, const float *grad_out,
                       int precision, float *g_mean, float *g_factor, float *g_weight,
                       float *g_colour, void *stream);
+
+/* Conditions every Gaussian on fixed values of its trailing dimensions (the
+ * paper's global conditioning, Sec. 3.2: with every input but the position
+ * constant over an image, the N-D Gaussians are conditioned on them and
+ * then culled and evaluated as p-D ones).  With V = L L^T split into the
+ * kept dimensions 0..p-1 and the fixed ones p..n-1 (textbook Schur
+ * complement):
+ *   mean'   = m_p + V_pc V_cc^-1 (x_c - m_c)
+ *   factor' = Cholesky factor (positive diagonal) of V_pp - V_pc V_cc^-1 V_cp
+ *   weight' = alpha exp(-(x_c - m_c)^T V_cc^-1 (x_c - m_c) / 2),  colour' = c
+ * so that the p-D mixture of these parameters takes, at every x_p, the value
+ * of the N-D mixture at (x_p, x_c).  Float64 arithmetic, one thread per
+ * Gaussian, from the parameters of the last update.
+ *   p          kept dimensions, 1 .. n-1
+ *   xc         HOST, n - p finite values of dimensions p .. n-1 (copied)
+ *   outputs    device: mean_out k x p, factor_out k x p(p+1)/2 (packed like
+ *              ngd_mixture_update), weight_out k, colour_out k x 3 --
+ *              the arguments of ngd_mixture_update for a p-D mixture.
+ * A conditional covariance that is not positive in float64 gets a zero
+ * diagonal, which that update reports through ngd_mixture_validate.
+ * Invalid p, NULL / non-finite xc, NULL or misaligned outputs: NGD_E_INVAL;
+ * no update yet: NGD_E_STALE.  Does not synchronise. */
+int ngd_mixture_condition(const ngd_mixture *mix, int p, const float *xc, float *mean_out,
+                          float *factor_out, float *weight_out, float *colour_out, void *stream);
+
+/* ngd_eval_backward for a mixture whose last update was
+ * ngd_mixture_update_composed (else NGD_E_INVAL), with the gradients carried
+ * through the composition (Sec. 3.3, Eq. 6-7) by the chain rule of the
+ * product, for every child j of parent p:
+ *   dU_j = tril(L_p^T dL_c),   dm_u,j = L_p^T dm_c,
+ *   dL_p += tril(dL_c U_j^T + dm_c m_u,j^T),   dm_p += dm_c,
+ * where dL_c, dm_c are the gradients with respect to the child's absolute
+ * factor and mean.  Outputs (device, overwritten): g_mean kp x n and
+ * g_factor kp x n(n+1)/2 (the parents' own terms plus their children's, the
+ * children summed in index order), g_weight k and g_colour k x 3 (every
+ * Gaussian), g_rel_factor kc x n(n+1)/2 and g_rel_mean kc x n.  Float64
+ * chain arithmetic, no atomics: bitwise reproducible.  Other arguments and
+ * errors as ngd_eval_backward.  Does not synchronise. */
+int ngd_eval_backward_composed(const ngd_mixture *mix, const ngd_cull *cull,
+                               const float *queries, int64_t q, const float *grad_out,
+                               int precision, float *g_mean, float *g_factor, float *g_weight,
+                               float *g_colour, float *g_rel_factor, float *g_rel_mean,
+                               void *stream);
 
 /* Mean squared error and its gradient, the loss of the 10-D fitting
  * workload (Sec. 4.1 fits colours with an L2-type loss):

@@ -1,7 +1,9 @@
 """CPU oracle for the N-D Gaussian mixture hot path -- TEST INFRASTRUCTURE.
 
 Plain float64 C code (ngd_oracle.c: the direct sum and its gradient) and a
-CPU re-implementation of the tile cull (ngd_cull_ref.c), loaded with ctypes.
+CPU re-implementation of the tile cull (ngd_cull_ref.c), loaded with ctypes;
+in numpy float64, the parent-child composition of Sec. 3.3 (Eq. 6-7) with
+its chain rule, and the conditioning of Sec. 3.2 by the textbook formulas.
 Only the tests, the smoke check and the benchmark's CPU-baseline leg may
 import this package; the product path shares no code with it.
 
@@ -240,7 +242,7 @@ def kappa2_from_tau(tau: float) -> np.float32:
 
 def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=2, tiling=0):
     """CPU re-implementation of the tile cull (tiling 0: k-d order, 1: Morton
-    key).  Returns a dict of arrays:
+    key, 2: the queries' given order).  Returns a dict of arrays:
     perm, gperm, tile_off, cand, g_off, g_tiles, tile_lo, tile_hi, g_mr,
     g_thr, qkey, gkey, qlo, qhi (see ngd_cull_ref.c)."""
     mean = np.ascontiguousarray(mean, dtype=np.float32)
@@ -294,3 +296,74 @@ def cull(mean, factor, queries, proj, tau=1e-4, tile=256, key_proj=16, key_bits=
     out["tile"] = tile
     out["kappa2"] = kappa2_from_tau(tau)
     return out
+
+
+def _unpack(packed, n):
+    r, c = np.tril_indices(n)
+    full = np.zeros(packed.shape[:-1] + (n, n))
+    full[..., r, c] = packed
+    return full
+
+
+def compose(mean_p, factor_p, parent, rel_factor, rel_mean):
+    """Absolute (mean, factor) of parents then children in float64, from the
+    children's parameters relative to their parents (Sec. 3.3, Eq. 6-7):
+    L_c = L_p U, m_c = L_p m_u + m_p.  Factors packed lower by rows."""
+    mean_p, factor_p = _d(mean_p), _d(factor_p)
+    n = mean_p.shape[1]
+    parent = np.asarray(parent, np.int64)
+    lp = _unpack(factor_p[parent], n)
+    u = _unpack(_d(rel_factor), n)
+    lc = lp @ u
+    mc = np.einsum("kij,kj->ki", lp, _d(rel_mean)) + mean_p[parent]
+    r, c = np.tril_indices(n)
+    return (np.concatenate([mean_p, mc]), np.concatenate([factor_p, lc[:, r, c]]))
+
+
+def compose_grad(factor_p, parent, rel_factor, rel_mean, g_mean, g_factor):
+    """Gradients with respect to (mean_p, factor_p, rel_factor, rel_mean) from
+    those with respect to every Gaussian's absolute (mean, factor), parents
+    then children (the derivative of the products of Eq. 6-7, restricted to
+    the lower triangles)."""
+    factor_p = _d(factor_p)
+    kp = factor_p.shape[0]
+    g_mean, g_factor = _d(g_mean), _d(g_factor)
+    n = g_mean.shape[1]
+    parent = np.asarray(parent, np.int64)
+    lp = _unpack(factor_p[parent], n)
+    u = _unpack(_d(rel_factor), n)
+    mu = _d(rel_mean)
+    gl = _unpack(g_factor[kp:], n)
+    gm = g_mean[kp:]
+    r, c = np.tril_indices(n)
+    g_u = np.transpose(lp, (0, 2, 1)) @ gl
+    g_mu = np.einsum("kji,kj->ki", lp, gm)
+    g_lp = gl @ np.transpose(u, (0, 2, 1)) + gm[:, :, None] * mu[:, None, :]
+    out_m = g_mean[:kp].copy()
+    out_l = g_factor[:kp].copy()
+    np.add.at(out_m, parent, gm)
+    np.add.at(out_l, parent, g_lp[:, r, c])
+    return out_m, out_l, g_u[:, r, c], g_mu
+
+
+def condition(mean, factor, weight, colour, p, xc):
+    """Every Gaussian conditioned on the values xc of its dimensions p..n-1
+    (the paper's global conditioning, Sec. 3.2), by the textbook formulas in
+    float64 with explicit inverses:
+        mean'   = m_p + V_pc V_cc^-1 (x_c - m_c)
+        cov'    = V_pp - V_pc V_cc^-1 V_cp,  factor' its Cholesky factor
+        weight' = alpha exp(-(x_c - m_c)^T V_cc^-1 (x_c - m_c) / 2)
+    with V = L L^T.  Returns (mean', factor' packed, weight', colour)."""
+    n, k, mean, factor, weight, colour = _check_mix(mean, factor, weight, colour)
+    L = _unpack(factor, n)
+    V = L @ np.transpose(L, (0, 2, 1))
+    xc = np.asarray(xc, np.float64).ravel()
+    d = xc[None, :] - mean[:, p:]
+    icc = np.linalg.inv(V[:, p:, p:])
+    vpc = V[:, :p, p:]
+    mu = mean[:, :p] + np.einsum("kij,kjl,kl->ki", vpc, icc, d)
+    cov = V[:, :p, :p] - vpc @ icc @ np.transpose(vpc, (0, 2, 1))
+    mc = np.einsum("ki,kij,kj->k", d, icc, d)
+    r, c = np.tril_indices(p)
+    fac = np.linalg.cholesky(cov)[:, r, c]
+    return mu, fac, weight * np.exp(-0.5 * mc), colour.copy()

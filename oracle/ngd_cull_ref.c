@@ -33,7 +33,10 @@
  *       queries in a tile are then compact too);
  *     tiling 1 (Morton): a stable sort (ties by original index) on key_proj
  *       projections quantised to key_bits each over the queries' range, bits
- *       interleaved most-significant first.
+ *       interleaved most-significant first;
+ *     tiling 2 (given order): the queries keep the caller's order, for
+ *       queries that come with an image laid out tile by tile (the paper's
+ *       16 x 16 pixel tiles); the Gaussians are ordered as with tiling 0.
  *     Tile t = ordered queries [t*tile, (t+1)*tile).
  *   - Gaussians are ordered the same way by their projected means (k-d runs
  *     of 64; or the Morton key clamped to the queries' range).  Candidate
@@ -207,7 +210,7 @@ cull_ref *ngd_cull_ref_run(int n, int64_t k, const float *mean, const float *fac
 {
     if (n < 1 || n > CULL_MAX_N || n_proj < 1 || n_proj > CULL_MAX_PROJ || tile < 1 ||
         key_proj < 0 || key_proj > n_proj || key_bits < 0 || key_proj * key_bits > 32 ||
-        k < 0 || q < 0 || tiling < 0 || tiling > 1)
+        k < 0 || q < 0 || tiling < 0 || tiling > 2)
         return NULL;
     const int64_t tri = (int64_t)n * (n + 1) / 2;
     cull_ref *c = (cull_ref *)calloc(1, sizeof(cull_ref));
@@ -272,16 +275,20 @@ cull_ref *ngd_cull_ref_run(int n, int64_t k, const float *mean, const float *fac
         c->gkey[i] = morton_key(c->g_mr + i * n_proj, c->qlo, scale, key_proj, key_bits);
     c->perm = (int32_t *)malloc(sizeof(int32_t) * qq);
     c->gperm = (int32_t *)malloc(sizeof(int32_t) * kk);
-    if (tiling == 0) {
-        /* k-d order of the query projections (leaves = tiles) and of the
-         * projected means (leaves of 64 Gaussians) */
+    if (tiling == 0 || tiling == 2) {
+        /* k-d order of the query projections (leaves = tiles; tiling 2: the
+         * queries keep their given order) and of the projected means (leaves
+         * of 64 Gaussians) */
         float *qr_soa = (float *)malloc(sizeof(float) * qq * n_proj);
         for (int64_t p = 0; p < q; ++p)
             for (int j = 0; j < n_proj; ++j) qr_soa[(int64_t)j * q + p] = q_r[p * n_proj + j];
         float *mr_soa = (float *)malloc(sizeof(float) * kk * n_proj);
         for (int64_t i = 0; i < k; ++i)
             for (int j = 0; j < n_proj; ++j) mr_soa[(int64_t)j * k + i] = c->g_mr[i * n_proj + j];
-        kd_order(n_proj, q, qr_soa, tile, tile < 64 ? tile : 64, c->perm);
+        if (tiling == 0)
+            kd_order(n_proj, q, qr_soa, tile, tile < 64 ? tile : 64, c->perm);
+        else
+            for (int64_t p = 0; p < q; ++p) c->perm[p] = (int32_t)p;
         kd_order(n_proj, k, mr_soa, 64, 64, c->gperm);
         free(qr_soa);
         free(mr_soa);

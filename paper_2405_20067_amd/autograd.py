@@ -26,7 +26,7 @@ import torch
 from . import ngd
 
 __all__ = ["diag_mask", "activate_factor", "raw_factor", "activate", "Evaluator",
-           "NgdMixtureEval", "NgdL2Loss", "mixture_eval", "GaussianMixture"]
+           "NgdMixtureEval", "NgdComposedEval", "NgdL2Loss", "mixture_eval", "GaussianMixture"]
 
 
 def diag_mask(n: int, device=None) -> torch.Tensor:
@@ -123,6 +123,44 @@ class NgdMixtureEval(torch.autograd.Function):
         gm, gf, gw, gc = ngd.eval_backward(mix, ev.cull, x, _f32(grad_f),
                                            precision=ev.precision)
         return gm, gf, gw, gc, None, None
+
+
+class NgdComposedEval(torch.autograd.Function):
+    """f(x) like NgdMixtureEval for a mixture of kp parents and kc children
+    given relative to their parents (Sec. 3.3, Eq. 6-7), composed inside the
+    library (ngd_mixture_update_composed; backward
+    ngd_eval_backward_composed): mean (kp, n) and factor (kp, n(n+1)/2) of
+    the parents, weight (k,) and colour (k, 3) of all, parent (kc,) int32
+    non-decreasing, rel_factor U (kc, n(n+1)/2), rel_mean m_u (kc, n).
+    Gradients flow to every float argument."""
+
+    @staticmethod
+    def forward(ctx, mean, factor, weight, colour, parent, rel_factor, rel_mean, queries,
+                ev: Evaluator):
+        k = weight.shape[0]
+        mix = ev.mixture(k)
+        x = _f32(queries)
+        mix.update_composed(mean.shape[0], _f32(mean), _f32(factor), _f32(weight), _f32(colour),
+                            parent.detach().to(torch.int32).contiguous(), _f32(rel_factor),
+                            _f32(rel_mean))
+        if ev.cull is not None:
+            ev.cull.build(mix, x, ev.proj, ev.params)
+        f = ngd.eval_mixture(mix, ev.cull, x, precision=ev.precision)
+        ctx.ev, ctx.mix, ctx.version = ev, mix, mix.info()[2]
+        ctx.save_for_backward(x)
+        return f
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, grad_f):
+        (x,) = ctx.saved_tensors
+        ev, mix = ctx.ev, ctx.mix
+        if ev.mix is not mix or mix.info()[2] != ctx.version:
+            raise RuntimeError("NgdComposedEval: the Evaluator was used for another forward "
+                               "before this backward; use one Evaluator per live graph")
+        gm, gf, gw, gc, gu, gmu = ngd.eval_backward_composed(mix, ev.cull, x, _f32(grad_f),
+                                                            precision=ev.precision)
+        return gm, gf, gw, gc, None, gu, gmu, None, None
 
 
 class NgdL2Loss(torch.autograd.Function):

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libngd.so")
 SOURCES = ["capi.hip", "prepare.hip", "cull.hip", "kd.hip", "sort.hip", "eval.hip",
-           "eval_mfma.hip", "backward.hip", "scan.hip"]
+           "eval_mfma.hip", "backward.hip", "scan.hip", "compose.hip",
+           "condition.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -226,6 +226,7 @@ int ngd_mixture_update(ngd_mixture *mix, const float *mean, const float *factor,
                                   mix->rec.as<float>(), mix->lfac.as<float>(),
                                   mix->flag.as<int>(), S(stream));
     if (e != hipSuccess) return hip_fail(e, "ngd_mixture_update");
+    mix->kp = -1;
     ++mix->version;
     return NGD_OK;
 }
@@ -238,10 +239,68 @@ int ngd_mixture_validate(const ngd_mixture *mix, void *stream)
                                   S(stream));
     if (e == hipSuccess) e = hipStreamSynchronize(S(stream));
     if (e != hipSuccess) return hip_fail(e, "ngd_mixture_validate");
+    if (flag & 2)
+        return fail(NGD_E_INVAL,
+                    "ngd_mixture_validate: a parent index is outside [0, kp) or smaller than "
+                    "the one before it");
     if (flag)
         return fail(NGD_E_SINGULAR,
                     "ngd_mixture_validate: a factor has a zero or non-finite diagonal entry, "
                     "or a parameter is not finite");
+    return NGD_OK;
+}
+
+int ngd_mixture_update_composed(ngd_mixture *mix, int64_t kp, const float *mean,
+                                const float *factor, const float *weight, const float *colour,
+                                const int32_t *parent, const float *rel_factor,
+                                const float *rel_mean, void *stream)
+{
+    const char *who = "ngd_mixture_update_composed";
+    if (!mix) return fail(NGD_E_INVAL, "%s: mixture is NULL", who);
+    const int64_t k = mix->k;
+    if (kp < 0 || kp > k)
+        return fail(NGD_E_INVAL, "%s: kp=%lld outside [0, k=%lld]", who, (long long)kp,
+                    (long long)k);
+    const int64_t kc = k - kp;
+    if (kc > 0 && kp == 0) return fail(NGD_E_INVAL, "%s: children without parents", who);
+    if ((kp > 0 && (!mean || !factor)) || (k > 0 && (!weight || !colour)) ||
+        (kc > 0 && (!parent || !rel_factor || !rel_mean)))
+        return fail(NGD_E_INVAL, "%s: NULL parameter array", who);
+    if (!aligned4(mean) || !aligned4(factor) || !aligned4(weight) || !aligned4(colour) ||
+        !aligned4(parent) || !aligned4(rel_factor) || !aligned4(rel_mean))
+        return fail(NGD_E_INVAL, "%s: arrays must be 4-byte aligned", who);
+    const int n = mix->n, t = tri(n);
+    const size_t kk = size_t(k > 0 ? k : 1), cc = size_t(kc > 0 ? kc : 1);
+    if (!mix->abs_mean.ensure(sizeof(float) * kk * n) ||
+        !mix->abs_factor.ensure(sizeof(float) * kk * t) ||
+        !mix->comp_parent.ensure(sizeof(int32_t) * cc) ||
+        !mix->comp_u.ensure(sizeof(float) * cc * t) || !mix->comp_mu.ensure(sizeof(float) * cc * n))
+        return fail(NGD_E_NOMEM, "%s: device allocation failed", who);
+    hipError_t e = hipSuccess;
+    // the backward applies the chain rule with the same relative parameters
+    if (kc > 0) {
+        e = hipMemcpyAsync(mix->comp_parent.p, parent, sizeof(int32_t) * kc,
+                           hipMemcpyDeviceToDevice, S(stream));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(mix->comp_u.p, rel_factor, sizeof(float) * kc * t,
+                               hipMemcpyDeviceToDevice, S(stream));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(mix->comp_mu.p, rel_mean, sizeof(float) * kc * n,
+                               hipMemcpyDeviceToDevice, S(stream));
+    }
+    if (e == hipSuccess) e = launch_clear_flag(mix->flag.as<int>(), S(stream));
+    if (e == hipSuccess)
+        e = launch_compose(n, k, kp, mean, factor, mix->comp_parent.as<int32_t>(),
+                           mix->comp_u.as<float>(), mix->comp_mu.as<float>(),
+                           mix->abs_mean.as<float>(), mix->abs_factor.as<float>(),
+                           mix->flag.as<int>(), S(stream));
+    if (e == hipSuccess)
+        e = launch_prepare(n, k, mix->abs_mean.as<float>(), mix->abs_factor.as<float>(), weight,
+                           colour, mix->rec.as<float>(), mix->lfac.as<float>(),
+                           mix->flag.as<int>(), S(stream), false);
+    if (e != hipSuccess) return hip_fail(e, who);
+    mix->kp = kp;
+    ++mix->version;
     return NGD_OK;
 }
 
@@ -258,9 +317,10 @@ int ngd_mixture_destroy(ngd_mixture *mix)
 {
     if (!mix) return NGD_OK;
     (void)hipDeviceSynchronize();
-    mix->rec.release();
-    mix->lfac.release();
-    mix->flag.release();
+    DevBuf *bufs[] = {&mix->rec,    &mix->lfac,       &mix->flag,  &mix->comp_parent,
+                      &mix->comp_u, &mix->comp_mu,    &mix->abs_mean, &mix->abs_factor,
+                      &mix->g_abs,  &mix->contrib};
+    for (DevBuf *b : bufs) b->release();
     delete mix;
     return NGD_OK;
 }
@@ -320,8 +380,9 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
         p->key_proj * p->key_bits > 32 || (p->key_proj > 0 && p->key_bits > 16))
         return fail(NGD_E_INVAL, "ngd_cull_build: key_proj=%d key_bits=%d invalid", p->key_proj,
                     p->key_bits);
-    if (p->tiling != 0 && p->tiling != 1)
-        return fail(NGD_E_INVAL, "ngd_cull_build: tiling=%d (0: k-d, 1: Morton)", p->tiling);
+    if (p->tiling < 0 || p->tiling > 2)
+        return fail(NGD_E_INVAL, "ngd_cull_build: tiling=%d (0: k-d, 1: Morton, 2: given order)",
+                    p->tiling);
     for (int i = 0; i < p->n_proj * mix->n; ++i)
         if (!std::isfinite(proj[i]))
             return fail(NGD_E_INVAL, "ngd_cull_build: projection vectors must be finite");
@@ -626,6 +687,66 @@ int ngd_eval_backward(const ngd_mixture *mix, const ngd_cull *cull, const float 
         e = launch_backward_dense(mix, queries, q, grad_out, g_mean, g_factor, g_weight, g_colour,
                                   S(stream));
     if (e != hipSuccess) return hip_fail(e, "ngd_eval_backward");
+    return NGD_OK;
+}
+
+int ngd_mixture_condition(const ngd_mixture *mix, int p, const float *xc, float *mean_out,
+                          float *factor_out, float *weight_out, float *colour_out, void *stream)
+{
+    const char *who = "ngd_mixture_condition";
+    if (!mix) return fail(NGD_E_INVAL, "%s: mixture is NULL", who);
+    if (p < 1 || p >= mix->n)
+        return fail(NGD_E_INVAL, "%s: p=%d outside [1, n-1=%d]", who, p, mix->n - 1);
+    if (!xc) return fail(NGD_E_INVAL, "%s: xc is NULL", who);
+    for (int j = 0; j < mix->n - p; ++j)
+        if (!std::isfinite(xc[j])) return fail(NGD_E_INVAL, "%s: xc[%d] is not finite", who, j);
+    if (mix->k > 0 && (!mean_out || !factor_out || !weight_out || !colour_out))
+        return fail(NGD_E_INVAL, "%s: NULL output array", who);
+    if (!aligned4(mean_out) || !aligned4(factor_out) || !aligned4(weight_out) ||
+        !aligned4(colour_out))
+        return fail(NGD_E_INVAL, "%s: arrays must be 4-byte aligned", who);
+    if (mix->version == 0) return fail(NGD_E_STALE, "%s: mixture has no parameters yet", who);
+    const hipError_t e =
+        launch_condition(mix, p, xc, mean_out, factor_out, weight_out, colour_out, S(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
+    return NGD_OK;
+}
+
+int ngd_eval_backward_composed(const ngd_mixture *mix, const ngd_cull *cull,
+                               const float *queries, int64_t q, const float *grad_out,
+                               int precision, float *g_mean, float *g_factor, float *g_weight,
+                               float *g_colour, float *g_rel_factor, float *g_rel_mean,
+                               void *stream)
+{
+    const char *who = "ngd_eval_backward_composed";
+    if (!mix) return fail(NGD_E_INVAL, "%s: mixture is NULL", who);
+    if (mix->kp < 0)
+        return fail(NGD_E_INVAL, "%s: the mixture's last update was not composed", who);
+    const int64_t kp = mix->kp, kc = mix->k - mix->kp;
+    if ((kp > 0 && (!g_mean || !g_factor)) || (kc > 0 && (!g_rel_factor || !g_rel_mean)))
+        return fail(NGD_E_INVAL, "%s: NULL output array", who);
+    if (!aligned4(g_mean) || !aligned4(g_factor) || !aligned4(g_rel_factor) ||
+        !aligned4(g_rel_mean))
+        return fail(NGD_E_INVAL, "%s: arrays must be 4-byte aligned", who);
+    const int n = mix->n, t = tri(n);
+    ngd_mixture *mm = const_cast<ngd_mixture *>(mix);
+    const size_t kk = size_t(mix->k > 0 ? mix->k : 1), cc = size_t(kc > 0 ? kc : 1);
+    if (!mm->g_abs.ensure(sizeof(float) * kk * (n + t)) ||
+        !mm->contrib.ensure(sizeof(float) * cc * (n + t)))
+        return fail(NGD_E_NOMEM, "%s: device allocation failed", who);
+    float *gm_abs = mm->g_abs.as<float>();
+    float *gl_abs = gm_abs + size_t(mix->k) * n;
+    // gradients with respect to every Gaussian's absolute parameters (the
+    // brightness and colour ones are the result already)
+    const int rc = ngd_eval_backward(mix, cull, queries, q, grad_out, precision, gm_abs, gl_abs,
+                                     g_weight, g_colour, stream);
+    if (rc) return rc;
+    if (mix->k == 0) return NGD_OK;
+    const hipError_t e = launch_compose_backward(
+        n, kp, kc, mix->comp_parent.as<int32_t>(), mix->lfac.as<float>(),
+        mix->comp_u.as<float>(), mix->comp_mu.as<float>(), gm_abs, gl_abs, g_mean, g_factor,
+        g_rel_factor, g_rel_mean, mm->contrib.as<float>(), S(stream));
+    if (e != hipSuccess) return hip_fail(e, who);
     return NGD_OK;
 }
 

@@ -736,7 +736,7 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     // Gaussians) they go there too, after the fork, so that the queries'
     // projections start at once.
     bool forked = false;
-    if (c->params.tiling == 0 && k > kWave) {
+    if (c->params.tiling != 1 && k > kWave) {
         if ((e = hipEventRecord(c->ev_fork, s)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(c->side, c->ev_fork, 0)) != hipSuccess) return e;
         forked = true;
@@ -784,10 +784,10 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     // ordered means read them without a gather
     const float *qr_s = nullptr;
     bool g_sorted = false, gauss_done = false;
-    if (c->params.tiling == 0) {
+    if (c->params.tiling != 1) {
         // k-d order of the query projections (runs of `tile`, and of 64
-        // inside those) and of the projected means (runs of 64, the chunks
-        // of the interval test).  The two are independent: the Gaussians'
+        // inside those; tiling 2: the caller's order, no reordering) and of
+        // the projected means (runs of 64, the chunks of the interval test).  The two are independent: the Gaussians'
         // order runs on the second stream, forked before their projections
         // and joined before anything reads it.  Both are enqueued a phase (a
         // level) at a time, alternately, so that each stream has work while
@@ -801,7 +801,7 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
             k_iota<<<nblk(k, kThreads), kThreads, 0, s>>>(c->gperm.as<int32_t>(), k);
         }
         if (e == hipSuccess && q > 0) {
-            if (q <= std::min(c->params.tile, kWave)) {
+            if (c->params.tiling == 2 || q <= std::min(c->params.tile, kWave)) {
                 k_iota<<<nblk(q, kThreads), kThreads, 0, s>>>(c->perm.as<int32_t>(), q);
             } else {
                 e = kd_start(rq, c->kd_q, c->kd_work, P, c->qr.as<float>(), q,
@@ -1131,10 +1131,14 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->gitem_off.ensure(sizeof(int64_t) * (kk + 1));
     ok &= c->scan_tmp.ensure(scan_tmp_bytes(scan_n));
     ok &= c->stats.ensure(sizeof(int64_t) * 2);
-    if (c->params.tiling == 0) {
-        ok &= kd_plan(c->kd_q, q, c->params.tile, std::min(c->params.tile, kWave)) &&
-              kd_plan(c->kd_g, k, kWave, kWave);
-        ok = ok && kd_reserve(c->kd_work, c->kd_q, q, P) && kd_reserve(c->kd_work_g, c->kd_g, k, P);
+    if (c->params.tiling != 1) {
+        // the queries' k-d plan only with the k-d tiling (tiling 2 keeps the
+        // caller's order); the Gaussians' with both
+        if (c->params.tiling == 0)
+            ok &= kd_plan(c->kd_q, q, c->params.tile, std::min(c->params.tile, kWave)) &&
+                  kd_reserve(c->kd_work, c->kd_q, q, P);
+        ok &= kd_plan(c->kd_g, k, kWave, kWave);
+        ok = ok && kd_reserve(c->kd_work_g, c->kd_g, k, P);
         if (ok && !c->side) ok = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
         if (ok && !c->ev_fork)
             ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;

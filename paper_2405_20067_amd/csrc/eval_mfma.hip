@@ -214,7 +214,9 @@ __global__ __launch_bounds__(256) void k_mfma_entry(int64_t total,
     constexpr int kSt = NV | 1;
     __shared__ float4 s_rec[256 / kWave][kWave * kSt];
     const int w = int(threadIdx.x) / kWave, lane = lane_id();
-    const int64_t ew = int64_t(blockIdx.x) * 256 + w * kWave;   // the wave's first entry
+    // consecutive blocks (neighbouring tiles' entries, which share
+    // Gaussians) on one XCD, so that they share its L2
+    const int64_t ew = xcd_block(blockIdx.x, gridDim.x) * 256 + w * kWave;   // the wave's first entry
     if (ew >= total) return;                                    // uniform over the wave
     const int nw = int(total - ew < kWave ? total - ew : kWave);
     const int64_t e = ew + lane;
@@ -317,7 +319,8 @@ __global__ __launch_bounds__(kMThreads, 3) void k_mfma_filter(
 
     // one workgroup per tile (and part of a tile of more than 256 queries):
     // the query features are formed once for all of the tile's candidates
-    const int64_t t = blockIdx.x;
+    // neighbouring tiles, which share candidates, on one XCD (one L2)
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x);
     const int64_t e0 = uniform64(tile_off[t]), e1 = uniform64(tile_off[t + 1]);
 
     const int lane = lane_id(), w = int(threadIdx.x) / kWave, h = lane / 32;

@@ -113,7 +113,14 @@ struct ngd_mixture {
     int device = 0;
     ngd::DevBuf rec;     // k x rec_stride(n) float
     ngd::DevBuf lfac;    // k x tri(n) float: copy of L for the cull
-    ngd::DevBuf flag;    // int: nonzero if the last update saw a bad factor
+    ngd::DevBuf flag;    // int: bit 1 a bad factor or parameter, bit 2 a bad parent index
+    // parent-child composition (ngd_mixture_update_composed): kp parents,
+    // then k - kp children; kp < 0 when the last update was a plain one
+    int64_t kp = -1;
+    ngd::DevBuf comp_parent, comp_u, comp_mu;   // copies: kc int32, kc x tri, kc x n
+    ngd::DevBuf abs_mean, abs_factor;           // k x n, k x tri: absolute parameters
+    ngd::DevBuf g_abs;                          // k x (n + tri): backward scratch
+    ngd::DevBuf contrib;                        // kc x (n + tri): children's shares
 };
 
 struct ngd_cull {
@@ -205,9 +212,28 @@ struct ngd_cull {
 namespace ngd {
 
 // ---- launchers (each returns the hipError_t of its launches) ----------
+// clear_flag: the mixture's flag is cleared first (false: a composition
+// kernel ahead of it has already cleared it and may have set bit 2).
 hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *factor,
                           const float *weight, const float *colour, float *rec,
-                          float *lfac, int *flag, hipStream_t s);
+                          float *lfac, int *flag, hipStream_t s, bool clear_flag = true);
+hipError_t launch_clear_flag(int *flag, hipStream_t s);
+// compose.hip: absolute parameters of parents and children (Eq. 6-7), and
+// the chain rule of the composition in the backward.
+hipError_t launch_compose(int n, int64_t k, int64_t kp, const float *mean, const float *factor,
+                          const int32_t *parent, const float *rel_factor, const float *rel_mean,
+                          float *abs_mean, float *abs_factor, int *flag, hipStream_t s);
+// condition.hip: every Gaussian conditioned on x_c (host, n - p values) of
+// its trailing dimensions; p-dimensional outputs.
+hipError_t launch_condition(const ngd_mixture *mix, int p, const float *xc, float *mean_out,
+                            float *factor_out, float *weight_out, float *colour_out,
+                            hipStream_t s);
+hipError_t launch_compose_backward(int n, int64_t kp, int64_t kc, const int32_t *parent,
+                                   const float *factor_p, const float *rel_factor,
+                                   const float *rel_mean, const float *g_abs_mean,
+                                   const float *g_abs_factor, float *g_mean, float *g_factor,
+                                   float *g_rel_factor, float *g_rel_mean, float *contrib,
+                                   hipStream_t s);
 
 hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix,
                                    const float *queries, hipStream_t s);

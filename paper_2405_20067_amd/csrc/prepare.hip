@@ -86,12 +86,17 @@ hipError_t prepare_n(int64_t k, const float *mean, const float *factor, const fl
 
 }  // namespace
 
-hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *factor,
-                          const float *weight, const float *colour, float *rec, float *lfac,
-                          int *flag, hipStream_t s)
+hipError_t launch_clear_flag(int *flag, hipStream_t s)
 {
     k_clear_flag<<<1, 1, 0, s>>>(flag);
-    hipError_t e = hipGetLastError();
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *factor,
+                          const float *weight, const float *colour, float *rec, float *lfac,
+                          int *flag, hipStream_t s, bool clear_flag)
+{
+    hipError_t e = clear_flag ? launch_clear_flag(flag, s) : hipSuccess;
     if (e != hipSuccess || k == 0) return e;
     switch (n) {
 #define NGD_CASE(NN) \

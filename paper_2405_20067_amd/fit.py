@@ -2,7 +2,9 @@
 
 Each step is one differentiable evaluation through the torch.autograd layer
 (`NgdMixtureEval`: ngd_mixture_update, ngd_cull_build, ngd_eval; its
-backward ngd_eval_backward), the library's loss (`NgdL2Loss`), and an Adam
+backward ngd_eval_backward; with children, by default `NgdComposedEval`,
+which has the library compose them: ngd_mixture_update_composed and
+ngd_eval_backward_composed), the library's loss (`NgdL2Loss`), and an Adam
 step on raw parameters.  The activations are torch ops, so autograd chains
 the library's gradients through them:
 
@@ -38,7 +40,8 @@ import math
 import torch
 
 from . import ngd
-from .autograd import Evaluator, NgdL2Loss, NgdMixtureEval, activate_factor, raw_factor
+from .autograd import (Evaluator, NgdComposedEval, NgdL2Loss, NgdMixtureEval, activate_factor,
+                       raw_factor)
 
 __all__ = ["compose_child", "pack", "unpack", "absolute_params", "Fit"]
 
@@ -99,13 +102,17 @@ class Fit:
 
     def __init__(self, mean, factor, weight, colour, *, lr=1e-3, lr_alpha=None,
                  threshold=0.01, phase=300, max_k=524288, child_alpha=1e-4, child_jitter=1e-2,
-                 loss="l2", eps=0.01, precision=ngd.FP32, cull_params=None, seed=0):
+                 loss="l2", eps=0.01, precision=ngd.FP32, cull_params=None, seed=0,
+                 compose="kernel"):
         dev = mean.device
         self.n = mean.shape[1]
         self.lr, self.threshold, self.phase = lr, threshold, phase
         self.lr_alpha = lr if lr_alpha is None else lr_alpha
         self.max_k, self.child_alpha, self.child_jitter = max_k, child_alpha, child_jitter
         self.loss_kind, self.eps, self.precision = loss, eps, precision
+        if compose not in ("kernel", "torch"):
+            raise ValueError(f"compose must be 'kernel' or 'torch', got {compose!r}")
+        self.compose = compose
         self.params = cull_params if cull_params is not None else ngd.default_params()
         self.gen = torch.Generator(device=dev)
         self.gen.manual_seed(seed)
@@ -163,11 +170,26 @@ class Fit:
         return absolute_params(self.n, self.mean, self.factor, self.a, self.c, self.child)
 
     # -- one step --------------------------------------------------------
+    def _forward(self, queries):
+        """The mixture's values at the queries, in the graph: with children
+        and compose="kernel" the library composes them (NgdComposedEval),
+        otherwise torch does (absolute parameters into NgdMixtureEval)."""
+        if self.child is None or self.compose == "torch":
+            return NgdMixtureEval.apply(*self.absolute(), queries, self.ev)
+        u, m_u, a_c, c_c = self.child
+        kp = self.mean.shape[0]
+        parent = torch.arange(kp, dtype=torch.int32, device=self.mean.device)
+        weight = torch.cat([torch.exp(self.a), torch.exp(a_c)])
+        colour = torch.cat([torch.sigmoid(self.c), torch.sigmoid(c_c)])
+        return NgdComposedEval.apply(self.mean, activate_factor(self.factor, self.n), weight,
+                                     colour, parent, activate_factor(u, self.n), m_u, queries,
+                                     self.ev)
+
     def evaluate(self, queries, proj):
         """The current mixture's values at the queries (no gradient)."""
         self.ev.proj = proj
         with torch.no_grad():
-            return NgdMixtureEval.apply(*self.absolute(), queries, self.ev)
+            return self._forward(queries)
 
     def step(self, queries, target, proj):
         """One Adam step on the loss of the mixture against target at the
@@ -175,7 +197,7 @@ class Fit:
         phase end the loss is read back (one synchronisation per phase) and
         a non-finite loss raises."""
         self.ev.proj = proj
-        f = NgdMixtureEval.apply(*self.absolute(), queries, self.ev)
+        f = self._forward(queries)
         loss = NgdL2Loss.apply(f, target, self.eps if self.loss_kind == "rel" else 0.0)
         self.opt.zero_grad(set_to_none=True)
         loss.backward()

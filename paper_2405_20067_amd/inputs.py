@@ -39,6 +39,8 @@ __all__ = [
     "gen_workload_queries",
     "gen_grad_out",
     "gen_projections",
+    "gen_gbuffer",
+    "gen_mixture_on",
     "SEED_MIXTURE",
     "SEED_QUERIES",
     "SEED_PROJ",
@@ -218,3 +220,87 @@ def workload_mixture(w: Workload, k: int | None = None,
                      seed: int = SEED_MIXTURE) -> dict:
     return gen_mixture(w.n, w.k if k is None else k, w.layout, w.s_diag,
                        w.s_off_sd, seed)
+
+
+def gen_gbuffer(width: int = 800, height: int = 800, tile: int = 16,
+                constant_features=None) -> np.ndarray:
+    """A synthetic 10-D G-buffer (position 3, normal 3, view direction 3,
+    roughness 1), the kind of per-pixel input the paper's global
+    illumination scenes evaluate its Gaussians at; float32, (height*width,
+    10), laid out tile by tile (tiles of tile x tile pixels in row-major
+    order of tiles, row-major pixels inside a tile), so that the cull's
+    given-order tiling (tiling 2) forms the paper's 16 x 16 pixel tiles.
+
+    The scene (no randomness): a pinhole camera at (0.5, 0.5, 1.8) looking
+    down -z through the open front of the unit box [0, 1]^3, whose inside
+    walls (floor, ceiling, back and side walls) and a sphere of radius 0.22
+    at (0.5, 0.25, 0.45) are the visible surfaces.  Normal: the surface
+    normal facing the camera; view: the unit vector from the point to the
+    camera; roughness 0.2 + 0.6 (0.5 + 0.5 sin(7x) cos(5z + 3y)), a smooth
+    texture.  With `constant_features` (7 values: normal, view, roughness),
+    every pixel keeps its position and takes those (the case of Sec. 3.2
+    where every input but the position is constant over the image)."""
+    if width % tile or height % tile:
+        raise ValueError("width and height must be multiples of the tile size")
+    cam = np.array([0.5, 0.5, 1.8])
+    v, u = np.meshgrid((np.arange(height) + 0.5) / height, (np.arange(width) + 0.5) / width,
+                       indexing="ij")
+    # image plane z = 1 (the box's open face), inside [0.02, 0.98]^2, so that
+    # every ray enters the box and meets an inside wall or the sphere
+    tgt = np.stack([0.02 + 0.96 * u, 0.98 - 0.96 * v, np.ones_like(u)], -1)
+    d = tgt - cam
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    t_best = np.full(u.shape, np.inf)
+    nrm = np.zeros(u.shape + (3,))
+    # inside walls: planes x=0, x=1, y=0, y=1, z=0 with inward normals
+    for axis, val, sgn in ((0, 0.0, 1.0), (0, 1.0, -1.0), (1, 0.0, 1.0), (1, 1.0, -1.0),
+                           (2, 0.0, 1.0)):
+        with np.errstate(divide="ignore", invalid="ignore"):
+            t = (val - cam[axis]) / d[..., axis]
+        pt = cam + t[..., None] * d
+        inside = np.all((pt >= -1e-9) & (pt <= 1 + 1e-9), axis=-1) & (t > 0)
+        hit = inside & (t < t_best)
+        t_best = np.where(hit, t, t_best)
+        nv = np.zeros(3)
+        nv[axis] = sgn
+        nrm = np.where(hit[..., None], nv, nrm)
+    # the sphere
+    cen, rad = np.array([0.5, 0.25, 0.45]), 0.22
+    oc = cam - cen
+    b = np.einsum("...i,i->...", d, oc)
+    disc = b * b - (oc @ oc - rad * rad)
+    ts = -b - np.sqrt(np.maximum(disc, 0.0))
+    hit = (disc > 0) & (ts > 0) & (ts < t_best)
+    t_best = np.where(hit, ts, t_best)
+    pts = cam + t_best[..., None] * d
+    sn = (pts - cen) / rad
+    nrm = np.where(hit[..., None], sn, nrm)
+    assert np.isfinite(t_best).all()
+    pos = pts
+    view = cam - pos
+    view /= np.linalg.norm(view, axis=-1, keepdims=True)
+    rough = 0.2 + 0.6 * (0.5 + 0.5 * np.sin(7 * pos[..., 0]) * np.cos(5 * pos[..., 2] +
+                                                                      3 * pos[..., 1]))
+    feat = np.concatenate([pos, nrm, view, rough[..., None]], -1)
+    if constant_features is not None:
+        cst = np.asarray(constant_features, np.float64).ravel()
+        assert cst.size == 7
+        feat[..., 3:] = cst
+    # tile-major layout
+    th, tw = height // tile, width // tile
+    feat = feat.reshape(th, tile, tw, tile, 10).transpose(0, 2, 1, 3, 4).reshape(-1, 10)
+    return np.ascontiguousarray(feat, dtype=np.float32)
+
+
+def gen_mixture_on(points: np.ndarray, k: int, s_diag=(10.0, 200.0), s_off_sd: float = 5.0,
+                   jitter: float = 0.02, seed: int = SEED_MIXTURE) -> dict:
+    """A mixture sitting on given data, as a fitted one does: the means are
+    k of the points (seeded choice) moved by N(0, jitter^2) per coordinate;
+    factors, brightness and colours as gen_mixture draws them."""
+    n = points.shape[1]
+    mix = gen_mixture(n, k, "cube", s_diag, s_off_sd, seed=seed)
+    rng = np.random.Generator(np.random.PCG64(seed + 17))
+    j = rng.integers(0, points.shape[0], size=k)
+    mean = points[j].astype(np.float64) + jitter * rng.standard_normal((k, n))
+    mix["mean"] = np.ascontiguousarray(mean, dtype=np.float32)
+    return mix

@@ -15,7 +15,8 @@ import numpy as np
 
 __all__ = [
     "NgdError", "CullParams", "Mixture", "Cull", "lib", "LIB_PATH",
-    "eval_mixture", "eval_prepare", "eval_backward", "eval_stats", "l2_loss", "l2_loss_noalloc",
+    "eval_mixture", "eval_prepare", "eval_backward", "eval_backward_composed", "eval_stats",
+    "l2_loss", "l2_loss_noalloc",
     "rel_l2_loss", "FP32", "BF16_MFMA",
     "E_INVAL", "E_SINGULAR", "E_HIP", "E_NOMEM", "E_STALE",
 ]
@@ -57,6 +58,8 @@ _SIGS = [
     ("ngd_mixture_update", ctypes.c_int,
      [ctypes.c_void_p] * 5 + [ctypes.c_void_p]),
     ("ngd_mixture_validate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    ("ngd_mixture_update_composed", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 8),
     ("ngd_mixture_info", ctypes.c_int,
      [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int64),
       ctypes.POINTER(ctypes.c_int64)]),
@@ -80,6 +83,11 @@ _SIGS = [
     ("ngd_eval_backward", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
       ctypes.c_int] + [ctypes.c_void_p] * 5),
+    ("ngd_mixture_condition", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_float)] + [ctypes.c_void_p] * 5),
+    ("ngd_eval_backward_composed", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+      ctypes.c_int] + [ctypes.c_void_p] * 7),
     ("ngd_l2_loss", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_void_p]),
@@ -152,6 +160,7 @@ class Mixture:
         self._h = h
         self.n, self.k = int(n), int(k)
         self.tri = self.n * (self.n + 1) // 2
+        self.kp = -1   # parents of the last composed update (-1: plain update)
 
     @property
     def handle(self):
@@ -163,6 +172,39 @@ class Mixture:
                                         _ptr(factor, "factor", k * t),
                                         _ptr(weight, "weight", k),
                                         _ptr(colour, "colour", k * 3), _stream(stream)))
+        self.kp = -1
+
+    def update_composed(self, kp, mean, factor, weight, colour, parent, rel_factor, rel_mean,
+                        stream=None):
+        """Parents 0..kp-1 given absolutely, children kp.. given relative to
+        their parents (include/ngd.h, ngd_mixture_update_composed)."""
+        import torch
+        k, n, t = self.k, self.n, self.tri
+        kc = k - int(kp)
+        _check(lib().ngd_mixture_update_composed(
+            self._h, int(kp), _ptr(mean, "mean", kp * n), _ptr(factor, "factor", kp * t),
+            _ptr(weight, "weight", k), _ptr(colour, "colour", k * 3),
+            _ptr(parent, "parent", kc, torch.int32), _ptr(rel_factor, "rel_factor", kc * t),
+            _ptr(rel_mean, "rel_mean", kc * n), _stream(stream)))
+        self.kp = int(kp)
+
+    def condition(self, p, xc, stream=None):
+        """(mean (k, p), factor (k, p(p+1)/2), weight (k,), colour (k, 3)):
+        every Gaussian conditioned on the values xc of dimensions p..n-1
+        (include/ngd.h, ngd_mixture_condition); the arguments of
+        Mixture(p, k).update."""
+        import torch
+        xc = np.ascontiguousarray(np.asarray(xc, dtype=np.float32).ravel())
+        if xc.size != self.n - int(p):
+            raise ValueError(f"xc needs {self.n - int(p)} values, got {xc.size}")
+        p = int(p)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        e = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+        out = (e(self.k, p), e(self.k, p * (p + 1) // 2), e(self.k), e(self.k, 3))
+        _check(lib().ngd_mixture_condition(
+            self._h, p, xc.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+            *[ctypes.c_void_p(t.data_ptr()) for t in out], _stream(stream)))
+        return out
 
     def validate(self, stream=None):
         _check(lib().ngd_mixture_validate(self._h, _stream(stream)))
@@ -308,6 +350,25 @@ def eval_backward(mix: Mixture, cull: Cull | None, queries, grad_out, grads=None
                                    _ptr(gw, "g_weight", mix.k),
                                    _ptr(gc, "g_colour", mix.k * 3), _stream(stream)))
     return grads
+
+
+def eval_backward_composed(mix: Mixture, cull: Cull | None, queries, grad_out, precision=FP32,
+                           stream=None):
+    """(g_mean (kp, n), g_factor (kp, tri), g_weight (k,), g_colour (k, 3),
+    g_rel_factor (kc, tri), g_rel_mean (kc, n)) of a composed mixture."""
+    import torch
+    q = queries.numel() // mix.n
+    dev = queries.device
+    # after a plain update (kp < 0) the library refuses the call itself
+    kp = max(mix.kp, 0)
+    kc = mix.k - kp if mix.kp >= 0 else 0
+    e = lambda *s: torch.empty(s, dtype=torch.float32, device=dev)
+    out = (e(kp, mix.n), e(kp, mix.tri), e(mix.k), e(mix.k, 3), e(kc, mix.tri), e(kc, mix.n))
+    _check(lib().ngd_eval_backward_composed(
+        mix.handle, cull.handle if cull is not None else None,
+        _ptr(queries, "queries", q * mix.n), q, _ptr(grad_out, "grad_out", q * 3),
+        int(precision), *[ctypes.c_void_p(t.data_ptr()) for t in out], _stream(stream)))
+    return out
 
 
 def rel_l2_loss(f, target, eps=0.01, loss=None, grad=None, stream=None):

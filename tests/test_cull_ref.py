@@ -189,6 +189,36 @@ def test_tiling_structure():
     assert c["g_off"][-1] == c["total"]
 
 
+def test_given_order_tiling():
+    """tiling 2: the queries keep their order (tile t = queries [t*tile,
+    (t+1)*tile)), the Gaussians take the k-d order of tiling 0, and each
+    tile's list is exactly the Gaussians whose interval meets the tile's box
+    on every projection (float64 recompute away from the boundary)."""
+    mix, x, proj = _setup(n=6, k=300, q=2000, layout="pos3+dir3", sdiag=(10, 200), soff=5.0)
+    tile = 100
+    c2 = oracle.cull(mix["mean"], mix["factor"], x, proj, tile=tile, tiling=2)
+    c0 = oracle.cull(mix["mean"], mix["factor"], x, proj, tile=tile, tiling=0)
+    np.testing.assert_array_equal(c2["perm"], np.arange(x.shape[0]))
+    np.testing.assert_array_equal(c2["gperm"], c0["gperm"])
+    qr = x.astype(np.float64) @ proj.astype(np.float64).T
+    for t in range(c2["ntiles"]):
+        sel = np.arange(t * tile, min((t + 1) * tile, x.shape[0]))
+        assert np.all(c2["tile_lo"][t] <= qr[sel].min(0) + 1e-6)
+        assert np.all(c2["tile_hi"][t] >= qr[sel].max(0) - 1e-6)
+    # the same pair set as a plain interval test on the given tiles
+    thr = c2["g_thr"].astype(np.float64)
+    mr = c2["g_mr"].astype(np.float64)
+    for t in range(c2["ntiles"]):
+        lo, hi = c2["tile_lo"][t].astype(np.float64), c2["tile_hi"][t].astype(np.float64)
+        d = np.maximum(np.maximum(lo[None] - mr, mr - hi[None]), 0.0)
+        margin = np.abs(d * d - thr) > 1e-5 * np.maximum(thr, 1e-30)
+        keep = np.all(d * d <= thr, axis=1)
+        sure = np.all(margin, axis=1)
+        got = np.zeros(300, bool)
+        got[c2["gperm"][c2["cand"][c2["tile_off"][t]:c2["tile_off"][t + 1]]]] = True
+        np.testing.assert_array_equal(got[sure], keep[sure])
+
+
 def test_mean_inside_tile_box_is_never_culled():
     """A Gaussian centred on a query projects inside that query's tile
     interval on every r, so dist = 0 and it is kept however narrow it is."""

@@ -65,6 +65,9 @@ CULL_CASES = [
     # other culling thresholds: 3 sigma (kappa^2 = 9) and a tight one
     dict(n=6, k=2000, q=9000, tile=256, tau=0.011108996538242306),
     dict(n=10, k=1500, q=4100, tile=64, tau=1e-6),
+    # queries in their given order (tiles laid out by the caller)
+    dict(n=10, k=1500, q=4100, tile=256, tiling=2),
+    dict(n=3, k=500, q=1000, tile=100, tiling=2),
 ]
 
 

@@ -108,22 +108,24 @@ def test_fit_gradients_match_the_oracle_chain(torch_cuda):
     and children) against the float64 chain: the oracle's value and gradient
     over the same candidate pairs with respect to the absolute parameters,
     carried through the activations (Sec. 3.1, 4.1) and the composition
-    (Eq. 6-7) by float64 autograd on the CPU.  Bar 1e-4 normwise."""
+    (Eq. 6-7) by float64 autograd on the CPU.  Bar 1e-4 normwise.  With the
+    composition done by the library (NgdComposedEval) and by torch."""
     torch = torch_cuda
     import oracle
     from gpu_helpers import normwise, per_gaussian_csr, per_query_csr
     from paper_2405_20067_amd import ngd
-    from paper_2405_20067_amd.autograd import NgdL2Loss, NgdMixtureEval
+    from paper_2405_20067_amd.autograd import NgdL2Loss
     from paper_2405_20067_amd.fit import absolute_params
-    for n, prec in ((4, ngd.FP32), (10, ngd.BF16_MFMA)):
-        print(f"[fit chain] n={n} precision={prec}", flush=True)
+    for n, prec, compose in ((4, ngd.FP32, "kernel"), (10, ngd.BF16_MFMA, "kernel"),
+                             (10, ngd.FP32, "torch")):
+        print(f"[fit chain] n={n} precision={prec} compose={compose}", flush=True)
         xd, target, proj, init = _problem(torch, n=n, k=64, q=16384)
-        fit = _fit(torch, init, child_jitter=0.3, precision=prec)
+        fit = _fit(torch, init, child_jitter=0.3, precision=prec, compose=compose)
         fit.add_children()
         with torch.no_grad():        # children bright enough to matter
             fit.child[2].copy_(torch.log(torch.full_like(fit.child[2], 0.05)))
         fit.ev.proj = proj
-        f = NgdMixtureEval.apply(*fit.absolute(), xd, fit.ev)
+        f = fit._forward(xd)
         loss = NgdL2Loss.apply(f, target, 0.0)
         fit.opt.zero_grad(set_to_none=True)
         loss.backward()
