@@ -148,7 +148,7 @@ def cpu_baseline(w, mix, x, budget_s: float, threads: int = 0):
 def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-3,
               lr_alpha: float = 3e-2, init_scale: float = 0.7, per_component: int = 8,
               child_alpha: float = 1e-4, child_jitter: float = 1e-2,
-              checkpoint: str | None = None):
+              checkpoint: str | None = None, target_kind: str = "coarse"):
     """The 10-D fitting loop (Adam, children from the second phase,
     materialised above t = 0.01): K starts at 32,768 Gaussians and may grow
     to 524,288; 2^21 queries near the hidden K=4,096 target mixture and
@@ -159,7 +159,10 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
     under-covers it and children have room to grow), brightness
     1/per_component, colours random.  Every step is timed; set-up (query
     pool, targets, handles) is not.  `checkpoint`: the fit's state is saved
-    there at the end."""
+    there at the end.  target_kind "detail": the hidden target is the
+    K=4,096 mixture with each component replaced by 16 narrower ones
+    (K_t = 65,536, inputs.gen_detailed_mixture) while the start stays on the
+    coarse components, so that the fit has to add Gaussians to reach it."""
     import torch
     from paper_2405_20067_amd import inputs, ngd
     from paper_2405_20067_amd.fit import Fit
@@ -178,11 +181,12 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
                factor=init_scale * tgt["factor"][src], weight=tgt["weight"][src] / rep,
                colour=rng.uniform(0.05, 0.95, (k0, 3)))
     mix = {a: np.ascontiguousarray(v, np.float32) for a, v in mix.items()}
-    x = inputs.gen_workload_queries(w, q=q, mixtures=[tgt])
+    hidden = inputs.gen_detailed_mixture(tgt) if target_kind == "detail" else tgt
+    x = inputs.gen_workload_queries(w, q=q, mixtures=[hidden])
     proj = inputs.gen_projections(w.n, 16, inputs.SEED_PROJ)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
     dev = dict(x=d(x))
-    target = targets(w, tgt, dev, proj)
+    target = targets(w, hidden, dev, proj)
     prec = ngd.BF16_MFMA if precision_name == "bf16_mfma" else ngd.FP32
     fit = Fit(d(mix["mean"]), d(mix["factor"]), d(mix["weight"]), d(mix["colour"]), lr=lr,
               lr_alpha=lr_alpha, phase=phase, max_k=max_k, precision=prec,
@@ -212,7 +216,7 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
                     precision=precision_name,
                     init=f"{rep} per target component, factors x{init_scale}",
                     child_alpha=child_alpha, child_jitter=child_jitter,
-                    k_target=w.k_target),
+                    target=target_kind, k_target=int(hidden["mean"].shape[0])),
         initial_loss=losses[0][1], final_loss=losses[-1][1], loss_trajectory=losses,
         k_trajectory=ks)), flush=True)
 
@@ -618,6 +622,125 @@ def image_bench(reps: int = 5, sample: int = 2048, width: int = 800, k: int = 26
         dense_fp32_fwd_ms=dense_ms, rows=rows, global_conditioning=glob)), flush=True)
 
 
+def _median_by_kernel(csv_path, counter=None):
+    """Per kernel name: (dispatches, median value) of a rocprofv3 CSV -- the
+    counter column of a --pmc run, or the duration of a --kernel-trace run."""
+    import csv
+    vals = {}
+    for r in csv.DictReader(open(csv_path)):
+        name = r["Kernel_Name"]
+        if counter is not None:
+            if r["Counter_Name"] != counter:
+                continue
+            v = float(r["Counter_Value"])
+        else:
+            v = float(r["End_Timestamp"]) - float(r["Start_Timestamp"])
+        vals.setdefault(name, []).append(v)
+    return {k: (len(v), float(np.median(v))) for k, v in vals.items()}
+
+
+def _short(name):
+    """A kernel's name without namespace and argument list (mangled names
+    demangled with c++filt)."""
+    if name.startswith("_Z"):
+        import re
+        import subprocess
+        try:
+            out = subprocess.run(["c++filt", name], capture_output=True, text=True,
+                                 check=True).stdout.strip()
+        except (OSError, subprocess.CalledProcessError):
+            out = name
+        if out.startswith("_Z"):
+            # names c++filt leaves mangled (bf16 vector arguments): the
+            # kernel's name and its int / bool template arguments
+            m = re.search(r"\d+(k_[A-Za-z0-9_]+?)I((?:L[ib]\d+E)+)E", name)
+            if not m:
+                return name
+            args = re.findall(r"L([ib])(\d+)E", m.group(2))
+            txt = [v if t == "i" else ("true" if v == "1" else "false") for t, v in args]
+            return f"{m.group(1)}<{', '.join(txt)}>"
+        name = out
+    base = name.replace("void ", "", 1) if name.startswith("void ") else name
+    base = base.replace("ngd::(anonymous namespace)::", "")
+    depth = 0
+    for i, ch in enumerate(base):
+        depth += ch == "<"
+        depth -= ch == ">"
+        if ch == "(" and depth == 0:
+            return base[:i]
+    return base
+
+
+def summarize_traffic(fetch_csv, write_csv, out_prefix):
+    """HBM bytes per launch of each path's forward from two rocprofv3 --pmc
+    runs of `bench.py --profile` (FETCH_SIZE, then WRITE_SIZE; KiB per
+    dispatch), each scaled by what the counter reads for the run's closing
+    device copy of 268,435,456 bytes.  Writes the JSON files the bench reads
+    (with the forward sources' hash) and prints a markdown table."""
+    fe = {(_short(k)): v for k, v in _median_by_kernel(fetch_csv, "FETCH_SIZE").items()}
+    wr = {(_short(k)): v for k, v in _median_by_kernel(write_csv, "WRITE_SIZE").items()}
+    copy = "__amd_rocclr_copyBuffer"
+    # the calibration copy is the largest copy dispatch of the run
+    import csv
+    cf = max(float(r["Counter_Value"]) for r in csv.DictReader(open(fetch_csv))
+             if r["Kernel_Name"].startswith(copy) and r["Counter_Name"] == "FETCH_SIZE")
+    cw = max(float(r["Counter_Value"]) for r in csv.DictReader(open(write_csv))
+             if r["Kernel_Name"].startswith(copy) and r["Counter_Name"] == "WRITE_SIZE")
+    nbytes = 268435456
+    ffac, wfac = nbytes / 1024 / cf, nbytes / 1024 / cw
+    paths = dict(fp32=(["k_eval_items<10, true, false>", "k_eval_reduce"], (KERNEL_SRC,)),
+                 bf16_mfma=(["k_mfma_filter<10, true, false>"], (MFMA_SRC, KERNEL_SRC)))
+    lines = ["| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB |", "|---|---|---|---|"]
+    for k in sorted(fe, key=lambda k: -fe[k][1]):
+        if k in wr and fe[k][1] + wr[k][1] > 1024:
+            lines.append(f"| `{k}` | {fe[k][0]} | {fe[k][1]:.0f} | {wr[k][1]:.0f} |")
+    for name, (kerns, srcs) in paths.items():
+        if not all(k in fe and k in wr for k in kerns):
+            continue
+        f_kib = sum(fe[k][1] for k in kerns)
+        w_kib = sum(wr[k][1] for k in kerns)
+        rec = dict(workload="10d-fwdbwd", path=name, kernels=kerns,
+                   source_sha256_16=source_hash(*srcs),
+                   sources=[os.path.relpath(x, ROOT) for x in srcs],
+                   fetch_kib_per_launch_raw=f_kib, write_kib_per_launch_raw=w_kib,
+                   copy_calibration=dict(bytes=nbytes, fetch_kib=cf, write_kib=cw,
+                                         fetch_factor=ffac, write_factor=wfac),
+                   hbm_bytes_per_launch=(f_kib * ffac + w_kib * wfac) * 1024)
+        json.dump(rec, open(TRAFFIC_FILES[name], "w"), indent=1)
+        lines.append(f"\n{name}: {rec['hbm_bytes_per_launch'] / 1e9:.3f} GB per forward "
+                     f"(calibrated), source hash {rec['source_sha256_16']}")
+    lines.append(f"\ncalibration copy of {nbytes} bytes: FETCH_SIZE {cf:.0f} KiB "
+                 f"(factor {ffac:.3f}), WRITE_SIZE {cw:.0f} KiB (factor {wfac:.3f})")
+    print("\n".join(lines))
+
+
+def summarize_trace(stats_csv, top=40):
+    """A markdown table of a rocprofv3 --kernel-trace --stats summary."""
+    import csv
+    rows = list(csv.DictReader(open(stats_csv)))
+    print("| kernel | calls | avg us | total ms | % |\n|---|---|---|---|---|")
+    for r in rows[:top]:
+        print(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
+              f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+
+
+def summarize_counters(pmc_csv, kernel):
+    """Median per dispatch of every counter a --pmc run collected for one
+    kernel, and the matrix-core utilisation they give."""
+    import csv
+    vals = {}
+    for r in csv.DictReader(open(pmc_csv)):
+        if _short(r["Kernel_Name"]) == kernel:
+            vals.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    med = {k: float(np.median(v)) for k, v in vals.items()}
+    for k, v in sorted(med.items()):
+        print(f"| {k} | {v:.4g} |")
+    if "SQ_VALU_MFMA_BUSY_CYCLES" in med and "GRBM_GUI_ACTIVE" in med:
+        # GRBM_GUI_ACTIVE summed over the 8 XCDs; 1,024 SIMDs
+        util = med["SQ_VALU_MFMA_BUSY_CYCLES"] / (med["GRBM_GUI_ACTIVE"] / 8 * 1024)
+        print(f"\nMFMA busy: {util:.3f} of the SIMD cycles the kernel spans")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -643,9 +766,18 @@ def main():
                     help="instead of the step benchmark, the cull on an image-coherent "
                          "G-buffer (16 x 16 pixel tiles against the k-d and Morton orders) "
                          "and the global-conditioning case; prints its own line")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="turn two rocprofv3 --pmc counter CSVs of `--profile` runs into the "
+                         "traffic files under profiles/ and print a table; no GPU")
+    ap.add_argument("--summarize-trace", metavar="KERNEL_STATS_CSV",
+                    help="print a rocprofv3 --kernel-trace --stats summary as a table; no GPU")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("PMC_CSV", "KERNEL"),
+                    help="print one kernel's counters from a rocprofv3 --pmc CSV; no GPU")
     ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
                     help="instead of the step benchmark, run the 10-D fitting loop for "
                          "STEPS steps and print its own line (ms/step, losses, K)")
+    ap.add_argument("--fit-lr", type=float, default=1e-3,
+                    help="Adam learning rate of the means, factors and colours in --fit")
     ap.add_argument("--fit-lr-alpha", type=float, default=3e-2,
                     help="Adam learning rate of the log-brightnesses in --fit")
     ap.add_argument("--fit-init-scale", type=float, default=0.7,
@@ -654,9 +786,21 @@ def main():
                     help="brightness of a new child in --fit")
     ap.add_argument("--fit-child-jitter", type=float, default=1e-2,
                     help="spread of a new child's relative parameters in --fit")
+    ap.add_argument("--fit-target", default="coarse", choices=["coarse", "detail"],
+                    help="hidden target of --fit: the K=4,096 mixture, or the same with "
+                         "16 narrower components in place of each (K=65,536)")
     ap.add_argument("--fit-checkpoint", default=None,
                     help="file the fit's final state is saved to (--fit)")
     args = ap.parse_args()
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, None)
+        return
+    if args.summarize_trace:
+        summarize_trace(args.summarize_trace)
+        return
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.profile:
         args.steps, args.warmup = 3, 1
         args.no_cpu_baseline = args.no_dense = args.no_configs = True
@@ -671,9 +815,9 @@ def main():
     ngd.lib()
     if args.fit > 0:
         fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma",
-                  lr_alpha=args.fit_lr_alpha, init_scale=args.fit_init_scale,
+                  lr=args.fit_lr, lr_alpha=args.fit_lr_alpha, init_scale=args.fit_init_scale,
                   child_alpha=args.fit_child_alpha, child_jitter=args.fit_child_jitter,
-                  checkpoint=args.fit_checkpoint)
+                  checkpoint=args.fit_checkpoint, target_kind=args.fit_target)
         return
     if args.sweep:
         sweep_bench()

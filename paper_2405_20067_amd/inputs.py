@@ -41,6 +41,7 @@ __all__ = [
     "gen_projections",
     "gen_gbuffer",
     "gen_mixture_on",
+    "gen_detailed_mixture",
     "SEED_MIXTURE",
     "SEED_QUERIES",
     "SEED_PROJ",
@@ -304,3 +305,24 @@ def gen_mixture_on(points: np.ndarray, k: int, s_diag=(10.0, 200.0), s_off_sd: f
     mean = points[j].astype(np.float64) + jitter * rng.standard_normal((k, n))
     mix["mean"] = np.ascontiguousarray(mean, dtype=np.float32)
     return mix
+
+
+def gen_detailed_mixture(coarse: dict, sub: int = 16, spread: float = 1.0,
+                         narrow: float = 0.35, seed: int = SEED_TARGET + 1) -> dict:
+    """A mixture with detail inside a coarse one: every coarse component j
+    is replaced by `sub` narrower components, means m_j + spread L_j z
+    (z ~ N(0, I)), factors narrow * L_j, brightness alpha_j * 4 / sub and
+    colours c_j moved by N(0, 0.2^2) (clipped to [0, 1]).  A fit that starts
+    from the coarse components has to add Gaussians to reach this one."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    k, n = coarse["mean"].shape
+    src = np.repeat(np.arange(k), sub)
+    r_all, c_all = np.tril_indices(n)
+    lf = np.zeros((k * sub, n, n))
+    lf[:, r_all, c_all] = coarse["factor"][src]
+    z = rng.standard_normal((k * sub, n))
+    mean = coarse["mean"][src] + spread * np.einsum("kij,kj->ki", lf, z)
+    colour = np.clip(coarse["colour"][src] + 0.2 * rng.standard_normal((k * sub, 3)), 0, 1)
+    f32 = lambda a: np.ascontiguousarray(a, dtype=np.float32)
+    return dict(mean=f32(mean), factor=f32(narrow * coarse["factor"][src]),
+                weight=f32(coarse["weight"][src] * 4.0 / sub), colour=f32(colour))
