@@ -146,23 +146,28 @@ def cpu_baseline(w, mix, x, budget_s: float, threads: int = 0):
 
 
 def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-3,
-              lr_alpha: float = 3e-2, init_scale: float = 0.7, per_component: int = 8,
-              child_alpha: float = 1e-4, child_jitter: float = 1e-2,
-              checkpoint: str | None = None, target_kind: str = "coarse"):
+              lr_alpha: float = 3e-2, lr_child: float | None = None, init_scale: float = 0.7,
+              per_component: float = 8, child_alpha: float = 1e-4, child_jitter: float = 1e-2,
+              checkpoint: str | None = None, target_kind: str = "coarse",
+              detail_sub: int = 16, detail_narrow: float = 0.35, adam_eps: float = 1e-15):
     """The 10-D fitting loop (Adam, children from the second phase,
     materialised above t = 0.01): K starts at 32,768 Gaussians and may grow
     to 524,288; 2^21 queries near the hidden K=4,096 target mixture and
     uniform, their target values computed once.  The start stands in for an
     initialisation from the data: `per_component` Gaussians per target
-    component, means drawn from that component, factors scaled by
+    component (below 1: one Gaussian on each of that fraction of the
+    components, a seeded subset), means drawn from that component (with
+    one per component: its mean), factors scaled by
     `init_scale` (below 1: narrower than the target, so the start
     under-covers it and children have room to grow), brightness
     1/per_component, colours random.  Every step is timed; set-up (query
     pool, targets, handles) is not.  `checkpoint`: the fit's state is saved
     there at the end.  target_kind "detail": the hidden target is the
     K=4,096 mixture with each component replaced by 16 narrower ones
-    (K_t = 65,536, inputs.gen_detailed_mixture) while the start stays on the
-    coarse components, so that the fit has to add Gaussians to reach it."""
+    (`detail_sub` components of factors `detail_narrow` times the coarse
+    one's: K_t = 65,536 by default, inputs.gen_detailed_mixture) while the
+    start stays on the coarse components, so that the fit has to add
+    Gaussians to reach it."""
     import torch
     from paper_2405_20067_amd import inputs, ngd
     from paper_2405_20067_amd.fit import Fit
@@ -170,18 +175,24 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
     k0, q, max_k = 32768, 1 << 21, 524288
     tgt = inputs.workload_mixture(w, k=w.k_target, seed=inputs.SEED_TARGET)
     rng = np.random.default_rng(inputs.SEED_MIXTURE)
-    rep = per_component
-    k0 = rep * w.k_target
-    src = np.repeat(np.arange(w.k_target), rep)
+    if per_component >= 1:
+        rep = int(per_component)
+        src = np.repeat(np.arange(w.k_target), rep)
+    else:
+        rep = 1
+        src = np.sort(rng.choice(w.k_target, max(1, round(per_component * w.k_target)),
+                                 replace=False))
+    k0 = src.size
     lfull = np.zeros((k0, w.n, w.n))
     r, c = np.tril_indices(w.n)
     lfull[:, r, c] = tgt["factor"][src]
-    z = rng.standard_normal((k0, w.n))
+    z = rng.standard_normal((k0, w.n)) if rep > 1 else np.zeros((k0, w.n))
     mix = dict(mean=tgt["mean"][src] + np.einsum("kij,kj->ki", lfull, z),
                factor=init_scale * tgt["factor"][src], weight=tgt["weight"][src] / rep,
                colour=rng.uniform(0.05, 0.95, (k0, 3)))
     mix = {a: np.ascontiguousarray(v, np.float32) for a, v in mix.items()}
-    hidden = inputs.gen_detailed_mixture(tgt) if target_kind == "detail" else tgt
+    hidden = inputs.gen_detailed_mixture(tgt, sub=detail_sub, narrow=detail_narrow) \
+        if target_kind == "detail" else tgt
     x = inputs.gen_workload_queries(w, q=q, mixtures=[hidden])
     proj = inputs.gen_projections(w.n, 16, inputs.SEED_PROJ)
     d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda")
@@ -189,8 +200,8 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
     target = targets(w, hidden, dev, proj)
     prec = ngd.BF16_MFMA if precision_name == "bf16_mfma" else ngd.FP32
     fit = Fit(d(mix["mean"]), d(mix["factor"]), d(mix["weight"]), d(mix["colour"]), lr=lr,
-              lr_alpha=lr_alpha, phase=phase, max_k=max_k, precision=prec,
-              child_alpha=child_alpha, child_jitter=child_jitter)
+              lr_alpha=lr_alpha, lr_child=lr_child, phase=phase, max_k=max_k, precision=prec,
+              child_alpha=child_alpha, child_jitter=child_jitter, adam_eps=adam_eps)
     log(f"fit: n={w.n} k0={k0} q={q} steps={steps} phase={phase} lr={lr}/{lr_alpha} "
         f"{precision_name}")
     ks, losses = [], []
@@ -201,7 +212,11 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
         if i == 0 or (i + 1) % phase == 0 or i + 1 == steps:
             losses.append((i + 1, float(loss[0])))   # synchronises: a few times per run
             ks.append((i + 1, fit.k))
-            log(f"fit step {i + 1}: loss {losses[-1][1]:.5g}, K {fit.k}")
+            rl = fit.refine_log[-1] if fit.refine_log and fit.refine_log[-1][0] == i + 1 \
+                else None
+            log(f"fit step {i + 1}: loss {losses[-1][1]:.5g}, K {fit.k}" +
+                (f"; refinement: {rl[1]} materialised, brightest child {rl[2]:.3g}, "
+                 f"{rl[3]} above t/10" if rl else ""))
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / max(steps, 1)
     if checkpoint:
@@ -212,13 +227,18 @@ def fit_bench(steps: int, precision_name: str, phase: int = 300, lr: float = 1e-
         higher_is_better=False, scaling="weak", vs_baseline=None,
         dtype="bf16+f32" if prec == ngd.BF16_MFMA else "f32", data="synthetic",
         config=dict(workload="10d-fit", n=w.n, k_start=k0, k_max=max_k, q=q, phase=phase,
-                    lr=lr, lr_alpha=lr_alpha, threshold=fit.threshold, loss="l2",
+                    lr=lr, lr_alpha=lr_alpha, lr_child=fit.lr_child, threshold=fit.threshold,
+                    loss="l2",
                     precision=precision_name,
-                    init=f"{rep} per target component, factors x{init_scale}",
-                    child_alpha=child_alpha, child_jitter=child_jitter,
+                    init=(f"{rep} per target component" if per_component >= 1 else
+                          f"one on {k0} of the {w.k_target} target components") +
+                         f", factors x{init_scale}",
+                    child_alpha=child_alpha, child_jitter=child_jitter, adam_eps=adam_eps,
                     target=target_kind, k_target=int(hidden["mean"].shape[0])),
         initial_loss=losses[0][1], final_loss=losses[-1][1], loss_trajectory=losses,
-        k_trajectory=ks)), flush=True)
+        k_trajectory=ks, refinements=[dict(step=a, materialised=b, brightest=round(m, 6),
+                                           above_tenth=t) for a, b, m, t in fit.refine_log])),
+        flush=True)
 
 
 def sweep_bench(reps: int = 5, sample: int = 4096):
@@ -778,6 +798,9 @@ def main():
                          "STEPS steps and print its own line (ms/step, losses, K)")
     ap.add_argument("--fit-lr", type=float, default=1e-3,
                     help="Adam learning rate of the means, factors and colours in --fit")
+    ap.add_argument("--fit-lr-child", type=float, default=None,
+                    help="Adam learning rate of the children's relative parameters in --fit "
+                         "(default: --fit-lr)")
     ap.add_argument("--fit-lr-alpha", type=float, default=3e-2,
                     help="Adam learning rate of the log-brightnesses in --fit")
     ap.add_argument("--fit-init-scale", type=float, default=0.7,
@@ -788,7 +811,16 @@ def main():
                     help="spread of a new child's relative parameters in --fit")
     ap.add_argument("--fit-target", default="coarse", choices=["coarse", "detail"],
                     help="hidden target of --fit: the K=4,096 mixture, or the same with "
-                         "16 narrower components in place of each (K=65,536)")
+                         "narrower components in place of each (--fit-detail-*)")
+    ap.add_argument("--fit-per-component", type=float, default=8,
+                    help="Gaussians of the --fit start per target component (below 1: one "
+                         "on that fraction of the components)")
+    ap.add_argument("--fit-detail-sub", type=int, default=16,
+                    help="components in place of each coarse one for --fit-target detail")
+    ap.add_argument("--fit-detail-narrow", type=float, default=0.35,
+                    help="their factor scale relative to the coarse one's")
+    ap.add_argument("--fit-adam-eps", type=float, default=1e-15,
+                    help="Adam's epsilon in --fit")
     ap.add_argument("--fit-checkpoint", default=None,
                     help="file the fit's final state is saved to (--fit)")
     args = ap.parse_args()
@@ -815,9 +847,12 @@ def main():
     ngd.lib()
     if args.fit > 0:
         fit_bench(args.fit, "fp32" if args.precision == "fp32" else "bf16_mfma",
-                  lr=args.fit_lr, lr_alpha=args.fit_lr_alpha, init_scale=args.fit_init_scale,
+                  lr=args.fit_lr, lr_alpha=args.fit_lr_alpha, lr_child=args.fit_lr_child,
+                  init_scale=args.fit_init_scale, per_component=args.fit_per_component,
                   child_alpha=args.fit_child_alpha, child_jitter=args.fit_child_jitter,
-                  checkpoint=args.fit_checkpoint, target_kind=args.fit_target)
+                  checkpoint=args.fit_checkpoint, target_kind=args.fit_target,
+                  detail_sub=args.fit_detail_sub, detail_narrow=args.fit_detail_narrow,
+                  adam_eps=args.fit_adam_eps)
         return
     if args.sweep:
         sweep_bench()

@@ -57,6 +57,50 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense(int64_t k, int64_t 
     }
 }
 
+// The same direct sum for batches too small to fill the chip one query per
+// lane: a workgroup takes 64 queries (lane = query) and its 4 waves split
+// the Gaussians into 4 consecutive ranges; the 4 partial sums are added in
+// range order through LDS, so the result does not depend on scheduling.
+constexpr int kSplit = kEvalThreads / kWave;
+template <int N>
+__global__ __launch_bounds__(kEvalThreads) void k_eval_dense_split(
+    int64_t k, int64_t q, const float *__restrict__ rec, const float *__restrict__ queries,
+    float *__restrict__ out)
+{
+    using Lay = RecLayout<N>;
+    __shared__ float part[kSplit][3][kWave];
+    const int w = int(threadIdx.x) / kWave, lane = lane_id();
+    const int64_t p = int64_t(blockIdx.x) * kWave + lane;
+    const bool valid = p < q;
+    float x[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) x[a] = valid ? queries[p * N + a] : 0.0f;
+    const int64_t per = (k + kSplit - 1) / kSplit;
+    const int64_t i0 = w * per, i1 = (i0 + per < k) ? i0 + per : k;
+    float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
+    float blk[Lay::PF], nxt[Lay::PF];
+    if (i0 < i1) load_block<N>(nxt, rec + i0 * Lay::R);
+    for (int64_t i = i0; i < i1; ++i) {
+#pragma unroll
+        for (int e = 0; e < Lay::PF; ++e) blk[e] = nxt[e];
+        if (i + 1 < i1) load_block<N>(nxt, rec + (i + 1) * Lay::R);
+        eval_pair<N, false>(blk, rec + i * Lay::R, x, valid, 0.0f, f0, f1, f2);
+    }
+    part[w][0][lane] = f0;
+    part[w][1][lane] = f1;
+    part[w][2][lane] = f2;
+    __syncthreads();
+    if (w == 0 && valid) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float acc = part[0][ch][lane];
+#pragma unroll
+            for (int v = 1; v < kSplit; ++v) acc += part[v][ch][lane];
+            out[p * 3 + ch] = acc;
+        }
+    }
+}
+
 // OUT = false: only the keep/skip flags are written (the backward pass needs
 // them when no forward ran on this cull).  COUNT (with OUT = false): the
 // flags are written and the stage counters of every wave are added to
@@ -182,8 +226,17 @@ template <int N>
 hipError_t dense_n(const ngd_mixture *mix, const float *queries, int64_t q, float *out,
                    hipStream_t s)
 {
-    const unsigned blocks = unsigned((q + kEvalThreads - 1) / kEvalThreads);
-    k_eval_dense<N><<<blocks, kEvalThreads, 0, s>>>(mix->k, q, mix->rec.as<float>(), queries, out);
+    // one query per lane while that gives every SIMD several waves;
+    // smaller batches split the Gaussians over the waves of a workgroup
+    if (q >= (int64_t(1) << 18) || mix->k < 4 * kSplit) {
+        const unsigned blocks = unsigned((q + kEvalThreads - 1) / kEvalThreads);
+        k_eval_dense<N><<<blocks, kEvalThreads, 0, s>>>(mix->k, q, mix->rec.as<float>(), queries,
+                                                        out);
+    } else {
+        const unsigned blocks = unsigned((q + kWave - 1) / kWave);
+        k_eval_dense_split<N><<<blocks, kEvalThreads, 0, s>>>(mix->k, q, mix->rec.as<float>(),
+                                                              queries, out);
+    }
     return hipGetLastError();
 }
 

@@ -100,15 +100,17 @@ class Fit:
     (0, 1): the initial mixture (activated values), any device tensors.
     """
 
-    def __init__(self, mean, factor, weight, colour, *, lr=1e-3, lr_alpha=None,
+    def __init__(self, mean, factor, weight, colour, *, lr=1e-3, lr_alpha=None, lr_child=None,
                  threshold=0.01, phase=300, max_k=524288, child_alpha=1e-4, child_jitter=1e-2,
                  loss="l2", eps=0.01, precision=ngd.FP32, cull_params=None, seed=0,
-                 compose="kernel"):
+                 compose="kernel", adam_eps=1e-15):
         dev = mean.device
         self.n = mean.shape[1]
         self.lr, self.threshold, self.phase = lr, threshold, phase
         self.lr_alpha = lr if lr_alpha is None else lr_alpha
+        self.lr_child = lr if lr_child is None else lr_child
         self.max_k, self.child_alpha, self.child_jitter = max_k, child_alpha, child_jitter
+        self.adam_eps = adam_eps
         self.loss_kind, self.eps, self.precision = loss, eps, precision
         if compose not in ("kernel", "torch"):
             raise ValueError(f"compose must be 'kernel' or 'torch', got {compose!r}")
@@ -123,6 +125,9 @@ class Fit:
         self.c = torch.logit(colour.detach().to(**f32).clamp(1e-4, 1 - 1e-4)).requires_grad_(True)
         self.child = None   # raw (u, m_u, a, c) once the second phase starts
         self.steps = 0
+        # one entry per refinement: (step, children materialised, the
+        # children's largest brightness, how many exceeded a tenth of t)
+        self.refine_log: list[tuple[int, int, float, int]] = []
         self.ev = Evaluator(self.n, None, self.params, precision)
         self.ev.cull = ngd.Cull()
         self._new_optimizer()
@@ -136,12 +141,19 @@ class Fit:
 
     def _new_optimizer(self):
         # moments restart whenever the parameter set changes (refinement);
-        # the log-brightnesses have a learning rate of their own
-        leaves = self._leaves()
-        alpha = [self.a] + ([self.child[2]] if self.child is not None else [])
-        rest = [t for t in leaves if all(t is not b for b in alpha)]
-        self.opt = torch.optim.Adam([dict(params=rest, lr=self.lr),
-                                     dict(params=alpha, lr=self.lr_alpha)])
+        # the log-brightnesses have a learning rate of their own, and so do
+        # the children's relative factor, offset and colour (their steps are
+        # in units of the parent's frame).  Adam's epsilon is far below the
+        # usual 1e-8: a mean loss over millions of queries gives a dim child
+        # gradients of order 1e-10, which an epsilon of 1e-8 would swamp, so
+        # that the child could never move or brighten.
+        groups = [dict(params=[self.mean, self.factor, self.c], lr=self.lr),
+                  dict(params=[self.a], lr=self.lr_alpha)]
+        if self.child is not None:
+            u, m_u, a_c, c_c = self.child
+            groups += [dict(params=[u, m_u, c_c], lr=self.lr_child),
+                       dict(params=[a_c], lr=self.lr_alpha)]
+        self.opt = torch.optim.Adam(groups, eps=self.adam_eps)
 
     @property
     def k(self) -> int:
@@ -222,8 +234,11 @@ class Fit:
             u, m_u, a_c, c_c = self.child
             kp = self.mean.shape[0]
             room = max(0, self.max_k // 2 - kp)
-            sel = torch.nonzero(torch.exp(a_c) > self.threshold).flatten()[:room]
+            bright = torch.exp(a_c)
+            sel = torch.nonzero(bright > self.threshold).flatten()[:room]
             count = int(sel.numel())
+            self.refine_log.append((self.steps, count, float(bright.max()),
+                                    int((bright > 0.1 * self.threshold).sum())))
             if count == 0:
                 return 0
             lp = activate_factor(self.factor[sel], self.n)

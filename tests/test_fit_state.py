@@ -2,7 +2,8 @@
 (and save / load through a file) carry the raw parameters, the children,
 Adam's moments, the step count and the generator, so that a restored fit
 takes exactly the steps the original takes.  Gradients are supplied by hand
-here (the library's forward needs a GPU); the GPU test resumes a real run."""
+here (the library's forward needs a GPU); tests/test_gpu_zfit.py resumes a
+real run on the GPU."""
 
 import numpy as np
 import pytest

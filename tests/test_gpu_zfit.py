@@ -152,3 +152,55 @@ def test_fit_gradients_match_the_oracle_chain(torch_cuda):
             e = normwise(a, leaf.grad.numpy())
             print(f"  leaf {i}: normwise {e:.2e}", flush=True)
             assert e <= 1e-4, (n, i, e)
+
+
+def test_resumed_fit_takes_the_same_steps(torch_cuda, tmp_path):
+    """A fit saved mid-run and loaded into a fresh Fit (another seed) takes
+    the same steps as the uninterrupted one, through a phase end that adds
+    children and one that refines: every kernel is deterministic (no float
+    atomics), so the parameters agree bit for bit."""
+    torch = torch_cuda
+    xd, target, proj, init = _problem(torch)
+    kw = dict(lr=2e-3, lr_alpha=0.05, lr_child=1e-2, phase=5, child_alpha=5e-3,
+              child_jitter=0.3)
+    a = _fit(torch, init, seed=3, **kw)
+    for _ in range(7):          # children added at step 5
+        a.step(xd, target, proj)
+    path = str(tmp_path / "fit.pt")
+    a.save(path)
+    b = _fit(torch, init, seed=11, **kw)
+    b.load(path)
+    for _ in range(6):          # a refinement at step 10
+        a.step(xd, target, proj)
+        b.step(xd, target, proj)
+    assert a.steps == b.steps == 13 and a.k == b.k
+    for x, y in zip(a._leaves(), b._leaves()):
+        assert torch.equal(x.detach(), y.detach())
+
+
+def test_children_brighten_and_materialise(torch_cuda):
+    """Refinement fires where the start lacks capacity: a start on the
+    coarse components of a target with 4 narrower components in place of
+    each (inputs.gen_detailed_mixture) grows K and ends with a lower loss
+    than at the first phase end (children at 10^-3, t = 0.01)."""
+    torch = torch_cuda
+    from paper_2405_20067_amd import ngd
+    n, k, q = 4, 64, 32768
+    coarse = inputs.gen_mixture(n, k, seed=5)
+    hidden = inputs.gen_detailed_mixture(coarse, sub=4, narrow=0.6)
+    x = np.concatenate([inputs.gen_queries(n, q // 2, seed=6),
+                        inputs.gen_near_queries([hidden], q - q // 2, seed=7)])
+    proj = inputs.gen_projections(n, 16, inputs.SEED_PROJ)
+    xd = dev(x)
+    mt = ngd.Mixture(n, hidden["mean"].shape[0])
+    mt.update(*(dev(hidden[a]) for a in ("mean", "factor", "weight", "colour")))
+    target = ngd.eval_mixture(mt, None, xd)
+    init = {a: dev(coarse[a]) for a in ("mean", "factor", "weight", "colour")}
+    fit = _fit(torch, init, lr=2e-3, lr_alpha=0.05, lr_child=1e-2, phase=100,
+               child_alpha=1e-3, child_jitter=0.3)
+    losses = [float(host(fit.step(xd, target, proj))[0]) for _ in range(500)]
+    grown = sum(c for _, c, _, _ in fit.refine_log)
+    print(f"[refine] K {2 * k} -> {fit.k}, materialised {grown}, loss {losses[99]:.4g} -> "
+          f"{losses[-1]:.4g}; log {fit.refine_log}", flush=True)
+    assert grown > 0 and fit.k == 2 * (k + grown)
+    assert np.isfinite(losses).all() and losses[-1] < losses[99]
