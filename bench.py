@@ -796,18 +796,17 @@ def main():
     ap.add_argument("--fit", type=int, default=0, metavar="STEPS",
                     help="instead of the step benchmark, run the 10-D fitting loop for "
                          "STEPS steps and print its own line (ms/step, losses, K)")
-    ap.add_argument("--fit-lr", type=float, default=1e-3,
+    ap.add_argument("--fit-lr", type=float, default=2e-3,
                     help="Adam learning rate of the means, factors and colours in --fit")
-    ap.add_argument("--fit-lr-child", type=float, default=None,
-                    help="Adam learning rate of the children's relative parameters in --fit "
-                         "(default: --fit-lr)")
-    ap.add_argument("--fit-lr-alpha", type=float, default=3e-2,
+    ap.add_argument("--fit-lr-child", type=float, default=1e-2,
+                    help="Adam learning rate of the children's relative parameters in --fit")
+    ap.add_argument("--fit-lr-alpha", type=float, default=5e-2,
                     help="Adam learning rate of the log-brightnesses in --fit")
     ap.add_argument("--fit-init-scale", type=float, default=0.7,
                     help="factor scale of the start relative to the target's in --fit")
-    ap.add_argument("--fit-child-alpha", type=float, default=1e-4,
+    ap.add_argument("--fit-child-alpha", type=float, default=1e-3,
                     help="brightness of a new child in --fit")
-    ap.add_argument("--fit-child-jitter", type=float, default=1e-2,
+    ap.add_argument("--fit-child-jitter", type=float, default=0.3,
                     help="spread of a new child's relative parameters in --fit")
     ap.add_argument("--fit-target", default="coarse", choices=["coarse", "detail"],
                     help="hidden target of --fit: the K=4,096 mixture, or the same with "
