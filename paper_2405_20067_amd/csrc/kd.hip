@@ -654,14 +654,25 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
                     lo[j] = 0xffffffffu;
                     hi[j] = 0u;
                 }
-#pragma unroll 1
-                for (int u = 0; u < kPer; ++u) {
-                    if (p0 + u >= m || rsi[run_of[p0 + u]] < 0) continue;
-                    const int o = ord[cur][p0 + u];
+                // all of the lane's loads issued together (positions outside
+                // a splitting run read a valid point and are left out)
+                int ou[kPer];
+                bool in[kPer];
 #pragma unroll
-                    for (int j = 0; j < PMAX; ++j) {
-                        if (j < P) {
-                            const uint32_t k = orderable(vin[int64_t(j) * n + start + o]);
+                for (int u = 0; u < kPer; ++u) {
+                    in[u] = p0 + u < m && sl[u] >= 0;
+                    ou[u] = in[u] ? ord[cur][p0 + u] : 0;
+                }
+#pragma unroll
+                for (int j = 0; j < PMAX; ++j) {
+                    if (j < P) {
+                        float v[kPer];
+#pragma unroll
+                        for (int u = 0; u < kPer; ++u) v[u] = vin[int64_t(j) * n + start + ou[u]];
+#pragma unroll
+                        for (int u = 0; u < kPer; ++u) {
+                            if (!in[u]) continue;
+                            const uint32_t k = orderable(v[u]);
                             lo[j] = min(lo[j], k);
                             hi[j] = max(hi[j], k);
                         }
