@@ -514,7 +514,7 @@ def run_workload(name: str, args, precisions, with_dense: bool, steps: int, warm
 
 # the workloads of the other configurations, timed after the headline one
 # and reported beside it in the same line
-OTHER_WORKLOADS = ("4d-dense", "6d-culled", "10d-4m")
+OTHER_WORKLOADS = ("4d-dense", "6d-culled", "10d-uniform", "10d-4m")
 
 
 def image_bench(reps: int = 5, sample: int = 2048, width: int = 800, k: int = 262144):

@@ -91,6 +91,11 @@ WORKLOADS = {
         description="10-D surface mixture (pos, normal, view, roughness), "
                     "K=262,144, 2^20 queries, culled FP32 forward + backward "
                     "of an L2 loss against a hidden K=4,096 mixture"),
+    "10d-uniform": Workload(
+        "10d-uniform", 10, 262144, 1 << 20, "pos3+nrm3+view3+rough1",
+        (10.0, 200.0), 5.0, 0.0, k_target=4096, backward=True,
+        description="the 10-D fwd+bwd workload with all 2^20 queries uniform over the "
+                    "domain (none drawn near the mixtures)"),
     "10d-4m": Workload(
         "10d-4m", 10, 262144, 1 << 22, "pos3+nrm3+view3+rough1",
         (10.0, 200.0), 5.0, 0.5, k_target=4096, backward=True,
