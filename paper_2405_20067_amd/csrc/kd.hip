@@ -663,20 +663,32 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
                     in[u] = p0 + u < m && sl[u] >= 0;
                     ou[u] = in[u] ? ord[cur][p0 + u] : 0;
                 }
+                // four projections per round: the workgroup's gathers then
+                // stay within 4 x 4 KB of the subtree's values at a time,
+                // which the L2 keeps while every lane reads them
 #pragma unroll
-                for (int j = 0; j < PMAX; ++j) {
-                    if (j < P) {
-                        float v[kPer];
+                for (int j0 = 0; j0 < PMAX; j0 += 4) {
+                    float v[4][kPer];
 #pragma unroll
-                        for (int u = 0; u < kPer; ++u) v[u] = vin[int64_t(j) * n + start + ou[u]];
+                    for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                        for (int u = 0; u < kPer; ++u)
+                            v[jj][u] = j0 + jj < P ? vin[int64_t(j0 + jj) * n + start + ou[u]] : 0.0f;
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) {
+                        const int j = j0 + jj;
+                        if (j >= P) continue;
 #pragma unroll
                         for (int u = 0; u < kPer; ++u) {
                             if (!in[u]) continue;
-                            const uint32_t k = orderable(v[u]);
+                            const uint32_t k = orderable(v[jj][u]);
                             lo[j] = min(lo[j], k);
                             hi[j] = max(hi[j], k);
                         }
                     }
+                    // each round's loads complete before the next round's
+                    // are issued
+                    __builtin_amdgcn_s_waitcnt(0);
                 }
                 merge(lr, lo, hi);
             } else {
