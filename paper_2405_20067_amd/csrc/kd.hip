@@ -853,20 +853,32 @@ __global__ __launch_bounds__(kLocalThreads) void k_kd_local(
             for (int i = rs[b] + lane; i < rs[b] + rl[b]; i += kWave) run_of[i] = uint8_t(b);
         __syncthreads();
     }
+    // the subtree's points in their final order; the values move four
+    // projections at a time, as the extents read them
+    int64_t of[kPer];
+    bool pin[kPer];
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int p = tid + q * kLocalThreads;
-        if (p >= m) break;
-        const int64_t o = start + ord[cur][p];
-        idx_out[start + p] = idx_in ? idx_in[o] : int32_t(o);
-        if (vout) {
-            float v[PMAX];
+        pin[q] = p < m;
+        of[q] = start + (pin[q] ? ord[cur][p] : 0);
+        if (pin[q]) idx_out[start + p] = idx_in ? idx_in[of[q]] : int32_t(of[q]);
+    }
+    if (vout) {
 #pragma unroll
-            for (int j = 0; j < PMAX; ++j)
-                if (j < P) v[j] = vin[int64_t(j) * n + o];
+        for (int j0 = 0; j0 < PMAX; j0 += 4) {
+            float v[4][kPer];
 #pragma unroll
-            for (int j = 0; j < PMAX; ++j)
-                if (j < P) vout[int64_t(j) * n + start + p] = v[j];
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int q = 0; q < kPer; ++q)
+                    v[jj][q] = j0 + jj < P ? vin[int64_t(j0 + jj) * n + of[q]] : 0.0f;
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int q = 0; q < kPer; ++q)
+                    if (j0 + jj < P && pin[q])
+                        vout[int64_t(j0 + jj) * n + start + tid + q * kLocalThreads] = v[jj][q];
         }
     }
 }
