@@ -426,6 +426,7 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (!cull_reserve_front(c))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: device workspace allocation failed"));
     hipStream_t s = S(stream);
+    c->coef_next = false;
     hipError_t e = hipMemcpyAsync(c->proj.p, proj, sizeof(float) * p->n_proj * mix->n,
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_cull_build_front(c, mix, queries, s);
@@ -452,6 +453,7 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: candidate list allocation failed"));
     c->act_version = -1;
     ++c->build_seq;
+    if (c->coef_next) c->coef_seq = c->build_seq;
     c->transposed = false;
     e = launch_cull_build_lists(c, s);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (lists)"));

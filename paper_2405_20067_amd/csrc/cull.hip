@@ -232,6 +232,9 @@ __global__ __launch_bounds__(kThreads) void k_keys(int64_t n, int P,
 }
 
 // ---- tiles ---------------------------------------------------------------
+// Also the centre of each tile's box in the query space (the midpoint of
+// each coordinate's range; the matrix-core forward expands its quadratic
+// forms about it), into tcen.
 template <int N, int PMAX>
 __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P, int PP,
                                                       const int32_t *__restrict__ perm,
@@ -241,9 +244,11 @@ __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P
                                                       float *__restrict__ qs,
                                                       float *__restrict__ tlo,
                                                       float *__restrict__ thi,
-                                                      float *__restrict__ tbnd)
+                                                      float *__restrict__ tbnd,
+                                                      float *__restrict__ tcen)
 {
     __shared__ float smin[1024 / kWave][PMAX], smax[1024 / kWave][PMAX];
+    __shared__ float xmin[1024 / kWave][N], xmax[1024 / kWave][N];
     const int64_t t = blockIdx.x;
     float lo[PMAX], hi[PMAX];
 #pragma unroll
@@ -268,17 +273,58 @@ __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P
         }
     }
     const int w = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    // wave minima / maxima by DPP on order-preserving keys (the float order
+    // exactly, no LDS traffic), totals in lane 63
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) {
         if (j < P) {
-            const float a = wave_min(lo[j]), b = wave_max(hi[j]);
-            if (lane_id() == 0) {
-                smin[w][j] = a;
-                smax[w][j] = b;
+            const uint32_t a = wave_umin_dpp(orderable(lo[j]));
+            const uint32_t b = wave_umax_dpp(orderable(hi[j]));
+            if (lane_id() == kWave - 1) {
+                smin[w][j] = from_orderable(a);
+                smax[w][j] = from_orderable(b);
+            }
+        }
+    }
+    // the coordinates' ranges, read back from this thread's own stores of
+    // the sorted copy (coalesced), once the projections' registers are free
+    {
+        float xl[N], xh[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            xl[a] = INFINITY;
+            xh[a] = -INFINITY;
+        }
+        for (int s = threadIdx.x; s < tile; s += blockDim.x) {
+            const int64_t p = t * tile + s;
+            if (p >= q) break;
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                const float v = qs[a * q + p];
+                xl[a] = fminf(xl[a], v);
+                xh[a] = fmaxf(xh[a], v);
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            const uint32_t mn = wave_umin_dpp(orderable(xl[a]));
+            const uint32_t mx = wave_umax_dpp(orderable(xh[a]));
+            if (lane_id() == kWave - 1) {
+                xmin[w][a] = from_orderable(mn);
+                xmax[w][a] = from_orderable(mx);
             }
         }
     }
     __syncthreads();
+    if (int(threadIdx.x) < N) {
+        const int a = threadIdx.x;
+        float mn = INFINITY, mx = -INFINITY;
+        for (int i = 0; i < nw; ++i) {
+            mn = fminf(mn, xmin[i][a]);
+            mx = fmaxf(mx, xmax[i][a]);
+        }
+        tcen[t * N + a] = (mn <= mx) ? 0.5f * mn + 0.5f * mx : 0.0f;
+    }
     if (int(threadIdx.x) < PP) {
         const int j = threadIdx.x;
         // the padding projections pass every test
@@ -813,10 +859,14 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
             if (!rq.done) e = kd_step(rq);
             if (e == hipSuccess && !rg.done) e = kd_step(rg);
         }
-        // the Gaussians' side goes on while the queries' order finishes
+        // the Gaussians' side goes on while the queries' order finishes,
+        // and with it the matrix-core forward's per-Gaussian coefficients
+        // (off the critical path: the queries' order takes longer)
         if (forked && e == hipSuccess) {
             e = gauss_side(c, mix, k, R, P, true, c->side);
             gauss_done = true;
+            if (e == hipSuccess) e = launch_mfma_coef(N, c, c->side);
+            c->coef_next = e == hipSuccess;
         }
         if (forked) {
             const hipError_t ej = hipEventRecord(c->ev_join, c->side);
@@ -863,12 +913,12 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
             k_tile_bounds<N, 16><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
                 q, c->params.tile, P, PP, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s,
                 queries, c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>(),
-                c->tbnd.as<float>());
+                c->tbnd.as<float>(), c->tcen.as<float>());
         else
             k_tile_bounds<N, 32><<<dim3(unsigned(c->ntiles)), bt, 0, s>>>(
                 q, c->params.tile, P, PP, c->perm.as<int32_t>(), c->qr.as<float>(), qr_s,
                 queries, c->qs.as<float>(), c->tile_lo.as<float>(), c->tile_hi.as<float>(),
-                c->tbnd.as<float>());
+                c->tbnd.as<float>(), c->tcen.as<float>());
         const int64_t nsup = (c->ntiles + kSuperTiles - 1) / kSuperTiles;
         k_super_bounds<<<nblk(nsup * 2 * PP, kThreads), kThreads, 0, s>>>(
             c->ntiles, PP, c->tbnd.as<float>(), c->sbnd.as<float>());
@@ -1116,9 +1166,12 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->tile_lo.ensure(sizeof(float) * T * P);
     ok &= c->tile_hi.ensure(sizeof(float) * T * P);
     ok &= c->tbnd.ensure(sizeof(float) * T * 2 * pad_proj(P));
+    ok &= c->tcen.ensure(sizeof(float) * T * c->n);
     ok &= c->sbnd.ensure(sizeof(float) * ((T + kSuperTiles - 1) / kSuperTiles) * 2 * pad_proj(P));
     if (c->params.tiling == 0) ok &= c->qr_s.ensure(sizeof(float) * P * qq);
     ok &= c->grec.ensure(sizeof(float) * kk * rec_stride(int(n)));
+    ok &= c->mrec.ensure(kk * mfma_rec_bytes(int(n)));
+    ok &= c->mrow.ensure(sizeof(float) * kk);
     ok &= c->g_mr_s.ensure(sizeof(float) * P * kk);
     ok &= c->g_ub.ensure(sizeof(float) * P * kk);
     ok &= c->g_lb.ensure(sizeof(float) * P * kk);

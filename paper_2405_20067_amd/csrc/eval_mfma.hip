@@ -31,9 +31,10 @@
 // they differ from the fp32 kernel's only by pairs below the certificate.
 //
 // Once per cull build: the quadratic coefficients of every ordered Gaussian
-// (float64 P', then bf16 hi / lo), the centre of every tile's query box, and
-// for every candidate entry (tile, Gaussian) the centred constant and linear
-// coefficients and bound terms -- one thread per entry.
+// (float64 P', then bf16 hi / lo) and for every candidate entry (tile,
+// Gaussian) the centred constant and linear coefficients and bound terms --
+// one thread per entry; the centre of every tile's query box comes with the
+// cull's tile bounds.
 // Filter kernel, one workgroup per tile (up to 256 queries in 4 waves):
 // per wave the query features as MFMA A fragments (rows = queries, 2 blocks
 // of 32); the entries' B fragments staged in LDS in double-buffered chunks of
@@ -144,51 +145,6 @@ __global__ __launch_bounds__(256) void k_mfma_coef(int64_t k, const float *__res
         best = rs > best ? rs : best;
     }
     rrow[s] = float(best) * (1.0f + 1.0f / 1048576.0f);
-}
-
-// Centre of each tile's query box (x-space, the sorted queries).
-template <int N>
-__global__ __launch_bounds__(256) void k_tile_centre(int64_t q, int tile,
-                                                     const float *__restrict__ qs,
-                                                     float *__restrict__ tcen)
-{
-    __shared__ float slo[256 / kWave][N], shi[256 / kWave][N];
-    const int64_t t = blockIdx.x;
-    float lo[N], hi[N];
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-        lo[a] = INFINITY;
-        hi[a] = -INFINITY;
-    }
-    for (int i = int(threadIdx.x); i < tile; i += 256) {
-        const int64_t p = t * tile + i;
-        if (p >= q) break;
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            const float v = qs[a * q + p];
-            lo[a] = fminf(lo[a], v);
-            hi[a] = fmaxf(hi[a], v);
-        }
-    }
-    const int w = int(threadIdx.x) / kWave;
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-        const float mn = wave_min(lo[a]), mx = wave_max(hi[a]);
-        if (lane_id() == 0) {
-            slo[w][a] = mn;
-            shi[w][a] = mx;
-        }
-    }
-    __syncthreads();
-    if (int(threadIdx.x) < N) {
-        const int a = int(threadIdx.x);
-        float mn = INFINITY, mx = -INFINITY;
-        for (int v = 0; v < 256 / kWave; ++v) {
-            mn = fminf(mn, slo[v][a]);
-            mx = fmaxf(mx, shi[v][a]);
-        }
-        tcen[t * N + a] = (mn <= mx) ? 0.5f * mn + 0.5f * mx : 0.0f;
-    }
 }
 
 // Per candidate entry (tile, Gaussian): the centred constant and linear
@@ -610,15 +566,15 @@ __global__ __launch_bounds__(kMThreads, 3) void k_mfma_filter(
 template <int N>
 hipError_t mfma_prepare_n(ngd_cull *c, hipStream_t s)
 {
-    const int tile = c->params.tile;
     hipError_t e;
     if (c->mrec_seq != c->build_seq) {
-        // once per cull build: per-Gaussian quadratic coefficients, tile
-        // centres, per-entry centred coefficients
-        k_mfma_coef<N><<<unsigned((c->k + 255) / 256), 256, 0, s>>>(
-            c->k, c->grec.as<float>(), c->mrec.as<__bf16>(), c->mrow.as<float>());
-        k_tile_centre<N><<<unsigned(c->ntiles), 256, 0, s>>>(c->q, tile, c->qs.as<float>(),
-                                                            c->tcen.as<float>());
+        // once per cull build: per-Gaussian quadratic coefficients (unless
+        // the build launched them beside its own work) and the per-entry
+        // centred coefficients (the tile centres come with the cull's tile
+        // bounds)
+        if (c->coef_seq != c->build_seq && c->k > 0)
+            k_mfma_coef<N><<<unsigned((c->k + 255) / 256), 256, 0, s>>>(
+                c->k, c->grec.as<float>(), c->mrec.as<__bf16>(), c->mrow.as<float>());
         if (c->total > 0)
             k_mfma_entry<N><<<unsigned((c->total + 255) / 256), 256, 0, s>>>(
                 c->total, c->cand.as<int32_t>(), c->ent_tile.as<int32_t>(), c->grec.as<float>(),
@@ -670,6 +626,22 @@ size_t mfma_rec_bytes(int n)
 }
 
 size_t mfma_entry_bytes() { return 4 * sizeof(bf16x8) + sizeof(float4); }
+
+hipError_t launch_mfma_coef(int n, ngd_cull *c, hipStream_t s)
+{
+    if (c->k == 0) return hipSuccess;
+    switch (n) {
+#define NGD_CASE(NN)                                                                           \
+    case NN:                                                                                   \
+        k_mfma_coef<NN><<<unsigned((c->k + 255) / 256), 256, 0, s>>>(                          \
+            c->k, c->grec.as<float>(), c->mrec.as<__bf16>(), c->mrow.as<float>());             \
+        return hipGetLastError();
+        NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
+        NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
+#undef NGD_CASE
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_mfma_prepare(const ngd_mixture *mix, ngd_cull *c, hipStream_t s)
 {

@@ -74,20 +74,6 @@ constexpr int kNodeCols = 8;
 // slice table row: start, length, node
 constexpr int kSliceCols = 3;
 
-__device__ __forceinline__ uint32_t wave_umin(uint32_t v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = min(v, uint32_t(__shfl_xor(int(v), m, kWave)));
-    return v;
-}
-
-__device__ __forceinline__ uint32_t wave_umax(uint32_t v)
-{
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v = max(v, uint32_t(__shfl_xor(int(v), m, kWave)));
-    return v;
-}
-
 // The plane of min / max key slots a workgroup merges into.
 __device__ __forceinline__ uint32_t *ext_plane(uint32_t *ext, int64_t max_nodes, int P)
 {
@@ -117,11 +103,12 @@ __device__ void block_merge_ext(const uint32_t (&kmin)[PMAX], const uint32_t (&k
 {
     __shared__ uint32_t smin[kThreads / kWave][PMAX], smax[kThreads / kWave][PMAX];
     const int w = threadIdx.x / kWave;
+    // wave minima / maxima by DPP (no LDS traffic), totals in lane 63
 #pragma unroll
     for (int j = 0; j < PMAX; ++j) {
         if (j < P) {
-            const uint32_t a = wave_umin(kmin[j]), b = wave_umax(kmax[j]);
-            if (lane_id() == 0) {
+            const uint32_t a = wave_umin_dpp(kmin[j]), b = wave_umax_dpp(kmax[j]);
+            if (lane_id() == kWave - 1) {
                 smin[w][j] = a;
                 smax[w][j] = b;
             }

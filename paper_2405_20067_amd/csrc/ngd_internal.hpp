@@ -206,7 +206,9 @@ struct ngd_cull {
     ngd::DevBuf eb0;           // total x 64 B: centred constant / linear terms, bf16
     ngd::DevBuf ebnd;          // total x 4 float: bound terms of each entry
     int64_t build_seq = 0;     // builds of this handle
-    int64_t mrec_seq = -1;     // build the coefficients belong to
+    int64_t mrec_seq = -1;     // build the per-entry records belong to
+    int64_t coef_seq = -1;     // build the per-Gaussian coefficients (mrec, mrow) belong to
+    bool coef_next = false;    // the build in progress has launched them
 };
 
 namespace ngd {
@@ -261,6 +263,9 @@ hipError_t launch_mfma_prepare(const ngd_mixture *mix, ngd_cull *c, hipStream_t 
 hipError_t launch_eval_mfma(const ngd_mixture *mix, ngd_cull *c, float *out,
                             unsigned long long *stats, hipStream_t s);
 size_t mfma_rec_bytes(int n);
+// The per-Gaussian coefficients of the matrix-core forward (c->mrec, c->mrow)
+// from the cull's ordered records c->grec, on stream s.
+hipError_t launch_mfma_coef(int n, ngd_cull *c, hipStream_t s);
 size_t mfma_entry_bytes();
 hipError_t launch_eval_culled(const ngd_mixture *mix, const ngd_cull *c, float *out,
                               hipStream_t s);
