@@ -161,18 +161,16 @@ __global__ __launch_bounds__(kThreads) void k_kd_root_ext(int64_t n, int P,
     block_merge_ext<PMAX>(kmin, kmax, P, ext_plane(ext, max_nodes, P), 0);
 }
 
-// Block exclusive scan of one int64 per thread (THREADS threads).
+// Block exclusive scan of one count per thread (THREADS threads).  Every
+// caller scans counts of points of one node, whose wave sums stay below
+// 2^31 (the point count is): the wave scan runs in 32 bits by DPP, the
+// workgroup's combination in 64.
 template <int THREADS = kThreads>
 __device__ int64_t block_exscan(int64_t v, int64_t *total)
 {
     __shared__ int64_t wt[THREADS / kWave];
     const int lane = lane_id(), w = threadIdx.x / kWave;
-    int64_t inc = v;
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int64_t y = __shfl_up(inc, d, kWave);
-        if (lane >= d) inc += y;
-    }
+    const int64_t inc = wave_inclusive_scan(int(v));
     if (lane == kWave - 1) wt[w] = inc;
     __syncthreads();
     int64_t before = 0, all = 0;
