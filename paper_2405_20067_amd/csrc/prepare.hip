@@ -34,17 +34,19 @@ __global__ __launch_bounds__(256) void k_prepare(int64_t k, const float *__restr
     for (int a = 0; a < N; ++a) bad |= (L[a * (a + 1) / 2 + a] == 0.0);
 
     // S = L^-1, column by column: S_jj = 1 / L_jj,
-    // S_ij = -(sum_{k=j}^{i-1} L_ik S_kj) / L_ii  for i > j.
+    // S_ij = -(sum_{k=j}^{i-1} L_ik S_kj) S_ii  for i > j
+    // (one float64 division per row; S_ii = 1 / L_ii).
     double S[T];
 #pragma unroll
+    for (int j = 0; j < N; ++j) S[j * (j + 1) / 2 + j] = 1.0 / L[j * (j + 1) / 2 + j];
+#pragma unroll
     for (int j = 0; j < N; ++j) {
-        S[j * (j + 1) / 2 + j] = 1.0 / L[j * (j + 1) / 2 + j];
 #pragma unroll
         for (int r = j + 1; r < N; ++r) {
             double acc = 0.0;
 #pragma unroll
             for (int c = j; c < r; ++c) acc = fma(L[r * (r + 1) / 2 + c], S[c * (c + 1) / 2 + j], acc);
-            S[r * (r + 1) / 2 + j] = -acc / L[r * (r + 1) / 2 + r];
+            S[r * (r + 1) / 2 + j] = -acc * S[r * (r + 1) / 2 + r];
         }
     }
 
