@@ -229,11 +229,13 @@ int ngd_eval(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
              int64_t q, int precision, float *out, void *stream);
 
 /* Builds, ahead of ngd_eval, what a forward of `precision` derives once per
- * cull build: for NGD_BF16_MFMA the per-Gaussian quadratic coefficients,
- * the tiles' centres and the per-entry centred terms (the matrix-core
- * forward of Eq. 1-2 expanded); nothing for NGD_FP32.  ngd_eval builds them
- * itself when they are missing, so this call only moves that work out of
- * the first forward (for instance to time the forward kernel alone).
+ * cull build: for NGD_BF16_MFMA the per-entry centred terms of the
+ * matrix-core forward of Eq. 1-2 expanded (and the per-Gaussian quadratic
+ * coefficients, which ngd_cull_build itself launches beside its own work when
+ * it orders the Gaussians on its second stream; the tiles' centres come with
+ * the cull's tile bounds); nothing for NGD_FP32.  ngd_eval builds them itself
+ * when they are missing, so this call only moves that work out of the first
+ * forward (for instance to time the forward kernel alone).
  *   mix, cull, queries, q as for ngd_eval (a cull is required).
  * Returns NGD_E_INVAL for a NULL handle or an unknown precision,
  * NGD_E_STALE for a cull of another mixture version or queries.
