@@ -247,9 +247,12 @@ int ngd_eval_prepare(const ngd_mixture *mix, const ngd_cull *cull, const float *
  * Runs the forward kernel of `precision` on the same cull in a counting mode
  * (no colours written) and returns in counts (host, 5 x int64): the
  * (64-query group, candidate) pairs examined, those not skipped by the
- * matrix-core filter (all of them with NGD_FP32), those that then passed the
- * first and the second Mahalanobis-bound check (marginals over the first 3
- * and 6 coordinates), and those kept (evaluated with exp and accumulated).
+ * first filter (the matrix-core one with NGD_BF16_MFMA; with NGD_FP32 the
+ * test of the group's bounding box against each Gaussian's per-coordinate
+ * box of half-widths sqrt(2 ln2 skip V_ii), skip the forward's threshold),
+ * those that then passed the first and the second Mahalanobis-bound check
+ * (marginals over the first 3 and 6 coordinates), and those kept (evaluated
+ * with exp and accumulated).
  * `cull` and `queries`/q as for ngd_eval. */
 int ngd_eval_stats(const ngd_mixture *mix, const ngd_cull *cull, const float *queries,
                    int64_t q, int precision, int64_t *counts, void *stream);

@@ -199,13 +199,15 @@ int ngd_mixture_create(int n, int64_t k, ngd_mixture **out)
     m->k = k;
     const size_t kk = size_t(k > 0 ? k : 1);
     if (!m->rec.ensure(sizeof(float) * kk * rec_stride(n)) ||
-        !m->lfac.ensure(sizeof(float) * kk * tri(n)) || !m->flag.ensure(sizeof(int))) {
+        !m->lfac.ensure(sizeof(float) * kk * tri(n)) ||
+        !m->msd.ensure(sizeof(float) * kk * n) || !m->flag.ensure(sizeof(int))) {
         m->rec.release();
         m->lfac.release();
+        m->msd.release();
         m->flag.release();
         delete m;
         return fail(NGD_E_NOMEM, "ngd_mixture_create: device allocation of %zu bytes failed",
-                    sizeof(float) * kk * (rec_stride(n) + tri(n)));
+                    sizeof(float) * kk * (rec_stride(n) + tri(n) + n));
     }
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) m->device = dev;
@@ -224,7 +226,7 @@ int ngd_mixture_update(ngd_mixture *mix, const float *mean, const float *factor,
         return fail(NGD_E_INVAL, "ngd_mixture_update: arrays must be 4-byte aligned");
     hipError_t e = launch_prepare(mix->n, mix->k, mean, factor, weight, colour,
                                   mix->rec.as<float>(), mix->lfac.as<float>(),
-                                  mix->flag.as<int>(), S(stream));
+                                  mix->msd.as<float>(), mix->flag.as<int>(), S(stream));
     if (e != hipSuccess) return hip_fail(e, "ngd_mixture_update");
     mix->kp = -1;
     ++mix->version;
@@ -297,7 +299,7 @@ int ngd_mixture_update_composed(ngd_mixture *mix, int64_t kp, const float *mean,
     if (e == hipSuccess)
         e = launch_prepare(n, k, mix->abs_mean.as<float>(), mix->abs_factor.as<float>(), weight,
                            colour, mix->rec.as<float>(), mix->lfac.as<float>(),
-                           mix->flag.as<int>(), S(stream), false);
+                           mix->msd.as<float>(), mix->flag.as<int>(), S(stream), false);
     if (e != hipSuccess) return hip_fail(e, who);
     mix->kp = kp;
     ++mix->version;
@@ -317,7 +319,7 @@ int ngd_mixture_destroy(ngd_mixture *mix)
 {
     if (!mix) return NGD_OK;
     (void)hipDeviceSynchronize();
-    DevBuf *bufs[] = {&mix->rec,    &mix->lfac,       &mix->flag,  &mix->comp_parent,
+    DevBuf *bufs[] = {&mix->rec,    &mix->lfac,       &mix->msd,   &mix->flag,  &mix->comp_parent,
                       &mix->comp_u, &mix->comp_mu,    &mix->abs_mean, &mix->abs_factor,
                       &mix->g_abs,  &mix->contrib};
     for (DevBuf *b : bufs) b->release();

@@ -363,6 +363,37 @@ __global__ __launch_bounds__(kThreads) void k_rec_gather(int64_t k, int R,
     }
 }
 
+// Per ordered Gaussian, a box outside which no query is kept by the forward:
+// M = (x - m)^T V^-1 (x - m) >= (x_i - m_i)^2 / V_ii for every coordinate i
+// (V = L L^T; Cauchy-Schwarz), so a query with |x_i - m_i| > r_i,
+// r_i = sqrt(rr V_ii), has M above rr whatever its other coordinates.  rr is
+// the forward's skip threshold in units of M, widened by (1 + 2^-8)^2 for the
+// rounding of its float32 distances; the box [m - r, m + r] is formed in
+// float64 from the mean and the mixture's sqrt(V_ii) and rounded outwards.
+// gbox holds lo_0..lo_{n-1}, hi_0..hi_{n-1} per Gaussian (k x 2n float); one
+// thread per (Gaussian, coordinate), so a wave reads and writes runs of
+// consecutive floats.
+__global__ __launch_bounds__(kThreads) void k_gauss_box(int64_t k, int n, int R, double sr,
+                                                        const int32_t *__restrict__ gperm,
+                                                        const float *__restrict__ rec,
+                                                        const float *__restrict__ msd,
+                                                        float *__restrict__ gbox)
+{
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    if (e >= k * n) return;
+    const int64_t s = e / n;
+    const int i = int(e - s * n);
+    const int64_t g = gperm[s];
+    const double m = double(rec[g * R + i]);
+    const double r = sr * double(msd[g * n + i]);
+    const double lo = m - r, hi = m + r;
+    float flo = float(lo), fhi = float(hi);
+    if (double(flo) > lo) flo = nextafterf(flo, -INFINITY);
+    if (double(fhi) < hi) fhi = nextafterf(fhi, INFINITY);
+    gbox[s * 2 * n + i] = flo;
+    gbox[s * 2 * n + n + i] = fhi;
+}
+
 // ---- the interval test restated as two comparisons ------------------------
 // For a Gaussian with projected mean m and threshold thr = fl(kappa^2 sigma^2)
 // on projection j, Eq. 5 keeps a box [lo, hi] iff
@@ -756,8 +787,22 @@ hipError_t launch_items(int64_t n, const int64_t *off, int per, DevBuf &cnt, Dev
     return scan_counts(cnt, ioff, n, scan_tmp, s);
 }
 
-// The Gaussians in their tile order: records, and the interval test's
-// limits (g_sorted: the projected means are already in that order).
+hipError_t launch_gauss_box(const ngd_cull *c, const ngd_mixture *mix, int64_t k, int R,
+                            hipStream_t s)
+{
+    if (k == 0) return hipSuccess;
+    // the forward drops a pair at exp2(-M log2(e) / 2) < tau 2^-margin
+    const double skip = -std::log2(double(c->params.tau)) + kSkipLog2Margin;
+    const double sr = std::sqrt(2.0 * std::log(2.0) * skip) * (1.0 + 0x1p-8);
+    k_gauss_box<<<nblk(k * c->n, kThreads), kThreads, 0, s>>>(
+        k, c->n, R, sr, c->gperm.as<int32_t>(), mix->rec.as<float>(), mix->msd.as<float>(),
+        c->gbox.as<float>());
+    return hipGetLastError();
+}
+
+// The Gaussians in their tile order: records, the interval test's limits
+// (g_sorted: the projected means are already in that order) and the boxes of
+// the forward's per-wave test.
 hipError_t gauss_side(ngd_cull *c, const ngd_mixture *mix, int64_t k, int R, int P,
                       bool g_sorted, hipStream_t s)
 {
@@ -766,7 +811,9 @@ hipError_t gauss_side(ngd_cull *c, const ngd_mixture *mix, int64_t k, int R, int
     k_gauss_limits<<<dim3(nblk(k, kThreads), unsigned(P)), kThreads, 0, s>>>(
         k, c->gperm.as<int32_t>(), c->g_mr.as<float>(), g_sorted ? c->g_mr_s.as<float>() : nullptr,
         c->g_thr.as<float>(), c->g_ub.as<float>(), c->g_lb.as<float>());
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_gauss_box(c, mix, k, R, s);
 }
 
 template <int N>
@@ -1174,6 +1221,7 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->mrow.ensure(sizeof(float) * kk);
     ok &= c->g_mr_s.ensure(sizeof(float) * P * kk);
     ok &= c->g_ub.ensure(sizeof(float) * P * kk);
+    ok &= c->gbox.ensure(sizeof(float) * 2 * kk * n);
     ok &= c->g_lb.ensure(sizeof(float) * P * kk);
     ok &= c->masks.ensure(sizeof(uint64_t) * std::max<int64_t>(c->nchunks, 1) *
                           std::max<int64_t>(c->tpad, 64));

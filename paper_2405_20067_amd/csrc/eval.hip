@@ -20,6 +20,13 @@
 // certifies G < tau * 2^-20, so a dropped pair changes f by less than that
 // times alpha |c|.  The same test is applied once more before the exp.
 //
+// Ahead of those checks each wave tests its 64 queries' bounding box against
+// a per-Gaussian box built with the cull (lane = candidate, one vector load
+// of 2n floats each): a Gaussian whose box misses the queries' box in some
+// coordinate has every distance above the skip threshold (the marginal over
+// that coordinate alone bounds it), so it is dropped before its record is
+// read, and only the survivors go through the staged evaluation.
+//
 // Dense kernel: the plain direct sum over all Gaussians, no skipping.
 #include "eval_common.hpp"
 #include "ngd_internal.hpp"
@@ -104,11 +111,12 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_dense_split(
 // OUT = false: only the keep/skip flags are written (the backward pass needs
 // them when no forward ran on this cull).  COUNT (with OUT = false): the
 // flags are written and the stage counters of every wave are added to
-// stats[0..4] = (pairs examined, examined again (no matrix filter here),
-// passed check 1, passed check 2, kept).
+// stats[0..4] = (pairs examined, passed the box test, passed check 1, passed
+// check 2, kept).
 template <int N, bool OUT, bool COUNT = false>
 __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
-    int64_t q, int tile, const float *__restrict__ grec, const float *__restrict__ qs,
+    int64_t q, int tile, const float *__restrict__ grec, const float *__restrict__ gbox,
+    const float *__restrict__ qs,
     const int64_t *__restrict__ tile_off, const int32_t *__restrict__ cand,
     const int32_t *__restrict__ perm, const int32_t *__restrict__ item_tile,
     const int64_t *__restrict__ item_off, float skip, float *__restrict__ out,
@@ -132,51 +140,88 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
     for (int a = 0; a < N; ++a) x[a] = valid ? qs[a * q + p] : 0.0f;
     float f0 = 0.0f, f1 = 0.0f, f2 = 0.0f;
 
-    // Candidate indices are read 64 at a time with one vector load; each
-    // record is fetched with wave-uniform loads one candidate ahead into one
-    // of two register blocks.  Uniform loads may complete out of order, so
-    // the wait for the current block is placed before the next block's load
-    // is issued: the wait then never covers the load still in flight.
+    // the wave's query box (empty, lo > hi, for a wave without queries),
+    // broadcast into vector registers: the scalar ones hold the records
+    float qlo[N], qhi[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        qlo[a] = from_orderable(uint32_t(
+            __shfl(int(wave_umin_dpp(orderable(valid ? x[a] : INFINITY))), kWave - 1, kWave)));
+        qhi[a] = from_orderable(uint32_t(
+            __shfl(int(wave_umax_dpp(orderable(valid ? x[a] : -INFINITY))), kWave - 1, kWave)));
+    }
+
+    // Candidate indices are read 64 at a time with one vector load, and each
+    // lane tests its candidate's box.  The survivors' records are fetched
+    // with wave-uniform loads one survivor ahead into one of two register
+    // blocks.  Uniform loads may complete out of order, so the wait for the
+    // current block is placed before the next block's load is issued: the
+    // wait then never covers the load still in flight.
     // keep/skip flag of each (candidate entry, 64-query group), one byte each
     const int ngroups = (tile + kWave - 1) / kWave;
     const int grp = s / kWave;
     float bufA[Lay::PF], bufB[Lay::PF];
     uint32_t st[3] = {0u, 0u, 0u};
+    uint32_t boxed = 0;
     for (int64_t ch = e0; ch < e1; ch += kWave) {
         const int n = int((e1 - ch < kWave) ? e1 - ch : kWave);
         const int lane = lane_id();
         const int vidx = (lane < n) ? cand[ch + lane] : 0;
+        bool near = false;
+        if (lane < n) {
+            const float *b = gbox + int64_t(vidx) * (2 * N);
+            float bl[2 * N];
+#pragma unroll
+            for (int e = 0; e < 2 * N; ++e) bl[e] = b[e];
+            bool apart = false;
+#pragma unroll
+            for (int a = 0; a < N; ++a) apart |= (qlo[a] > bl[N + a]) | (qhi[a] < bl[a]);
+            near = !apart;
+        }
+        uint64_t live = ballot(near);
+        if constexpr (COUNT) boxed += uint32_t(__builtin_popcountll(live));
         uint32_t kept = 0;
-        int64_t ia = __builtin_amdgcn_readlane(vidx, 0);
-        load_block<N>(bufA, grec + ia * Lay::R);
-        for (int j = 0; j < n; j += 2) {
-            __builtin_amdgcn_s_waitcnt(kWaitScalar);
-            int64_t ib = 0;
-            if (j + 1 < n) {
-                ib = __builtin_amdgcn_readlane(vidx, j + 1);
-                load_block<N>(bufB, grec + ib * Lay::R);
+        if (live != 0) {
+            int ja = __builtin_ctzll(live);
+            live &= live - 1;
+            int64_t ia = __builtin_amdgcn_readlane(vidx, ja);
+            load_block<N>(bufA, grec + ia * Lay::R);
+            for (;;) {
+                __builtin_amdgcn_s_waitcnt(kWaitScalar);
+                int jb = -1;
+                int64_t ib = 0;
+                if (live != 0) {
+                    jb = __builtin_ctzll(live);
+                    live &= live - 1;
+                    ib = __builtin_amdgcn_readlane(vidx, jb);
+                    load_block<N>(bufB, grec + ib * Lay::R);
+                }
+                if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
+                                                   f1, f2, st))
+                    kept = (lane == ja) ? 1u : kept;
+                if (jb < 0) break;
+                __builtin_amdgcn_s_waitcnt(kWaitScalar);
+                ja = -1;
+                if (live != 0) {
+                    ja = __builtin_ctzll(live);
+                    live &= live - 1;
+                    ia = __builtin_amdgcn_readlane(vidx, ja);
+                    load_block<N>(bufA, grec + ia * Lay::R);
+                }
+                if (eval_pair<N, true, OUT, COUNT>(bufB, grec + ib * Lay::R, x, valid, skip, f0,
+                                                   f1, f2, st))
+                    kept = (lane == jb) ? 1u : kept;
+                if (ja < 0) break;
             }
-            if (eval_pair<N, true, OUT, COUNT>(bufA, grec + ia * Lay::R, x, valid, skip, f0,
-                                               f1, f2, st))
-                kept = (lane == j) ? 1u : kept;
-            if (j + 1 >= n) break;
-            __builtin_amdgcn_s_waitcnt(kWaitScalar);
-            if (j + 2 < n) {
-                ia = __builtin_amdgcn_readlane(vidx, j + 2);
-                load_block<N>(bufA, grec + ia * Lay::R);
-            }
-            if (eval_pair<N, true, OUT, COUNT>(bufB, grec + ib * Lay::R, x, valid, skip, f0,
-                                               f1, f2, st))
-                kept = (lane == j + 1) ? 1u : kept;
         }
         if (lane < n && grp < ngroups) act[(ch + lane) * ngroups + grp] = uint8_t(kept);
     }
     if constexpr (COUNT) {
         if (lane_id() == 0 && grp < ngroups) {
-            // (examined, not skipped by a matrix filter -- there is none here,
-            // passed check 1, passed check 2, kept)
+            // (examined, passed the box test, passed check 1, passed check 2,
+            // kept)
             atomicAdd(&stats[0], static_cast<unsigned long long>(e1 - e0));
-            atomicAdd(&stats[1], static_cast<unsigned long long>(e1 - e0));
+            atomicAdd(&stats[1], static_cast<unsigned long long>(boxed));
             atomicAdd(&stats[2], static_cast<unsigned long long>(st[0]));
             atomicAdd(&stats[3], static_cast<unsigned long long>(st[1]));
             atomicAdd(&stats[4], static_cast<unsigned long long>(st[2]));
@@ -253,12 +298,14 @@ hipError_t culled_n(const ngd_mixture *mix, const ngd_cull *c, float *out, hipSt
     if (c->nitems > 0) {
         if (out)
             k_eval_items<N, true><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
-                c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
+                c->q, tile, c->grec.as<float>(), c->gbox.as<float>(), c->qs.as<float>(),
+                c->tile_off.as<int64_t>(),
                 c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
                 c->item_off.as<int64_t>(), skip, out, c->fpart.as<float>(), act);
         else
             k_eval_items<N, false><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
-                c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
+                c->q, tile, c->grec.as<float>(), c->gbox.as<float>(), c->qs.as<float>(),
+                c->tile_off.as<int64_t>(),
                 c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
                 c->item_off.as<int64_t>(), skip, nullptr, c->fpart.as<float>(), act);
     }
@@ -276,7 +323,8 @@ hipError_t stats_n(const ngd_cull *c, unsigned long long *stats, hipStream_t s)
     const float skip = float(-std::log2(double(c->params.tau)) + kSkipLog2Margin);
     if (c->nitems > 0)
         k_eval_items<N, false, true><<<dim3(unsigned(c->nitems), gy), per, 0, s>>>(
-            c->q, tile, c->grec.as<float>(), c->qs.as<float>(), c->tile_off.as<int64_t>(),
+            c->q, tile, c->grec.as<float>(), c->gbox.as<float>(), c->qs.as<float>(),
+            c->tile_off.as<int64_t>(),
             c->cand.as<int32_t>(), c->perm.as<int32_t>(), c->item_tile.as<int32_t>(),
             c->item_off.as<int64_t>(), skip, nullptr, c->fpart.as<float>(), c->act.as<uint8_t>(),
             stats);

@@ -113,6 +113,7 @@ struct ngd_mixture {
     int device = 0;
     ngd::DevBuf rec;     // k x rec_stride(n) float
     ngd::DevBuf lfac;    // k x tri(n) float: copy of L for the cull
+    ngd::DevBuf msd;     // k x n float: sqrt(V_ii), V = L L^T, rounded up
     ngd::DevBuf flag;    // int: bit 1 a bad factor or parameter, bit 2 a bad parent index
     // parent-child composition (ngd_mixture_update_composed): kp parents,
     // then k - kp children; kp < 0 when the last update was a plain one
@@ -163,6 +164,8 @@ struct ngd_cull {
     ngd::DevBuf grec;          // k x rec_stride float, sorted Gaussians
     ngd::DevBuf g_mr_s;             // n_proj x k float, sorted Gaussians
     ngd::DevBuf g_ub, g_lb;         // n_proj x k float, sorted: the interval test's limits
+    ngd::DevBuf gbox;               // k x 2n float, sorted: per coordinate, the range
+                                    // outside which the forward keeps no query
     ngd::DevBuf masks;         // nchunks x tpad uint64
     ngd::DevBuf seg_cnt;       // nseg x ntiles int32 (counts, then prefixes)
     ngd::DevBuf tile_cnt;      // ntiles int32
@@ -218,7 +221,8 @@ namespace ngd {
 // kernel ahead of it has already cleared it and may have set bit 2).
 hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *factor,
                           const float *weight, const float *colour, float *rec,
-                          float *lfac, int *flag, hipStream_t s, bool clear_flag = true);
+                          float *lfac, float *msd, int *flag, hipStream_t s,
+                          bool clear_flag = true);
 hipError_t launch_clear_flag(int *flag, hipStream_t s);
 // compose.hip: absolute parameters of parents and children (Eq. 6-7), and
 // the chain rule of the composition in the backward.

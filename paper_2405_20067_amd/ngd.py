@@ -320,8 +320,8 @@ def eval_prepare(mix: Mixture, cull: Cull, queries, precision=FP32, stream=None)
 def eval_stats(mix: Mixture, cull: Cull, queries, precision=FP32, stream=None):
     """Work counters of the culled forward of `precision`: dict(examined,
     filtered, pass1, pass2, kept), counted in (64-query group, candidate)
-    pairs; `filtered` are those the matrix-core filter did not skip (all
-    examined ones with FP32)."""
+    pairs; `filtered` are those the first filter did not skip (the
+    matrix-core one with BF16_MFMA, the per-coordinate box test with FP32)."""
     q = queries.numel() // mix.n
     counts = (ctypes.c_int64 * 5)()
     _check(lib().ngd_eval_stats(mix.handle, cull.handle, _ptr(queries, "queries", q * mix.n),

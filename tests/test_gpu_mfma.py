@@ -122,7 +122,8 @@ def test_mfma_filter_work_and_kept_pairs(torch_cuda):
     mix, x, m, xd, c = _setup(cfg)
     sf = ngd.eval_stats(m, c, xd, precision=ngd.FP32)
     sm = ngd.eval_stats(m, c, xd, precision=ngd.BF16_MFMA)
-    assert sf["examined"] == sm["examined"] and sf["filtered"] == sf["examined"]
+    assert sf["examined"] == sm["examined"]
+    assert sf["pass1"] <= sf["filtered"] <= sf["examined"], sf
     assert sm["filtered"] <= 0.5 * sm["examined"], sm
     assert sm["kept"] <= sm["filtered"]
     assert abs(sm["kept"] - sf["kept"]) <= 1e-3 * sf["kept"] + 2, (sm, sf)
