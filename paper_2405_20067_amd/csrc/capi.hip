@@ -199,15 +199,13 @@ int ngd_mixture_create(int n, int64_t k, ngd_mixture **out)
     m->k = k;
     const size_t kk = size_t(k > 0 ? k : 1);
     if (!m->rec.ensure(sizeof(float) * kk * rec_stride(n)) ||
-        !m->lfac.ensure(sizeof(float) * kk * tri(n)) ||
-        !m->msd.ensure(sizeof(float) * kk * n) || !m->flag.ensure(sizeof(int))) {
+        !m->lfac.ensure(sizeof(float) * kk * tri(n)) || !m->flag.ensure(sizeof(int))) {
         m->rec.release();
         m->lfac.release();
-        m->msd.release();
         m->flag.release();
         delete m;
         return fail(NGD_E_NOMEM, "ngd_mixture_create: device allocation of %zu bytes failed",
-                    sizeof(float) * kk * (rec_stride(n) + tri(n) + n));
+                    sizeof(float) * kk * (rec_stride(n) + tri(n)));
     }
     int dev = 0;
     if (hipGetDevice(&dev) == hipSuccess) m->device = dev;
@@ -226,7 +224,7 @@ int ngd_mixture_update(ngd_mixture *mix, const float *mean, const float *factor,
         return fail(NGD_E_INVAL, "ngd_mixture_update: arrays must be 4-byte aligned");
     hipError_t e = launch_prepare(mix->n, mix->k, mean, factor, weight, colour,
                                   mix->rec.as<float>(), mix->lfac.as<float>(),
-                                  mix->msd.as<float>(), mix->flag.as<int>(), S(stream));
+                                  mix->flag.as<int>(), S(stream));
     if (e != hipSuccess) return hip_fail(e, "ngd_mixture_update");
     mix->kp = -1;
     ++mix->version;
@@ -299,7 +297,7 @@ int ngd_mixture_update_composed(ngd_mixture *mix, int64_t kp, const float *mean,
     if (e == hipSuccess)
         e = launch_prepare(n, k, mix->abs_mean.as<float>(), mix->abs_factor.as<float>(), weight,
                            colour, mix->rec.as<float>(), mix->lfac.as<float>(),
-                           mix->msd.as<float>(), mix->flag.as<int>(), S(stream), false);
+                           mix->flag.as<int>(), S(stream), false);
     if (e != hipSuccess) return hip_fail(e, who);
     mix->kp = kp;
     ++mix->version;
@@ -319,7 +317,7 @@ int ngd_mixture_destroy(ngd_mixture *mix)
 {
     if (!mix) return NGD_OK;
     (void)hipDeviceSynchronize();
-    DevBuf *bufs[] = {&mix->rec,    &mix->lfac,       &mix->msd,   &mix->flag,  &mix->comp_parent,
+    DevBuf *bufs[] = {&mix->rec,    &mix->lfac,       &mix->flag,  &mix->comp_parent,
                       &mix->comp_u, &mix->comp_mu,    &mix->abs_mean, &mix->abs_factor,
                       &mix->g_abs,  &mix->contrib};
     for (DevBuf *b : bufs) b->release();
@@ -355,8 +353,9 @@ static void cull_release(ngd_cull *c)
     if (c->side) (void)hipStreamDestroy(c->side);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_done) (void)hipEventDestroy(c->ev_done);
     c->side = nullptr;
-    c->ev_fork = c->ev_join = nullptr;
+    c->ev_fork = c->ev_join = c->ev_done = nullptr;
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     c->stats_host = nullptr;
 }

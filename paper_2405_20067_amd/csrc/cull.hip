@@ -34,15 +34,28 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Per Gaussian: its projected means and the interval test's squared
+// half-widths (Eq. 3-4), and the box of the forward's per-wave test.
+//
+// The box: M = (x - m)^T V^-1 (x - m) >= (x_i - m_i)^2 / V_ii for every
+// coordinate i (V = L L^T; Cauchy-Schwarz), so a query with
+// |x_i - m_i| > sr sqrt(V_ii) has M above sr^2 whatever its other
+// coordinates.  sr^2 is the forward's skip threshold in units of M, widened
+// by (1 + 2^-8)^2 for the rounding of its float32 distances.  V_ii =
+// |row i of L|^2 and [m - r, m + r] are formed in float64 and the box is
+// rounded outwards; box holds lo_0..lo_{n-1}, hi_0..hi_{n-1} per Gaussian
+// (stride BS floats), in the caller's order (gathered with the records).
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_gauss_proj(int64_t k, int P,
                                                          const float *__restrict__ rec, int R,
                                                          const float *__restrict__ lfac,
                                                          const float *__restrict__ proj,
                                                          float kappa2, float *__restrict__ g_mr,
-                                                         float *__restrict__ g_thr)
+                                                         float *__restrict__ g_thr, double sr,
+                                                         float *__restrict__ box)
 {
     constexpr int T = N * (N + 1) / 2;
+    constexpr int BS = (2 * N + 3) / 4 * 4;
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= k) return;
     float m[N];
@@ -51,6 +64,26 @@ __global__ __launch_bounds__(kThreads) void k_gauss_proj(int64_t k, int P,
     for (int a = 0; a < N; ++a) m[a] = rec[i * R + a];
 #pragma unroll
     for (int e = 0; e < T; ++e) L[e] = lfac[i * T + e];
+    float bx[BS];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) v = fma(L[a * (a + 1) / 2 + b], L[a * (a + 1) / 2 + b], v);
+        const double r = sr * sqrt(v);
+        const double lo = double(m[a]) - r, hi = double(m[a]) + r;
+        float flo = float(lo), fhi = float(hi);
+        if (double(flo) > lo) flo = nextafterf(flo, -INFINITY);
+        if (double(fhi) < hi) fhi = nextafterf(fhi, INFINITY);
+        bx[a] = flo;
+        bx[N + a] = fhi;
+    }
+#pragma unroll
+    for (int e = 2 * N; e < BS; ++e) bx[e] = 0.0f;
+    float4 *bo = reinterpret_cast<float4 *>(box + i * BS);
+#pragma unroll
+    for (int e = 0; e < BS / 4; ++e)
+        bo[e] = make_float4(bx[4 * e], bx[4 * e + 1], bx[4 * e + 2], bx[4 * e + 3]);
     for (int j = 0; j < P; ++j) {
         const float *r = proj + j * N;
         float acc = 0.0f;
@@ -344,54 +377,35 @@ __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P
     }
 }
 
-// Records of the Gaussians in their tile order: a block moves 64 records of
-// R floats as float4s, consecutive threads on consecutive float4s.
-__global__ __launch_bounds__(kThreads) void k_rec_gather(int64_t k, int R,
+// Records and forward boxes of the Gaussians in their tile order: a block
+// moves 64 records of R floats and 64 boxes of B floats as float4s,
+// consecutive threads on consecutive float4s.
+__global__ __launch_bounds__(kThreads) void k_rec_gather(int64_t k, int R, int B,
                                                          const int32_t *__restrict__ gperm,
                                                          const float *__restrict__ rec,
-                                                         float *__restrict__ grec)
+                                                         const float *__restrict__ box,
+                                                         float *__restrict__ grec,
+                                                         float *__restrict__ gbox)
 {
-    const int R4 = R / 4;
+    const int R4 = R / 4, B4 = B / 4;
     const int64_t s0 = int64_t(blockIdx.x) * kWave;
     const int cnt = int(k - s0 < kWave ? k - s0 : kWave);
-    const float4 *src = reinterpret_cast<const float4 *>(rec);
-    float4 *dst = reinterpret_cast<float4 *>(grec) + s0 * R4;
-    for (int e = threadIdx.x; e < cnt * R4; e += kThreads) {
-        const int sl = e / R4;
-        const int f = e - sl * R4;
-        dst[e] = src[int64_t(gperm[s0 + sl]) * R4 + f];
+    {
+        const float4 *src = reinterpret_cast<const float4 *>(rec);
+        float4 *dst = reinterpret_cast<float4 *>(grec) + s0 * R4;
+        for (int e = threadIdx.x; e < cnt * R4; e += kThreads) {
+            const int sl = e / R4;
+            const int f = e - sl * R4;
+            dst[e] = src[int64_t(gperm[s0 + sl]) * R4 + f];
+        }
     }
-}
-
-// Per ordered Gaussian, a box outside which no query is kept by the forward:
-// M = (x - m)^T V^-1 (x - m) >= (x_i - m_i)^2 / V_ii for every coordinate i
-// (V = L L^T; Cauchy-Schwarz), so a query with |x_i - m_i| > r_i,
-// r_i = sqrt(rr V_ii), has M above rr whatever its other coordinates.  rr is
-// the forward's skip threshold in units of M, widened by (1 + 2^-8)^2 for the
-// rounding of its float32 distances; the box [m - r, m + r] is formed in
-// float64 from the mean and the mixture's sqrt(V_ii) and rounded outwards.
-// gbox holds lo_0..lo_{n-1}, hi_0..hi_{n-1} per Gaussian (k x 2n float); one
-// thread per (Gaussian, coordinate), so a wave reads and writes runs of
-// consecutive floats.
-__global__ __launch_bounds__(kThreads) void k_gauss_box(int64_t k, int n, int R, double sr,
-                                                        const int32_t *__restrict__ gperm,
-                                                        const float *__restrict__ rec,
-                                                        const float *__restrict__ msd,
-                                                        float *__restrict__ gbox)
-{
-    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (e >= k * n) return;
-    const int64_t s = e / n;
-    const int i = int(e - s * n);
-    const int64_t g = gperm[s];
-    const double m = double(rec[g * R + i]);
-    const double r = sr * double(msd[g * n + i]);
-    const double lo = m - r, hi = m + r;
-    float flo = float(lo), fhi = float(hi);
-    if (double(flo) > lo) flo = nextafterf(flo, -INFINITY);
-    if (double(fhi) < hi) fhi = nextafterf(fhi, INFINITY);
-    gbox[s * 2 * n + i] = flo;
-    gbox[s * 2 * n + n + i] = fhi;
+    const float4 *src = reinterpret_cast<const float4 *>(box);
+    float4 *dst = reinterpret_cast<float4 *>(gbox) + s0 * B4;
+    for (int e = threadIdx.x; e < cnt * B4; e += kThreads) {
+        const int sl = e / B4;
+        const int f = e - sl * B4;
+        dst[e] = src[int64_t(gperm[s0 + sl]) * B4 + f];
+    }
 }
 
 // ---- the interval test restated as two comparisons ------------------------
@@ -787,37 +801,29 @@ hipError_t launch_items(int64_t n, const int64_t *off, int per, DevBuf &cnt, Dev
     return scan_counts(cnt, ioff, n, scan_tmp, s);
 }
 
-hipError_t launch_gauss_box(const ngd_cull *c, const ngd_mixture *mix, int64_t k, int R,
-                            hipStream_t s)
+// The Gaussians in their tile order, what the interval test needs: its
+// limits (g_sorted: the projected means are already in that order).
+hipError_t gauss_limits(ngd_cull *c, int64_t k, int P, bool g_sorted, hipStream_t s)
 {
-    if (k == 0) return hipSuccess;
-    // the forward drops a pair at exp2(-M log2(e) / 2) < tau 2^-margin
-    const double skip = -std::log2(double(c->params.tau)) + kSkipLog2Margin;
-    const double sr = std::sqrt(2.0 * std::log(2.0) * skip) * (1.0 + 0x1p-8);
-    k_gauss_box<<<nblk(k * c->n, kThreads), kThreads, 0, s>>>(
-        k, c->n, R, sr, c->gperm.as<int32_t>(), mix->rec.as<float>(), mix->msd.as<float>(),
-        c->gbox.as<float>());
-    return hipGetLastError();
-}
-
-// The Gaussians in their tile order: records, the interval test's limits
-// (g_sorted: the projected means are already in that order) and the boxes of
-// the forward's per-wave test.
-hipError_t gauss_side(ngd_cull *c, const ngd_mixture *mix, int64_t k, int R, int P,
-                      bool g_sorted, hipStream_t s)
-{
-    k_rec_gather<<<nblk(k, kWave), kThreads, 0, s>>>(k, R, c->gperm.as<int32_t>(),
-                                                      mix->rec.as<float>(), c->grec.as<float>());
     k_gauss_limits<<<dim3(nblk(k, kThreads), unsigned(P)), kThreads, 0, s>>>(
         k, c->gperm.as<int32_t>(), c->g_mr.as<float>(), g_sorted ? c->g_mr_s.as<float>() : nullptr,
         c->g_thr.as<float>(), c->g_ub.as<float>(), c->g_lb.as<float>());
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return launch_gauss_box(c, mix, k, R, s);
+    return hipGetLastError();
+}
+
+// The Gaussians in their tile order, what the forward needs: records and the
+// boxes of its per-wave test.
+hipError_t gauss_records(ngd_cull *c, const ngd_mixture *mix, int64_t k, int R, hipStream_t s)
+{
+    k_rec_gather<<<nblk(k, kWave), kThreads, 0, s>>>(
+        k, R, box_stride(c->n), c->gperm.as<int32_t>(), mix->rec.as<float>(),
+        c->gbox_u.as<float>(), c->grec.as<float>(), c->gbox.as<float>());
+    return hipGetLastError();
 }
 
 template <int N>
-hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hipStream_t s)
+hipError_t front_body_n(ngd_cull *c, const ngd_mixture *mix, const float *queries,
+                        hipStream_t s, bool &side_open)
 {
     const int P = c->params.n_proj;
     const int64_t q = c->q, k = c->k;
@@ -835,9 +841,13 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         forked = true;
     }
     if (k > 0) {
+        // the forward drops a pair at exp2(-M log2(e) / 2) < tau 2^-margin:
+        // its boxes' half-widths are sr sqrt(V_ii)
+        const double skip = -std::log2(double(c->params.tau)) + kSkipLog2Margin;
+        const double sr = std::sqrt(2.0 * std::log(2.0) * skip) * (1.0 + 0x1p-8);
         k_gauss_proj<N><<<nblk(k, kThreads), kThreads, 0, forked ? c->side : s>>>(
             k, P, mix->rec.as<float>(), R, mix->lfac.as<float>(), c->proj.as<float>(), c->kappa2,
-            c->g_mr.as<float>(), c->g_thr.as<float>());
+            c->g_mr.as<float>(), c->g_thr.as<float>(), sr, c->gbox_u.as<float>());
     }
     const int64_t nparts = (q + kThreads - 1) / kThreads;
     // With the k-d tiling of the queries the projection kernel's block
@@ -906,25 +916,31 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
             if (!rq.done) e = kd_step(rq);
             if (e == hipSuccess && !rg.done) e = kd_step(rg);
         }
-        // the Gaussians' side goes on while the queries' order finishes,
-        // and with it the matrix-core forward's per-Gaussian coefficients
-        // (off the critical path: the queries' order takes longer)
+        // the Gaussians' side goes on while the queries' order finishes:
+        // first the interval test's limits (the join point), then what only
+        // the forward reads -- the ordered records, the boxes and the
+        // matrix-core forward's per-Gaussian coefficients -- which the main
+        // stream waits for only at the end of the front half
         if (forked && e == hipSuccess) {
-            e = gauss_side(c, mix, k, R, P, true, c->side);
+            e = gauss_limits(c, k, P, true, c->side);
             gauss_done = true;
-            if (e == hipSuccess) e = launch_mfma_coef(N, c, c->side);
-            c->coef_next = e == hipSuccess;
         }
         if (forked) {
             const hipError_t ej = hipEventRecord(c->ev_join, c->side);
             if (e == hipSuccess) e = ej;
+            if (e == hipSuccess) {
+                side_open = true;
+                e = gauss_records(c, mix, k, R, c->side);
+                if (e == hipSuccess) e = launch_mfma_coef(N, c, c->side);
+                c->coef_next = e == hipSuccess;
+            }
             if (e != hipSuccess) {
+                (void)hipEventRecord(c->ev_join, c->side);
                 (void)hipStreamWaitEvent(s, c->ev_join, 0);
                 return e;
             }
         }
         if (e != hipSuccess) return e;
-        if (forked && (e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess) return e;
     }
     // Morton: queries: keys, sort -> perm
     if (c->params.tiling == 1 && q > 0) {
@@ -970,8 +986,12 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
         k_super_bounds<<<nblk(nsup * 2 * PP, kThreads), kThreads, 0, s>>>(
             c->ntiles, PP, c->tbnd.as<float>(), c->sbnd.as<float>());
     }
-    if (k > 0 && !gauss_done && (e = gauss_side(c, mix, k, R, P, g_sorted, s)) != hipSuccess)
-        return e;
+    // the tiles' bounds above overlap the second stream's last kernels
+    if (side_open && (e = hipStreamWaitEvent(s, c->ev_join, 0)) != hipSuccess) return e;
+    if (k > 0 && !gauss_done) {
+        if ((e = gauss_limits(c, k, P, g_sorted, s)) != hipSuccess) return e;
+        if ((e = gauss_records(c, mix, k, R, s)) != hipSuccess) return e;
+    }
     k_zero_u64<<<1, 64, 0, s>>>(reinterpret_cast<unsigned long long *>(c->stats.p), 2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (k == 0 || c->ntiles == 0) {
@@ -1016,6 +1036,21 @@ hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hi
     e = scan_counts(c->tile_cnt, c->tile_off, c->ntiles, c->scan_tmp, s);
     if (e != hipSuccess) return e;
     return launch_items(c->ntiles, c->tile_off.as<int64_t>(), kItemCands, c->item_cnt, c->item_off, c->scan_tmp, s);
+}
+
+template <int N>
+hipError_t front_n(ngd_cull *c, const ngd_mixture *mix, const float *queries, hipStream_t s)
+{
+    bool side_open = false;
+    hipError_t e = front_body_n<N>(c, mix, queries, s, side_open);
+    if (side_open) {
+        // the second stream's work past the interval test's join point ends
+        // before the front half does, whatever happened in between
+        hipError_t ej = hipEventRecord(c->ev_done, c->side);
+        if (ej == hipSuccess) ej = hipStreamWaitEvent(s, c->ev_done, 0);
+        if (e == hipSuccess) e = ej;
+    }
+    return e;
 }
 
 }  // namespace
@@ -1221,7 +1256,8 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->mrow.ensure(sizeof(float) * kk);
     ok &= c->g_mr_s.ensure(sizeof(float) * P * kk);
     ok &= c->g_ub.ensure(sizeof(float) * P * kk);
-    ok &= c->gbox.ensure(sizeof(float) * 2 * kk * n);
+    ok &= c->gbox.ensure(sizeof(float) * kk * box_stride(int(n)));
+    ok &= c->gbox_u.ensure(sizeof(float) * kk * box_stride(int(n)));
     ok &= c->g_lb.ensure(sizeof(float) * P * kk);
     ok &= c->masks.ensure(sizeof(uint64_t) * std::max<int64_t>(c->nchunks, 1) *
                           std::max<int64_t>(c->tpad, 64));
@@ -1249,6 +1285,8 @@ bool cull_reserve_front(ngd_cull *c)
             ok = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
         if (ok && !c->ev_join)
             ok = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
+        if (ok && !c->ev_done)
+            ok = hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming) == hipSuccess;
     }
     return ok;
 }

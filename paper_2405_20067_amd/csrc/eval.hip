@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
         const int vidx = (lane < n) ? cand[ch + lane] : 0;
         bool near = false;
         if (lane < n) {
-            const float *b = gbox + int64_t(vidx) * (2 * N);
+            const float *b = gbox + int64_t(vidx) * ((2 * N + 3) / 4 * 4);
             float bl[2 * N];
 #pragma unroll
             for (int e = 0; e < 2 * N; ++e) bl[e] = b[e];

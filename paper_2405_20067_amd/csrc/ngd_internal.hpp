@@ -33,6 +33,8 @@ inline int tri(int n) { return n * (n + 1) / 2; }
 // floats: m (n) | S' = sqrt(kHalfLog2e) L^-1 packed lower by rows (tri) |
 // alpha*c (3) | alpha (1) | c (3) | padding to a multiple of 4.
 inline int rec_stride(int n) { return (n + tri(n) + 7 + 3) / 4 * 4; }
+// floats per Gaussian of the forward's box (n lows, n highs, padding)
+inline int box_stride(int n) { return (2 * n + 3) / 4 * 4; }
 
 // Device allocation through the configurable allocator; reports the
 // matching release function (NULL: hipFree) and its context.
@@ -113,7 +115,6 @@ struct ngd_mixture {
     int device = 0;
     ngd::DevBuf rec;     // k x rec_stride(n) float
     ngd::DevBuf lfac;    // k x tri(n) float: copy of L for the cull
-    ngd::DevBuf msd;     // k x n float: sqrt(V_ii), V = L L^T, rounded up
     ngd::DevBuf flag;    // int: bit 1 a bad factor or parameter, bit 2 a bad parent index
     // parent-child composition (ngd_mixture_update_composed): kp parents,
     // then k - kp children; kp < 0 when the last update was a plain one
@@ -164,8 +165,9 @@ struct ngd_cull {
     ngd::DevBuf grec;          // k x rec_stride float, sorted Gaussians
     ngd::DevBuf g_mr_s;             // n_proj x k float, sorted Gaussians
     ngd::DevBuf g_ub, g_lb;         // n_proj x k float, sorted: the interval test's limits
-    ngd::DevBuf gbox;               // k x 2n float, sorted: per coordinate, the range
-                                    // outside which the forward keeps no query
+    ngd::DevBuf gbox_u, gbox;       // k x box_stride(n) float, caller's order and
+                                    // sorted: per coordinate, the range outside which
+                                    // the forward keeps no query
     ngd::DevBuf masks;         // nchunks x tpad uint64
     ngd::DevBuf seg_cnt;       // nseg x ntiles int32 (counts, then prefixes)
     ngd::DevBuf tile_cnt;      // ntiles int32
@@ -201,7 +203,9 @@ struct ngd_cull {
     ngd::KdWork kd_work;       // query k-d work
     ngd::KdWork kd_work_g;     // Gaussian k-d work (runs concurrently, on `side`)
     hipStream_t side = nullptr;          // default-priority, non-blocking
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    // fork; the interval test's join (the Gaussians' limits); the end of the
+    // second stream's work (the forward's per-Gaussian data)
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr;
     // matrix-core forward: quadratic coefficients of the ordered Gaussians
     ngd::DevBuf mrec;          // k x mfma_rec_bytes(n): bf16 hi / lo pairs
     ngd::DevBuf mrow;          // k float: bound factor R'
@@ -221,8 +225,7 @@ namespace ngd {
 // kernel ahead of it has already cleared it and may have set bit 2).
 hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *factor,
                           const float *weight, const float *colour, float *rec,
-                          float *lfac, float *msd, int *flag, hipStream_t s,
-                          bool clear_flag = true);
+                          float *lfac, int *flag, hipStream_t s, bool clear_flag = true);
 hipError_t launch_clear_flag(int *flag, hipStream_t s);
 // compose.hip: absolute parameters of parents and children (Eq. 6-7), and
 // the chain rule of the composition in the backward.

@@ -1,8 +1,6 @@
 // Per-Gaussian preparation in float64 (Sec. 3.1, Eq. 2): the precision
 // factor S = L^-1 by triangular inversion, and the records the evaluation
-// kernels read; beside them each coordinate's standard deviation
-// sqrt(V_ii) = |row i of L| (rounded up to float32), from which the cull
-// forms the boxes of the forward's per-wave test.  One thread per Gaussian; O(n^3) float64 work each, a few
+// kernels read.  One thread per Gaussian; O(n^3) float64 work each, a few
 // microseconds for the whole mixture.
 #include "ngd_internal.hpp"
 
@@ -16,7 +14,6 @@ __global__ __launch_bounds__(256) void k_prepare(int64_t k, const float *__restr
                                                  const float *__restrict__ colour,
                                                  float *__restrict__ rec,
                                                  float *__restrict__ lfac,
-                                                 float *__restrict__ msd,
                                                  int *__restrict__ flag)
 {
     constexpr int T = N * (N + 1) / 2;
@@ -35,16 +32,6 @@ __global__ __launch_bounds__(256) void k_prepare(int64_t k, const float *__restr
     }
 #pragma unroll
     for (int a = 0; a < N; ++a) bad |= (L[a * (a + 1) / 2 + a] == 0.0);
-#pragma unroll
-    for (int a = 0; a < N; ++a) {
-        double v = 0.0;
-#pragma unroll
-        for (int c = 0; c <= a; ++c) v = fma(L[a * (a + 1) / 2 + c], L[a * (a + 1) / 2 + c], v);
-        const double sd = sqrt(v);
-        float f = float(sd);
-        if (double(f) < sd) f = nextafterf(f, INFINITY);
-        msd[i * N + a] = f;
-    }
 
     // S = L^-1, column by column: S_jj = 1 / L_jj,
     // S_ij = -(sum_{k=j}^{i-1} L_ik S_kj) S_ii  for i > j
@@ -91,12 +78,11 @@ __global__ void k_clear_flag(int *flag) { *flag = 0; }
 
 template <int N>
 hipError_t prepare_n(int64_t k, const float *mean, const float *factor, const float *weight,
-                     const float *colour, float *rec, float *lfac, float *msd, int *flag,
-                     hipStream_t s)
+                     const float *colour, float *rec, float *lfac, int *flag, hipStream_t s)
 {
     const int64_t blocks = (k + 255) / 256;
     k_prepare<N><<<dim3(unsigned(blocks)), dim3(256), 0, s>>>(k, mean, factor, weight, colour,
-                                                             rec, lfac, msd, flag);
+                                                             rec, lfac, flag);
     return hipGetLastError();
 }
 
@@ -110,13 +96,13 @@ hipError_t launch_clear_flag(int *flag, hipStream_t s)
 
 hipError_t launch_prepare(int n, int64_t k, const float *mean, const float *factor,
                           const float *weight, const float *colour, float *rec, float *lfac,
-                          float *msd, int *flag, hipStream_t s, bool clear_flag)
+                          int *flag, hipStream_t s, bool clear_flag)
 {
     hipError_t e = clear_flag ? launch_clear_flag(flag, s) : hipSuccess;
     if (e != hipSuccess || k == 0) return e;
     switch (n) {
 #define NGD_CASE(NN) \
-    case NN: return prepare_n<NN>(k, mean, factor, weight, colour, rec, lfac, msd, flag, s);
+    case NN: return prepare_n<NN>(k, mean, factor, weight, colour, rec, lfac, flag, s);
         NGD_CASE(1) NGD_CASE(2) NGD_CASE(3) NGD_CASE(4) NGD_CASE(5) NGD_CASE(6)
         NGD_CASE(7) NGD_CASE(8) NGD_CASE(9) NGD_CASE(10) NGD_CASE(11) NGD_CASE(12)
 #undef NGD_CASE

@@ -364,3 +364,62 @@ def test_mixed_sign_diagonals(torch_cuda, n):
             want_g = np.zeros_like(a, dtype=np.float64)
             want_g[sel] = b
             assert normwise(a, want_g) <= TOL_FP32, (prec, name)
+
+
+@pytest.mark.parametrize("n", [4, 10])
+def test_pairs_at_the_skip_threshold_are_kept(torch_cuda, n):
+    """Pairs just inside the forward's skip threshold must be evaluated.
+    Correlated Gaussians (V_ii well above L_ii^2), far apart; each tile of
+    128 queries (given order) holds 64 queries at a Gaussian's mean, which
+    keep it a candidate, and 64 at its extreme point along one axis,
+    x - m = r V e_i / sqrt(V_ii): Mahalanobis distance r, and the same
+    distance r from the mean in that coordinate alone, in sigma_i.  With
+    r = 6.5 and 6.75, below the threshold sqrt(2 ln(1/tau) + 40 ln 2) = 6.79
+    (tau = 1e-4), the value exp(-r^2 / 2) exceeds what the skip may drop,
+    tau 2^-20, so every precision must return it: a query box or a
+    per-coordinate bound narrower than r sigma_i would lose it."""
+    from paper_2405_20067_amd import ngd
+    rng = np.random.default_rng(90 + n)
+    k, tile, tau = 4, 128, 1e-4
+    r_, c_ = np.tril_indices(n)
+    fac = np.where(r_ == c_, rng.uniform(0.5, 1.5, (k, r_.size)),
+                   rng.uniform(-1.0, 1.0, (k, r_.size)))
+    L = np.zeros((k, n, n))
+    L[:, r_, c_] = fac
+    V = L @ L.transpose(0, 2, 1)
+    assert (np.einsum("kii->ki", V) > 1.5 * np.einsum("kii->ki", L) ** 2).any()
+    mean = np.zeros((k, n))
+    mean[:, 0] = 1000.0 * np.arange(k)
+    xs = []
+    for g in range(k):
+        sd = np.sqrt(np.diag(V[g]))
+        for i in range(n):
+            for sgn in (-1.0, 1.0):
+                for rad in (6.5, 6.75):
+                    centre = mean[g] + 1e-3 * sd * rng.standard_normal((64, n))
+                    edge = mean[g] + sgn * rad * V[g][:, i] / sd[i]
+                    probe = edge + 1e-6 * sd * rng.standard_normal((64, n))
+                    xs += [centre, probe]
+    x = np.ascontiguousarray(np.concatenate(xs), dtype=np.float32)
+    q = x.shape[0]
+    mix = dict(mean=mean.astype(np.float32), factor=fac.astype(np.float32),
+               weight=np.ones(k, np.float32),
+               colour=np.tile(np.float32([0.5, 0.7, 0.9]), (k, 1)))
+    proj = inputs.gen_projections(n, 16, seed=7)
+    m = _mixture(torch_cuda, mix)
+    xd = dev(x)
+    c = ngd.Cull().build(m, xd, proj, _params(tile=tile, tau=tau, tiling=2))
+    exp = c.export()
+    assert np.all(np.diff(exp["tile_off"]) == 1)   # each tile: its own Gaussian only
+    qoff, gidx = per_query_csr(exp, q, tile)
+    want = oracle.eval_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x,
+                             qoff, gidx)
+    probes = np.concatenate([np.arange(t * tile + 64, (t + 1) * tile) for t in range(q // tile)])
+    colour = mix["colour"][0].astype(np.float64)
+    g_val = want[probes] / colour
+    assert g_val.min() > 1.25 * tau * 2.0 ** -20    # above what the skip may drop
+    for prec in (ngd.FP32, ngd.BF16_MFMA):
+        f = host(ngd.eval_mixture(m, c, xd, precision=prec)).astype(np.float64)
+        err = np.abs(f - want)
+        assert np.all(err <= 1e-4 * np.abs(want) + tau * 2.0 ** -20 * colour), (
+            prec, float((err / np.maximum(np.abs(want), 1e-300)).max()))
