@@ -735,13 +735,33 @@ def summarize_traffic(fetch_csv, write_csv, out_prefix):
 
 
 def summarize_trace(stats_csv, top=40):
-    """A markdown table of a rocprofv3 --kernel-trace --stats summary."""
+    """A markdown table of a rocprofv3 --kernel-trace --stats summary; with
+    the per-dispatch trace beside it (`*_kernel_trace.csv`), a second table
+    of each kernel's median over the main workload's dispatches: those of at
+    least 0.4 times the kernel's longest, which leaves out the small
+    hidden-target (K = 4,096) build and forward that the averages include."""
     import csv
     rows = list(csv.DictReader(open(stats_csv)))
     print("| kernel | calls | avg us | total ms | % |\n|---|---|---|---|---|")
     for r in rows[:top]:
         print(f"| `{_short(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.1f} | "
               f"{float(r['TotalDurationNs']) / 1e6:.2f} | {float(r['Percentage']):.1f} |")
+    trace_csv = stats_csv.replace("_kernel_stats.csv", "_kernel_trace.csv")
+    if trace_csv == stats_csv or not os.path.exists(trace_csv):
+        return
+    dur = {}
+    for r in csv.DictReader(open(trace_csv)):
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        dur.setdefault(_short(r["Kernel_Name"]), []).append(d)
+    med = []
+    for name, d in dur.items():
+        big = [v for v in d if v >= 0.4 * max(d)]
+        med.append((float(np.median(big)) * len(big), name, len(big), float(np.median(big))))
+    med.sort(reverse=True)
+    print("\nMain workload (dispatches of at least 0.4 x the kernel's longest):\n")
+    print("| kernel | dispatches | median us |\n|---|---|---|")
+    for _, name, n, m in med[:top]:
+        print(f"| `{name}` | {n} | {m:.1f} |")
 
 
 def summarize_counters(pmc_csv, kernel):
