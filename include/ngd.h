@@ -103,10 +103,12 @@ int ngd_version(void);
 int ngd_cull_params_default(ngd_cull_params *p);
 
 /* Replaces the device allocator used for library-owned workspaces (default
- * hipMalloc / hipFree).  alloc(bytes, ctx) returns a device pointer or NULL;
- * free(ptr, ctx) releases it.  Both NULL restores the default.  Affects
- * allocations made after the call; memory is always released with the
- * allocator that made it. */
+ * hipMalloc / hipFree).  alloc(bytes, ctx) returns a device pointer aligned
+ * to 256 bytes (as hipMalloc's are), or NULL; free(ptr, ctx) releases it.  A
+ * pointer that is not so aligned is released at once and the call that
+ * needed it fails with NGD_E_NOMEM.  Both NULL restores the default.
+ * Affects allocations made after the call; memory is always released with
+ * the allocator that made it. */
 int ngd_set_allocator(void *(*alloc_fn)(size_t bytes, void *ctx),
                       void (*free_fn)(void *ptr, void *ctx), void *ctx);
 

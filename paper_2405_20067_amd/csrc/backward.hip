@@ -26,6 +26,7 @@ namespace ngd {
 namespace {
 
 constexpr int kBwdThreads = 256;
+constexpr int kMaxGroups = 16;   // 64-query groups of the largest tile (1024)
 constexpr int kWavesPerBlock = kBwdThreads / kWave;
 static_assert(kItemTiles <= kWave, "an item's tile list must fit one wave");
 
@@ -239,26 +240,39 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
 #pragma unroll
     for (int e = 0; e < T; ++e) b2[e] = 0.0f;
 
-    // (entry, query group) pairs of this item, 64 per round, lane = pair:
-    // keep the ones the forward kept, then visit them in ascending order
+    // The item's entries, lane = entry (at most kItemTiles <= 64): the
+    // entry's tile and the flags of its query groups, loaded together once
+    // the entry is known; then the kept (entry, group) pairs in ascending
+    // entry order, groups ascending within an entry.
     const int ngroups = (tile + kWave - 1) / kWave;
-    const int64_t npairs = (e1 - e0) * ngroups;
-    bool any = false;
-    for (int64_t base = 0; base < npairs; base += kWave) {
-        const int64_t pi = base + lane;
-        int ent = 0, tl = 0;
-        bool kept = false;
-        if (pi < npairs) {
-            ent = a_ent[e0 + pi / ngroups];
-            kept = act[int64_t(ent) * ngroups + pi % ngroups] != 0;
-            tl = kept ? ent_tile[ent] : 0;
+    const int nent = int(e1 - e0);
+    int tl = 0;
+    uint32_t fl = 0;   // bit g: group g kept
+    if (lane < nent) {
+        const int64_t ent = a_ent[e0 + lane];
+        tl = ent_tile[ent];
+        const uint8_t *af = act + ent * ngroups;
+        if (ngroups == 4) {
+            // one aligned 4-byte load: tiles of 193..256 queries
+            const uint32_t v = *reinterpret_cast<const uint32_t *>(af);
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) fl |= uint32_t(((v >> (8 * gq)) & 0xffu) != 0) << gq;
+        } else {
+            // tiles of at most 1024 queries: at most 16 groups, loaded
+            // together
+#pragma unroll
+            for (int gq = 0; gq < kMaxGroups; ++gq)
+                if (gq < ngroups) fl |= uint32_t(af[gq] != 0) << gq;
         }
-        uint64_t m = ballot(kept);
-        while (m) {
-            const int l = __ffsll(static_cast<unsigned long long>(m)) - 1;
-            m &= m - 1;
+    }
+    bool any = false;
+    for (uint64_t m = ballot(fl != 0); m != 0; m = ballot(fl != 0)) {
+        const int l = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        const uint32_t fb = __builtin_amdgcn_readlane(fl, l);
+        const int gq = __builtin_ctz(fb);
+        if (lane == l) fl = fb & (fb - 1);
+        {
             const int64_t tt = __builtin_amdgcn_readlane(tl, l);
-            const int gq = int((base + l) % ngroups);
             const int sidx = gq * kWave + lane;
             const int64_t p = tt * tile + sidx;
             const bool valid = (sidx < tile) && (p < q);

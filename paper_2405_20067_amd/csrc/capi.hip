@@ -75,6 +75,11 @@ bool DevBuf::ensure(size_t bytes)
     p = dev_alloc(want, &free_fn, &ctx);
     if (!p) return false;
     cap = want;
+    // the kernels read workspaces with 16-byte vector loads
+    if ((reinterpret_cast<uintptr_t>(p) & 255u) != 0) {
+        release();
+        return false;
+    }
     return true;
 }
 

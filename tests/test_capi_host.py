@@ -128,6 +128,30 @@ def test_allocator_failure_is_reported_as_nomem(L):
         assert L.ngd_set_allocator(ngd.ALLOC_FN(), ngd.FREE_FN(), None) == 0
 
 
+def test_allocator_misaligned_memory_is_returned_and_reported(L):
+    """A workspace pointer not aligned to 256 bytes is handed back to the
+    allocator's free at once (never used: the value below is no real
+    allocation) and the call fails with NGD_E_NOMEM."""
+    freed = []
+
+    @ngd.ALLOC_FN
+    def misaligned_alloc(nbytes, ctx):
+        return 0x10010
+
+    @ngd.FREE_FN
+    def record_free(ptr, ctx):
+        freed.append(ptr)
+
+    assert L.ngd_set_allocator(misaligned_alloc, record_free, None) == 0
+    try:
+        h = ctypes.c_void_p()
+        assert L.ngd_mixture_create(4, 100, ctypes.byref(h)) == ngd.E_NOMEM
+        assert h.value is None
+        assert freed and all(f == 0x10010 for f in freed)
+    finally:
+        assert L.ngd_set_allocator(ngd.ALLOC_FN(), ngd.FREE_FN(), None) == 0
+
+
 def test_allocator_must_be_given_in_pairs(L):
     @ngd.ALLOC_FN
     def a(nbytes, ctx):
