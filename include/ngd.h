@@ -186,8 +186,9 @@ int ngd_mixture_destroy(ngd_mixture *mix);
  * (p->tiling), tiles of p->tile consecutive ordered queries with
  * their projected bounds, the (tile, Gaussian) interval test (Eq. 5), the
  * per-tile candidate lists (CSR, ascending) and their transpose.
- * Synchronises once, to read the number of candidates.  q = 0 or k = 0
- * gives an empty structure. */
+ * Synchronises once, to read the number of candidates (the list kernels
+ * are already enqueued then; they complete in stream order).  q = 0 or
+ * k = 0 gives an empty structure. */
 int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
                    const ngd_cull_params *p, const float *proj, void *stream,
                    ngd_cull **inout);

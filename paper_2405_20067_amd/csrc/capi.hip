@@ -359,8 +359,9 @@ static void cull_release(ngd_cull *c)
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
     if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     if (c->ev_done) (void)hipEventDestroy(c->ev_done);
+    if (c->ev_sizes) (void)hipEventDestroy(c->ev_sizes);
     c->side = nullptr;
-    c->ev_fork = c->ev_join = c->ev_done = nullptr;
+    c->ev_fork = c->ev_join = c->ev_done = c->ev_sizes = nullptr;
     if (c->stats_host) (void)hipHostFree(c->stats_host);
     c->stats_host = nullptr;
 }
@@ -429,7 +430,9 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     c->nseg = int(std::min<int64_t>(64, std::max<int64_t>(1, c->nchunks / 16)));
     c->total = 0;
     c->max_per_tile = 0;
-    if (!cull_reserve_front(c))
+    if (!cull_reserve_front(c) ||
+        (!c->ev_sizes &&
+         hipEventCreateWithFlags(&c->ev_sizes, hipEventDisableTiming) != hipSuccess))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: device workspace allocation failed"));
     hipStream_t s = S(stream);
     c->coef_next = false;
@@ -446,12 +449,24 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (e == hipSuccess)
         e = hipMemcpyAsync(&c->stats_host[2], c->item_off.as<int64_t>() + c->ntiles,
                            sizeof(int64_t), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) e = hipEventRecord(c->ev_sizes, s);
+    // The lists go on at once into the buffers as they are (a rebuild of
+    // similar size needs no more), so the device does not wait for the host
+    // to read the sizes; lists that do not fit are built again below.
+    const int64_t cap_ent =
+        int64_t(std::min(c->cand.cap, c->ent_tile.cap) / sizeof(int32_t));
+    const int64_t cap_items = int64_t(c->item_tile.cap / sizeof(int32_t));
+    if (e == hipSuccess) e = launch_cull_build_lists(c, s, cap_ent, cap_items);
+    if (e == hipSuccess) e = hipEventSynchronize(c->ev_sizes);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (list sizes)"));
     c->total = c->stats_host[0];
     c->max_per_tile = (c->ntiles > 0 && c->k > 0) ? c->stats_host[1] : 0;
     c->nitems = c->stats_host[2];
     c->gitems_cap = c->k + (c->total + kItemTiles - 1) / kItemTiles;
+    const bool fits = c->total <= cap_ent && c->nitems <= cap_items;
+    // before any buffer the lists above write is replaced
+    if (!fits && (e = hipStreamSynchronize(s)) != hipSuccess)
+        return bail(hip_fail(e, "ngd_cull_build (lists)"));
     if (c->total >= (int64_t(1) << 31))
         return bail(fail(NGD_E_NOMEM, "ngd_cull_build: %lld candidates exceed 2^31",
                          (long long)c->total));
@@ -461,8 +476,10 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     ++c->build_seq;
     if (c->coef_next) c->coef_seq = c->build_seq;
     c->transposed = false;
-    e = launch_cull_build_lists(c, s);
-    if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (lists)"));
+    if (!fits) {
+        e = launch_cull_build_lists(c, s, c->total, c->nitems);
+        if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (lists)"));
+    }
     *inout = c;
     return NGD_OK;
 }

@@ -656,6 +656,7 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
                                                         const uint64_t *__restrict__ masks,
                                                         const int32_t *__restrict__ seg_cnt,
                                                         const int64_t *__restrict__ tile_off,
+                                                        int64_t cap,
                                                         int32_t *__restrict__ cand,
                                                         int32_t *__restrict__ ent_tile)
 {
@@ -671,7 +672,9 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
     if (int(threadIdx.x) < kFillTiles) {
         const int64_t t = t0 + threadIdx.x;
         run[threadIdx.x] = t < ntiles ? tile_off[t] + seg_cnt[seg * ntiles + t] : 0;
-        tend[threadIdx.x] = t < ntiles ? tile_off[t + 1] : 0;
+        // no entry at or past `cap` is written (lists longer than the
+        // buffers are built again once the buffers have grown)
+        tend[threadIdx.x] = t < ntiles ? (tile_off[t + 1] < cap ? tile_off[t + 1] : cap) : 0;
     }
     int32_t *st = stage[w];
     for (int64_t cb = c0; cb < c1; cb += kWave) {
@@ -1068,18 +1071,20 @@ hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix, const fl
     }
 }
 
-hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s)
+hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s, int64_t cap_ent,
+                                   int64_t cap_items)
 {
-    if (c->nitems > 0)
+    if (c->ntiles == 0) return hipSuccess;
+    if (cap_items > 0)
         k_item_fill<<<nblk(c->ntiles, kThreads), kThreads, 0, s>>>(
-            c->ntiles, c->item_off.as<int64_t>(), c->nitems, c->item_tile.as<int32_t>());
-    if (c->total == 0 || c->ntiles == 0 || c->k == 0) return hipGetLastError();
+            c->ntiles, c->item_off.as<int64_t>(), cap_items, c->item_tile.as<int32_t>());
+    if (cap_ent == 0 || c->k == 0) return hipGetLastError();
     const int64_t per_seg = (c->nchunks + c->nseg - 1) / c->nseg;
     dim3 sgrid(nblk(c->ntiles, kFillTiles), unsigned(c->nseg));
     k_fill_cand<<<sgrid, kThreads, 0, s>>>(c->ntiles, c->tpad, c->nchunks, per_seg,
                                            c->masks.as<uint64_t>(), c->seg_cnt.as<int32_t>(),
-                                           c->tile_off.as<int64_t>(), c->cand.as<int32_t>(),
-                                           c->ent_tile.as<int32_t>());
+                                           c->tile_off.as<int64_t>(), cap_ent,
+                                           c->cand.as<int32_t>(), c->ent_tile.as<int32_t>());
     return hipGetLastError();
 }
 

@@ -206,6 +206,7 @@ struct ngd_cull {
     // fork; the interval test's join (the Gaussians' limits); the end of the
     // second stream's work (the forward's per-Gaussian data)
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_done = nullptr;
+    hipEvent_t ev_sizes = nullptr;   // the list sizes have reached the host
     // matrix-core forward: quadratic coefficients of the ordered Gaussians
     ngd::DevBuf mrec;          // k x mfma_rec_bytes(n): bf16 hi / lo pairs
     ngd::DevBuf mrow;          // k float: bound factor R'
@@ -246,7 +247,10 @@ hipError_t launch_compose_backward(int n, int64_t kp, int64_t kc, const int32_t 
 
 hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix,
                                    const float *queries, hipStream_t s);
-hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s);
+// The lists of a built front: entries below cap_ent and items below
+// cap_items are written (the buffers' capacities, or the exact sizes).
+hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s, int64_t cap_ent,
+                                   int64_t cap_items);
 // Gaussian -> tile lists of all candidates (g_off, g_tiles); built on
 // demand for ngd_cull_export.
 hipError_t launch_cull_transpose_full(ngd_cull *c, hipStream_t s);

@@ -240,6 +240,30 @@ def test_rebuild_in_place_and_stale_detection(torch_cuda):
     assert normwise(f1, want) <= TOL_FP32
 
 
+def test_rebuild_growing_and_shrinking_lists(torch_cuda):
+    """The list kernels are launched before the host knows the list sizes,
+    into the buffers as they are: a rebuild whose lists outgrow them must
+    build them again after the buffers grow, and one that fits must leave
+    no stale entries.  Each build's lists equal the CPU cull's bit for bit."""
+    from paper_2405_20067_amd import ngd
+    mix, x, proj = case(6, 2000, 9000, seed=12)
+    m = _mixture(torch_cuda, mix)
+    c = ngd.Cull()
+    for qn in (300, 9000, 9000, 2500, 9000):
+        xs = np.ascontiguousarray(x[:qn])
+        xd = dev(xs)
+        c.build(m, xd, proj, _params())
+        got = c.export()
+        want = oracle.cull(mix["mean"], mix["factor"], xs, proj, tau=1e-4, tile=256,
+                           key_proj=16, key_bits=2)
+        assert got["total"] == want["total"], qn
+        for key in ("tile_off", "cand", "g_off", "g_tiles"):
+            np.testing.assert_array_equal(got[key], want[key], err_msg=f"{key} q={qn}")
+        f = host(ngd.eval_mixture(m, c, xd))
+        full = oracle.eval_mixture(mix["mean"], mix["factor"], mix["weight"], mix["colour"], xs)
+        assert normwise(f, full) <= TOL_FP32, qn
+
+
 def test_validate_flags_singular_factor(torch_cuda):
     from paper_2405_20067_amd import ngd
     mix, _, _ = case(4, 50, 10, seed=2)
