@@ -340,7 +340,8 @@ static void cull_release(ngd_cull *c)
                       &c->cand,    &c->g_cnt,    &c->g_off,      &c->g_tiles, &c->scan_tmp,
                       &c->stats,   &c->item_cnt, &c->item_off,   &c->item_tile, &c->fpart,
                       &c->gitem_cnt, &c->gitem_off, &c->gitem_g, &c->gpart,   &c->gflag,
-                      &c->g_ent,   &c->ent_tile, &c->act,
+                      &c->g_ent,   &c->ent_tile, &c->act,       &c->eflag,   &c->eoff,
+                      &c->a_cnt,   &c->a_off,    &c->gbox_u,     &c->gbox,
                       &c->kd_q.node_tab, &c->kd_q.slice_tab, &c->kd_g.node_tab,
                       &c->kd_g.slice_tab, &c->kd_work.idx[0], &c->kd_work.idx[1],
                       &c->kd_work.val[0], &c->kd_work.val[1], &c->kd_work.ext[0],

@@ -264,6 +264,36 @@ def test_rebuild_growing_and_shrinking_lists(torch_cuda):
         assert normwise(f, full) <= TOL_FP32, qn
 
 
+def test_destroy_returns_all_device_memory(torch_cuda):
+    """Every workspace a cull allocates (the front's, the lists', the
+    backward's and the matrix-core forward's) is freed by ngd_cull_destroy:
+    repeated build / evaluate / backward / destroy cycles leave the device's
+    free memory where it was."""
+    from paper_2405_20067_amd import ngd
+    mix, x, proj = case(10, 1 << 15, 1 << 17, seed=33)
+    m = _mixture(torch_cuda, mix)
+    xd = dev(x)
+    g = dev(inputs.gen_grad_out(x.shape[0], seed=4))
+
+    def cycle():
+        c = ngd.Cull().build(m, xd, proj, _params())
+        for prec in (ngd.FP32, ngd.BF16_MFMA):
+            ngd.eval_mixture(m, c, xd, precision=prec)
+            ngd.eval_backward(m, c, xd, g, precision=prec)
+        torch_cuda.cuda.synchronize()
+        assert c.stats()["total"] > 2 * 10 ** 5   # lists of a megabyte and more
+        c.close()
+
+    cycle()   # the first cycle may leave driver-side caches warm
+    torch_cuda.cuda.synchronize()
+    free0 = torch_cuda.cuda.mem_get_info()[0]
+    for _ in range(6):
+        cycle()
+    torch_cuda.cuda.synchronize()
+    free1 = torch_cuda.cuda.mem_get_info()[0]
+    assert free1 >= free0 - (16 << 20), (free0 - free1) / 2 ** 20
+
+
 def test_validate_flags_singular_factor(torch_cuda):
     from paper_2405_20067_amd import ngd
     mix, _, _ = case(4, 50, 10, seed=2)
