@@ -45,11 +45,18 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(int64_t n_max, const i
     const uint32_t mask = uint32_t(bins - 1);
     for (int b = threadIdx.x; b < bins; b += kThreads) cnt[b] = 0;
     __syncthreads();
-    const int64_t base = int64_t(blockIdx.x) * kRadixPerBlock;
-    for (int it = threadIdx.x; it < kRadixPerBlock; it += kThreads) {
-        const int64_t i = base + it;
-        if (i < n) atomicAdd(&cnt[(keys[i] >> shift) & mask], 1);
+    // every key of the thread loaded first, all in flight together
+    constexpr int kPerThread = kRadixPerBlock / kThreads;
+    const int64_t base = int64_t(blockIdx.x) * kRadixPerBlock + threadIdx.x;
+    uint32_t kk[kPerThread];
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+        const int64_t i = base + int64_t(u) * kThreads;
+        kk[u] = i < n ? keys[i] : 0u;
     }
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u)
+        if (base + int64_t(u) * kThreads < n) atomicAdd(&cnt[(kk[u] >> shift) & mask], 1);
     __syncthreads();
     for (int b = threadIdx.x; b < bins; b += kThreads)
         hist[int64_t(b) * nblocks + blockIdx.x] = cnt[b];
@@ -74,9 +81,20 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     }
     __syncthreads();
     const int64_t wstart = int64_t(blockIdx.x) * kRadixPerBlock + int64_t(w) * kRadixPerWave;
+    // the lane's keys and values loaded first, all in flight together; the
+    // ranking rounds below then wait on no memory
+    uint32_t kk[kRadixItems];
+    int32_t vv[kRadixItems];
+#pragma unroll
     for (int it = 0; it < kRadixItems; ++it) {
         const int64_t i = wstart + int64_t(it) * kWave + lane;
-        if (i < n) atomicAdd(&wcnt[w][(keys_in[i] >> shift) & mask], 1);
+        kk[it] = i < n ? keys_in[i] : 0u;
+        vv[it] = i < n ? vals_in[i] : 0;
+    }
+#pragma unroll
+    for (int it = 0; it < kRadixItems; ++it) {
+        const int64_t i = wstart + int64_t(it) * kWave + lane;
+        if (i < n) atomicAdd(&wcnt[w][(kk[it] >> shift) & mask], 1);
     }
     __syncthreads();
     for (int d = threadIdx.x; d < bins; d += kThreads) {
@@ -88,10 +106,11 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
         }
     }
     __syncthreads();
+#pragma unroll
     for (int it = 0; it < kRadixItems; ++it) {
         const int64_t i = wstart + int64_t(it) * kWave + lane;
         const bool valid = i < n;
-        const uint32_t key = valid ? keys_in[i] : 0u;
+        const uint32_t key = kk[it];
         const int d = int((key >> shift) & mask);
         uint64_t match = ballot(valid);
         for (int b = 0; b < width; ++b) {
@@ -104,7 +123,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
             const int64_t dest = int64_t(wbase[w][d]) + rank;
             if (dest < n) {
                 keys_out[dest] = key;
-                vals_out[dest] = vals_in[i];
+                vals_out[dest] = vv[it];
             }
         }
         __builtin_amdgcn_wave_barrier();
