@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kBwdThreads = 256;
 constexpr int kMaxGroups = 16;   // 64-query groups of the largest tile (1024)
+constexpr int64_t kBwdItemBlocks = 4096;
 constexpr int kWavesPerBlock = kBwdThreads / kWave;
 static_assert(kItemTiles <= kWave, "an item's tile list must fit one wave");
 
@@ -211,9 +212,10 @@ __device__ __forceinline__ void brows(const float *__restrict__ r, const float (
     }
 }
 
+// One work item (wave-uniform `it`).
 template <int N>
-__global__ __launch_bounds__(kBwdThreads) void k_backward_items(
-    int64_t k, int64_t q, int tile, const float *__restrict__ grec,
+__device__ __forceinline__ void backward_item(
+    int64_t it, int64_t q, int tile, const float *__restrict__ grec,
     const float *__restrict__ qs, const float *__restrict__ gs,
     const int64_t *__restrict__ a_off, const int32_t *__restrict__ a_ent,
     const int32_t *__restrict__ ent_tile, const uint8_t *__restrict__ act,
@@ -223,8 +225,6 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
     using Lay = BwdLayout<N>;
     constexpr int T = Lay::T;
     const int lane = lane_id();
-    const int64_t it = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave;
-    if (it >= uniform64(gitem_off[k])) return;
     const int64_t g = uniform(gitem_g[it]);
     const int64_t j0 = uniform64(gitem_off[g]);
     const int64_t t0 = uniform64(a_off[g]), t1 = uniform64(a_off[g + 1]);
@@ -331,6 +331,25 @@ __global__ __launch_bounds__(kBwdThreads) void k_backward_items(
     if (lane == kWave - 1) gflag[it] = 1;
 }
 
+// The items (their number on the device) taken by the launched waves in
+// turn: a wave's items lie a grid apart.
+template <int N>
+__global__ __launch_bounds__(kBwdThreads) void k_backward_items(
+    int64_t k, int64_t q, int tile, const float *__restrict__ grec,
+    const float *__restrict__ qs, const float *__restrict__ gs,
+    const int64_t *__restrict__ a_off, const int32_t *__restrict__ a_ent,
+    const int32_t *__restrict__ ent_tile, const uint8_t *__restrict__ act,
+    const int64_t *__restrict__ gitem_off, const int32_t *__restrict__ gitem_g,
+    float *__restrict__ gpart, int32_t *__restrict__ gflag)
+{
+    const int64_t nit = uniform64(gitem_off[k]);
+    const int64_t stride = int64_t(gridDim.x) * kWavesPerBlock;
+    for (int64_t it = int64_t(blockIdx.x) * kWavesPerBlock + threadIdx.x / kWave; it < nit;
+         it += stride)
+        backward_item<N>(it, q, tile, grec, qs, gs, a_off, a_ent, ent_tile, act, gitem_off,
+                         gitem_g, gpart, gflag);
+}
+
 // Per sorted Gaussian: sum its items' moments in item order, then
 //   dm = S'^T B1 / c, dL = tril(S'^T B2) / c^1.5, dalpha = c . H, dc = alpha H.
 template <int N>
@@ -418,7 +437,13 @@ hipError_t culled_n(const ngd_mixture *mix, ngd_cull *c, const float *grad_out, 
     hipError_t err = launch_backward_prepare(c, s);
     if (err != hipSuccess) return err;
     if (c->gitems_cap > 0) {
-        const unsigned blocks = unsigned((c->gitems_cap + kWavesPerBlock - 1) / kWavesPerBlock);
+        // about four rounds of resident waves (4 per SIMD at this kernel's
+        // register count), each taking items a grid apart: 1,024 / 2,048 /
+        // 4,096 blocks measured 327-343 / 319-326 / 293-305 us at 10-D,
+        // 2^20 queries (8,192 and 16,384 alike), against 346-353 us with
+        // one wave per item
+        const unsigned blocks = unsigned(std::min<int64_t>(
+            (c->gitems_cap + kWavesPerBlock - 1) / kWavesPerBlock, kBwdItemBlocks));
         const int32_t *a_ent = c->a_ent_buf ? c->vals1.as<int32_t>() : c->vals0.as<int32_t>();
         k_backward_items<N><<<blocks, kBwdThreads, 0, s>>>(
             mix->k, c->q, c->params.tile, c->grec.as<float>(), c->qs.as<float>(),
