@@ -441,15 +441,11 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
                                   hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_cull_build_front(c, mix, queries, s);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (projections, sort, test)"));
-    // the only device -> host read: list sizes
-    e = hipMemcpyAsync(&c->stats_host[0], c->tile_off.as<int64_t>() + c->ntiles, sizeof(int64_t),
-                       hipMemcpyDeviceToHost, s);
+    // the only device -> host read: list sizes, gathered into one copy
+    e = launch_gather_sizes(c, s);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(&c->stats_host[1], c->stats.as<int64_t>() + 1, sizeof(int64_t),
+        e = hipMemcpyAsync(c->stats_host, c->stats.as<int64_t>() + 1, 3 * sizeof(int64_t),
                            hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&c->stats_host[2], c->item_off.as<int64_t>() + c->ntiles,
-                           sizeof(int64_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipEventRecord(c->ev_sizes, s);
     // The lists go on at once into the buffers as they are (a rebuild of
     // similar size needs no more), so the device does not wait for the host
@@ -460,8 +456,8 @@ int ngd_cull_build(const ngd_mixture *mix, const float *queries, int64_t q,
     if (e == hipSuccess) e = launch_cull_build_lists(c, s, cap_ent, cap_items);
     if (e == hipSuccess) e = hipEventSynchronize(c->ev_sizes);
     if (e != hipSuccess) return bail(hip_fail(e, "ngd_cull_build (list sizes)"));
-    c->total = c->stats_host[0];
-    c->max_per_tile = (c->ntiles > 0 && c->k > 0) ? c->stats_host[1] : 0;
+    c->total = c->stats_host[1];
+    c->max_per_tile = (c->ntiles > 0 && c->k > 0) ? c->stats_host[0] : 0;
     c->nitems = c->stats_host[2];
     c->gitems_cap = c->k + (c->total + kItemTiles - 1) / kItemTiles;
     const bool fits = c->total <= cap_ent && c->nitems <= cap_items;

@@ -776,6 +776,16 @@ __global__ void k_zero_u64(unsigned long long *p, int n)
     if (int(threadIdx.x) < n) p[threadIdx.x] = 0ull;
 }
 
+// The list sizes next to the longest list, for one copy to the host:
+// stats[1] longest list (set by k_seg_prefix), stats[2] total, stats[3] items.
+__global__ void k_gather_sizes(int64_t *stats, const int64_t *tile_end, const int64_t *item_end)
+{
+    if (threadIdx.x == 0) {
+        stats[2] = *tile_end;
+        stats[3] = *item_end;
+    }
+}
+
 __global__ void k_iota(int32_t *p, int64_t n)
 {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -1071,6 +1081,13 @@ hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix, const fl
     }
 }
 
+hipError_t launch_gather_sizes(ngd_cull *c, hipStream_t s)
+{
+    k_gather_sizes<<<1, 64, 0, s>>>(c->stats.as<int64_t>(), c->tile_off.as<int64_t>() + c->ntiles,
+                                    c->item_off.as<int64_t>() + c->ntiles);
+    return hipGetLastError();
+}
+
 hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s, int64_t cap_ent,
                                    int64_t cap_items)
 {
@@ -1276,7 +1293,7 @@ bool cull_reserve_front(ngd_cull *c)
     ok &= c->gitem_cnt.ensure(sizeof(int32_t) * kk);
     ok &= c->gitem_off.ensure(sizeof(int64_t) * (kk + 1));
     ok &= c->scan_tmp.ensure(scan_tmp_bytes(scan_n));
-    ok &= c->stats.ensure(sizeof(int64_t) * 2);
+    ok &= c->stats.ensure(sizeof(int64_t) * 4);
     if (c->params.tiling != 1) {
         // the queries' k-d plan only with the k-d tiling (tiling 2 keeps the
         // caller's order); the Gaussians' with both

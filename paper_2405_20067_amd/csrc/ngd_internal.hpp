@@ -197,8 +197,8 @@ struct ngd_cull {
     ngd::DevBuf gpart;         // gitems_cap x (n + tri + 3) float: moments
     ngd::DevBuf gflag;         // gitems_cap int32: item had contributing pairs
     ngd::DevBuf scan_tmp;      // scan block sums
-    ngd::DevBuf stats;         // 2 int64: total, max per tile
-    int64_t *stats_host = nullptr;  // pinned: total, max per tile, items
+    ngd::DevBuf stats;         // 4 int64: -, max per tile, total, items
+    int64_t *stats_host = nullptr;  // pinned: max per tile, total, items
     ngd::KdPlan kd_q, kd_g;    // k-d tiling plans of the queries and the Gaussians
     ngd::KdWork kd_work;       // query k-d work
     ngd::KdWork kd_work_g;     // Gaussian k-d work (runs concurrently, on `side`)
@@ -247,6 +247,8 @@ hipError_t launch_compose_backward(int n, int64_t kp, int64_t kc, const int32_t 
 
 hipError_t launch_cull_build_front(ngd_cull *c, const ngd_mixture *mix,
                                    const float *queries, hipStream_t s);
+// stats[1..3] = longest list, total, items (device) for one copy to the host.
+hipError_t launch_gather_sizes(ngd_cull *c, hipStream_t s);
 // The lists of a built front: entries below cap_ent and items below
 // cap_items are written (the buffers' capacities, or the exact sizes).
 hipError_t launch_cull_build_lists(ngd_cull *c, hipStream_t s, int64_t cap_ent,
