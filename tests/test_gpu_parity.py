@@ -477,3 +477,33 @@ def test_pairs_at_the_skip_threshold_are_kept(torch_cuda, n):
         err = np.abs(f - want)
         assert np.all(err <= 1e-4 * np.abs(want) + tau * 2.0 ** -20 * colour), (
             prec, float((err / np.maximum(np.abs(want), 1e-300)).max()))
+
+
+@pytest.mark.parametrize("n", list(range(1, 13)))
+def test_every_dimension_forward_and_backward(torch_cuda, n):
+    """Every compiled dimension 1..12: the culled forward of both precisions
+    against the float64 oracle over the same candidate pairs, and the
+    backward against the oracle's gradient over the candidate queries of
+    each Gaussian (small sizes; tiles of 256 with a ragged last tile)."""
+    from paper_2405_20067_amd import ngd
+    k, q = 300, 1500
+    mix, x, proj = case(n, k, q, seed=500 + n)
+    m = _mixture(torch_cuda, mix)
+    xd = dev(x)
+    c = ngd.Cull().build(m, xd, proj, _params())
+    exp = c.export()
+    qoff, gidx = per_query_csr(exp, q, 256)
+    want = oracle.eval_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x,
+                             qoff, gidx)
+    g = inputs.gen_grad_out(q, seed=6)
+    sel, goff, gq = per_gaussian_csr(exp, q, 256)
+    part = oracle.grad_lists(mix["mean"], mix["factor"], mix["weight"], mix["colour"], x, g,
+                             sel, goff, gq)
+    for prec in (ngd.FP32, ngd.BF16_MFMA):
+        f = host(ngd.eval_mixture(m, c, xd, precision=prec))
+        assert normwise(f, want) <= TOL_FP32, (n, prec)
+        got = [host(t) for t in ngd.eval_backward(m, c, xd, dev(g), precision=prec)]
+        for name, a, b in zip(("mean", "factor", "weight", "colour"), got, part):
+            want_g = np.zeros_like(a, dtype=np.float64)
+            want_g[sel] = b
+            assert normwise(a, want_g) <= TOL_FP32, (n, prec, name)
