@@ -43,6 +43,12 @@ __global__ __launch_bounds__(kThreads) void k_radix_count(int64_t n_max, const i
     const int64_t n = count_of(n_max, n_dev);
     const int bins = 1 << width;
     const uint32_t mask = uint32_t(bins - 1);
+    if (int64_t(blockIdx.x) * kRadixPerBlock >= n) {
+        // past the device count: zero columns only
+        for (int b = threadIdx.x; b < bins; b += kThreads)
+            hist[int64_t(b) * nblocks + blockIdx.x] = 0;
+        return;
+    }
     for (int b = threadIdx.x; b < bins; b += kThreads) cnt[b] = 0;
     __syncthreads();
     // every key of the thread loaded first, all in flight together
@@ -72,6 +78,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(
     __shared__ int wcnt[W][kRadixMaxBins];
     __shared__ int wbase[W][kRadixMaxBins];
     const int64_t n = count_of(n_max, n_dev);
+    // a block past the device count has no keys to move (its histogram
+    // columns are zero): nothing to do
+    if (int64_t(blockIdx.x) * kRadixPerBlock >= n) return;
     const int w = threadIdx.x / kWave, lane = lane_id();
     const int bins = 1 << width;
     const uint32_t mask = uint32_t(bins - 1);
