@@ -669,13 +669,23 @@ __global__ __launch_bounds__(kThreads) void k_fill_cand(int64_t ntiles, int64_t 
     const int64_t c0 = seg * per_seg;
     const int64_t c1 = (c0 + per_seg < nchunks) ? c0 + per_seg : nchunks;
     const int w = int(threadIdx.x) / kWave, lane = lane_id();
+    int has = 0;   // this segment has candidates in this thread's tile
     if (int(threadIdx.x) < kFillTiles) {
         const int64_t t = t0 + threadIdx.x;
+        if (t < ntiles) {
+            // the segments' exclusive offsets within the tile's list
+            const int64_t b = seg_cnt[seg * ntiles + t];
+            const int64_t e = seg + 1 < int64_t(gridDim.y) ? seg_cnt[(seg + 1) * ntiles + t]
+                                                           : tile_off[t + 1] - tile_off[t];
+            has = e > b;
+        }
         run[threadIdx.x] = t < ntiles ? tile_off[t] + seg_cnt[seg * ntiles + t] : 0;
         // no entry at or past `cap` is written (lists longer than the
         // buffers are built again once the buffers have grown)
         tend[threadIdx.x] = t < ntiles ? (tile_off[t + 1] < cap ? tile_off[t + 1] : cap) : 0;
     }
+    // a (tiles, segment) block without candidates reads none of its masks
+    if (!__syncthreads_or(has)) return;
     int32_t *st = stage[w];
     for (int64_t cb = c0; cb < c1; cb += kWave) {
         __syncthreads();   // run[] set; the previous round's readers done
