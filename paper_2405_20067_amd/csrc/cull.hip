@@ -1149,28 +1149,52 @@ namespace {
 // Entries with at least one kept query group, compacted in entry order and
 // then stably sorted by Gaussian: each Gaussian's kept entries in ascending
 // tile order, without transposing the (much longer) full candidate lists.
-__global__ __launch_bounds__(kThreads) void k_eflag(int64_t total, int groups,
-                                                    const uint8_t *__restrict__ act,
-                                                    int32_t *__restrict__ eflag)
+// Whether any 64-query group kept entry e (the flags of its groups, read
+// together).
+__device__ __forceinline__ bool entry_kept(const uint8_t *__restrict__ act, int64_t e, int groups)
 {
-    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (e >= total) return;
+    const uint8_t *a = act + e * groups;
+    if (groups == 4) return *reinterpret_cast<const uint32_t *>(a) != 0u;   // aligned
     int any = 0;
-    for (int g = 0; g < groups; ++g) any |= act[e * groups + g];
-    eflag[e] = any ? 1 : 0;
+#pragma unroll
+    for (int g = 0; g < 16; ++g)   // groups <= 16 (tiles of at most 1024 queries)
+        if (g < groups) any |= a[g];
+    return any != 0;
 }
 
-__global__ __launch_bounds__(kThreads) void k_ecompact(int64_t total,
-                                                       const int32_t *__restrict__ eflag,
-                                                       const int64_t *__restrict__ eoff,
+// Kept entries per block of kThreads entries.
+__global__ __launch_bounds__(kThreads) void k_eflag(int64_t total, int groups,
+                                                    const uint8_t *__restrict__ act,
+                                                    int32_t *__restrict__ bcnt)
+{
+    const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
+    const bool kept = e < total && entry_kept(act, e, groups);
+    const int n = __syncthreads_count(kept);
+    if (threadIdx.x == 0) bcnt[blockIdx.x] = n;
+}
+
+// The kept entries in entry order: block offset (the scan of the block
+// counts) plus the rank within the block; keys = sorted Gaussian, values =
+// entry, and each Gaussian's count.
+__global__ __launch_bounds__(kThreads) void k_ecompact(int64_t total, int groups,
+                                                       const uint8_t *__restrict__ act,
+                                                       const int64_t *__restrict__ boff,
                                                        const int32_t *__restrict__ cand,
                                                        uint32_t *__restrict__ keys,
                                                        int32_t *__restrict__ vals,
                                                        int32_t *__restrict__ a_cnt)
 {
+    __shared__ int wcnt[kThreads / kWave];
     const int64_t e = int64_t(blockIdx.x) * kThreads + threadIdx.x;
-    if (e >= total || !eflag[e]) return;
-    const int64_t o = eoff[e];
+    const bool kept = e < total && entry_kept(act, e, groups);
+    const uint64_t b = ballot(kept);
+    const int w = int(threadIdx.x) / kWave;
+    if (lane_id() == 0) wcnt[w] = __popcll(b);
+    __syncthreads();
+    if (!kept) return;
+    int before = __popcll(b & lanemask_lt());
+    for (int i = 0; i < w; ++i) before += wcnt[i];
+    const int64_t o = boff[blockIdx.x] + before;
     const int32_t g = cand[e];
     keys[o] = uint32_t(g);
     vals[o] = int32_t(e);
@@ -1187,20 +1211,23 @@ hipError_t launch_backward_prepare(ngd_cull *c, hipStream_t s)
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (total > 0) {
-        k_eflag<<<nblk(total, kThreads), kThreads, 0, s>>>(total, groups, c->act.as<uint8_t>(),
-                                                           c->eflag.as<int32_t>());
-        e = scan_counts(c->eflag, c->eoff, total, c->scan_tmp, s);
+        // kept entries counted per block of kThreads entries, the block
+        // counts scanned (eflag and eoff hold the counts and the offsets),
+        // then each kept entry placed at its block's offset plus its rank
+        const int64_t nb = (total + kThreads - 1) / kThreads;
+        k_eflag<<<unsigned(nb), kThreads, 0, s>>>(total, groups, c->act.as<uint8_t>(),
+                                                  c->eflag.as<int32_t>());
+        e = scan_counts(c->eflag, c->eoff, nb, c->scan_tmp, s);
         if (e != hipSuccess) return e;
-        k_ecompact<<<nblk(total, kThreads), kThreads, 0, s>>>(
-            total, c->eflag.as<int32_t>(), c->eoff.as<int64_t>(), c->cand.as<int32_t>(),
+        k_ecompact<<<unsigned(nb), kThreads, 0, s>>>(
+            total, groups, c->act.as<uint8_t>(), c->eoff.as<int64_t>(), c->cand.as<int32_t>(),
             c->keys0.as<uint32_t>(), c->vals0.as<int32_t>(), c->a_cnt.as<int32_t>());
         int nbits = 0;
         while ((int64_t(1) << nbits) < k) ++nbits;
         int which = 0;
-        // the kept-entry count stays on the device: eoff[total]
-        e = radix_sort(total, c->eoff.as<int64_t>() + total, nbits, c->keys0, c->keys1, c->vals0, c->vals1, c->radix_hist,
-                       c->radix_off, c->scan_tmp, s,
-                       &which);
+        // the kept-entry count stays on the device: eoff[nb]
+        e = radix_sort(total, c->eoff.as<int64_t>() + nb, nbits, c->keys0, c->keys1, c->vals0,
+                       c->vals1, c->radix_hist, c->radix_off, c->scan_tmp, s, &which);
         if (e != hipSuccess) return e;
         c->a_ent_buf = which;
     } else {
@@ -1231,8 +1258,10 @@ bool cull_reserve_lists(ngd_cull *c)
     ok &= c->g_ent.ensure(sizeof(int32_t) * tot);
     ok &= c->g_tiles.ensure(sizeof(int32_t) * tot);
     ok &= c->act.ensure(size_t(tot) * size_t(groups));
-    ok &= c->eflag.ensure(sizeof(int32_t) * tot);
-    ok &= c->eoff.ensure(sizeof(int64_t) * (tot + 1));
+    // the backward's per-block kept counts and their offsets
+    const int64_t nbe = (tot + kThreads - 1) / kThreads;
+    ok &= c->eflag.ensure(sizeof(int32_t) * nbe);
+    ok &= c->eoff.ensure(sizeof(int64_t) * (nbe + 1));
     ok &= c->a_cnt.ensure(sizeof(int32_t) * kk);
     ok &= c->a_off.ensure(sizeof(int64_t) * (kk + 1));
     ok &= c->keys0.ensure(sizeof(uint32_t) * tot);

@@ -182,8 +182,8 @@ struct ngd_cull {
     mutable int64_t act_version = -1;  // mixture version the flags belong to
     bool transposed = false;   // g_off / g_tiles hold the full transposed lists
     // backward: the entries with a kept group, grouped by Gaussian
-    ngd::DevBuf eflag;         // total int32: entry has a kept group
-    ngd::DevBuf eoff;          // total + 1 int64
+    ngd::DevBuf eflag;         // ceil(total / 256) int32: kept entries per block
+    ngd::DevBuf eoff;          // ceil(total / 256) + 1 int64: their offsets
     ngd::DevBuf a_cnt;         // k int32
     ngd::DevBuf a_off;         // k + 1 int64
     int a_ent_buf = 0;         // which sort buffer (vals0 / vals1) holds them
