@@ -43,8 +43,28 @@ constexpr int kThreads = 256;
 // coordinates.  sr^2 is the forward's skip threshold in units of M, widened
 // by (1 + 2^-8)^2 for the rounding of its float32 distances.  V_ii =
 // |row i of L|^2 and [m - r, m + r] are formed in float64 and the box is
-// rounded outwards; box holds lo_0..lo_{n-1}, hi_0..hi_{n-1} per Gaussian
-// (stride BS floats), in the caller's order (gathered with the records).
+// rounded outwards to float16 (a looser box is still a certificate, and
+// half the bytes of float32 for the forward's per-pair reads); box holds
+// lo_0..lo_{n-1}, hi_0..hi_{n-1} per Gaussian as float16 bits, padded to
+// BSH halves (a multiple of 16 bytes), in the caller's order (gathered with
+// the records).
+// float16 bits of the largest float16 <= v (DOWN) or smallest >= v (up).
+// The nearest float16 of float(v) is one of the two float16 values around v
+// (rounding is monotone and float16 values are floats), so one step of the
+// bit pattern towards the right side suffices; overflow goes to +-inf.
+template <bool DOWN> __device__ __forceinline__ uint16_t half_outward(double v)
+{
+    const _Float16 h = _Float16(float(v));
+    uint16_t u = __builtin_bit_cast(uint16_t, h);
+    const double hv = double(float(h));
+    if (DOWN ? hv > v : hv < v) {
+        if ((u & 0x7fffu) == 0) u = DOWN ? 0x8001u : 0x0001u;   // +-0: smallest subnormal
+        else if ((u & 0x8000u) != 0) u = DOWN ? u + 1 : u - 1;  // negative: magnitude
+        else u = DOWN ? u - 1 : u + 1;                          // positive: magnitude
+    }
+    return u;
+}
+
 template <int N>
 __global__ __launch_bounds__(kThreads) void k_gauss_proj(int64_t k, int P,
                                                          const float *__restrict__ rec, int R,
@@ -55,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void k_gauss_proj(int64_t k, int P,
                                                          float *__restrict__ box)
 {
     constexpr int T = N * (N + 1) / 2;
-    constexpr int BS = (2 * N + 3) / 4 * 4;
+    constexpr int BSH = (2 * N + 7) / 8 * 8;
     const int64_t i = int64_t(blockIdx.x) * kThreads + threadIdx.x;
     if (i >= k) return;
     float m[N];
@@ -64,26 +84,25 @@ __global__ __launch_bounds__(kThreads) void k_gauss_proj(int64_t k, int P,
     for (int a = 0; a < N; ++a) m[a] = rec[i * R + a];
 #pragma unroll
     for (int e = 0; e < T; ++e) L[e] = lfac[i * T + e];
-    float bx[BS];
+    uint16_t bx[BSH];
 #pragma unroll
     for (int a = 0; a < N; ++a) {
         double v = 0.0;
 #pragma unroll
         for (int b = 0; b <= a; ++b) v = fma(L[a * (a + 1) / 2 + b], L[a * (a + 1) / 2 + b], v);
         const double r = sr * sqrt(v);
-        const double lo = double(m[a]) - r, hi = double(m[a]) + r;
-        float flo = float(lo), fhi = float(hi);
-        if (double(flo) > lo) flo = nextafterf(flo, -INFINITY);
-        if (double(fhi) < hi) fhi = nextafterf(fhi, INFINITY);
-        bx[a] = flo;
-        bx[N + a] = fhi;
+        bx[a] = half_outward<true>(double(m[a]) - r);
+        bx[N + a] = half_outward<false>(double(m[a]) + r);
     }
 #pragma unroll
-    for (int e = 2 * N; e < BS; ++e) bx[e] = 0.0f;
-    float4 *bo = reinterpret_cast<float4 *>(box + i * BS);
+    for (int e = 2 * N; e < BSH; ++e) bx[e] = 0;
+    uint4 *bo = reinterpret_cast<uint4 *>(box) + i * (BSH / 8);
 #pragma unroll
-    for (int e = 0; e < BS / 4; ++e)
-        bo[e] = make_float4(bx[4 * e], bx[4 * e + 1], bx[4 * e + 2], bx[4 * e + 3]);
+    for (int e = 0; e < BSH / 8; ++e) {
+        const uint16_t *h = bx + 8 * e;
+        bo[e] = make_uint4(h[0] | uint32_t(h[1]) << 16, h[2] | uint32_t(h[3]) << 16,
+                           h[4] | uint32_t(h[5]) << 16, h[6] | uint32_t(h[7]) << 16);
+    }
     for (int j = 0; j < P; ++j) {
         const float *r = proj + j * N;
         float acc = 0.0f;
@@ -378,7 +397,7 @@ __global__ __launch_bounds__(1024) void k_tile_bounds(int64_t q, int tile, int P
 }
 
 // Records and forward boxes of the Gaussians in their tile order: a block
-// moves 64 records of R floats and 64 boxes of B floats as float4s,
+// moves 64 records of R floats and 64 boxes of B 4-byte words as float4s,
 // consecutive threads on consecutive float4s.
 __global__ __launch_bounds__(kThreads) void k_rec_gather(int64_t k, int R, int B,
                                                          const int32_t *__restrict__ gperm,

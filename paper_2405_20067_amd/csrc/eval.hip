@@ -21,8 +21,8 @@
 // times alpha |c|.  The same test is applied once more before the exp.
 //
 // Ahead of those checks each wave tests its 64 queries' bounding box against
-// a per-Gaussian box built with the cull (lane = candidate, one vector load
-// of 2n floats each): a Gaussian whose box misses the queries' box in some
+// a per-Gaussian box built with the cull (lane = candidate, 2n float16
+// bounds rounded outwards, in 16-byte loads): a Gaussian whose box misses the queries' box in some
 // coordinate has every distance above the skip threshold (the marginal over
 // that coordinate alone bounds it), so it is dropped before its record is
 // read, and only the survivors go through the staged evaluation.
@@ -169,10 +169,18 @@ __global__ __launch_bounds__(kEvalThreads) void k_eval_items(
         const int vidx = (lane < n) ? cand[ch + lane] : 0;
         bool near = false;
         if (lane < n) {
-            const float *b = gbox + int64_t(vidx) * ((2 * N + 3) / 4 * 4);
+            constexpr int BW = (2 * N + 7) / 8;   // 16-byte words of 8 float16
+            const uint4 *b = reinterpret_cast<const uint4 *>(gbox) + int64_t(vidx) * BW;
+            uint32_t hw[4 * BW];
+#pragma unroll
+            for (int w = 0; w < BW; ++w) {
+                const uint4 v = b[w];
+                hw[4 * w] = v.x, hw[4 * w + 1] = v.y, hw[4 * w + 2] = v.z, hw[4 * w + 3] = v.w;
+            }
             float bl[2 * N];
 #pragma unroll
-            for (int e = 0; e < 2 * N; ++e) bl[e] = b[e];
+            for (int e = 0; e < 2 * N; ++e)
+                bl[e] = float(__builtin_bit_cast(_Float16, uint16_t(hw[e / 2] >> (16 * (e & 1)))));
             bool apart = false;
 #pragma unroll
             for (int a = 0; a < N; ++a) apart |= (qlo[a] > bl[N + a]) | (qhi[a] < bl[a]);

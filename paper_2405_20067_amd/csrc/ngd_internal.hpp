@@ -33,8 +33,9 @@ inline int tri(int n) { return n * (n + 1) / 2; }
 // floats: m (n) | S' = sqrt(kHalfLog2e) L^-1 packed lower by rows (tri) |
 // alpha*c (3) | alpha (1) | c (3) | padding to a multiple of 4.
 inline int rec_stride(int n) { return (n + tri(n) + 7 + 3) / 4 * 4; }
-// floats per Gaussian of the forward's box (n lows, n highs, padding)
-inline int box_stride(int n) { return (2 * n + 3) / 4 * 4; }
+// 4-byte words per Gaussian of the forward's box: n lows, then n highs, as
+// float16, padded to a multiple of 16 bytes
+inline int box_stride(int n) { return (2 * n + 7) / 8 * 4; }
 
 // Device allocation through the configurable allocator; reports the
 // matching release function (NULL: hipFree) and its context.
@@ -165,7 +166,7 @@ struct ngd_cull {
     ngd::DevBuf grec;          // k x rec_stride float, sorted Gaussians
     ngd::DevBuf g_mr_s;             // n_proj x k float, sorted Gaussians
     ngd::DevBuf g_ub, g_lb;         // n_proj x k float, sorted: the interval test's limits
-    ngd::DevBuf gbox_u, gbox;       // k x box_stride(n) float, caller's order and
+    ngd::DevBuf gbox_u, gbox;       // k x box_stride(n) words, caller's order and
                                     // sorted: per coordinate, the range outside which
                                     // the forward keeps no query
     ngd::DevBuf masks;         // nchunks x tpad uint64
